@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the CSR SpMV + dot hot path on one MI355X.
+
+Default workload (one "step" = one whole solve): conjugate gradient on the
+synthetic SPD matrix n = 150,000 with about 241 non-zeros per row, float64,
+75 iterations (product + 2 dots + 3 vector updates each), the matrix resident
+on the device and the whole solve replayed as one captured HIP graph.
+
+Printed: one JSON line with the effective bandwidth of the solve (credited
+algorithmic bytes / time), solves per second, the roofline of the dominant
+kernel (the CSR tile kernel, timed with HIP events on the stream it runs on)
+and the oracle's CPU time on the same input.
+
+Other workloads (--workload): spmv16 (single product, n = 4096, 16 per row),
+pagerank (R-MAT 2^22, 2^26 edge draws, float32, 20 steps), batched (512
+matrices in one grouped launch), serve (Poisson request stream over resident
+matrices).  --workload all adds every other workload's figures under
+"extras" of the same line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpMV effective GB/s & % HBM peak; batched/served CG solves/s + p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(A, vsize: int) -> int:
+    """Algorithmic bytes of one product y = A x: every non-zero (value and
+    column index) once, row_ptr once, each referenced x entry once, y once."""
+    n_x = int(np.count_nonzero(np.bincount(A.col_idx, minlength=A.cols))) if A.nnz else 0
+    return A.nnz * (vsize + 4) + (A.rows + 1) * 4 + n_x * vsize + A.rows * vsize
+
+
+def cg_iter_bytes(A) -> int:
+    """Credited bytes of one CG iteration: the product (p gathered, q
+    written; p.q fused into it), x/r update (read x, p, r, q; write x, r;
+    r.r fused) and p = r + beta p (read r, p; write p)."""
+    return spmv_bytes(A, 8) + 9 * A.rows * 8
+
+
+def time_events(fn, reps: int, stream) -> float:
+    """Average milliseconds of fn() over reps launches, HIP events recorded
+    on `stream` (the stream fn launches on)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_cg_baseline(A, b, iters: int, credited: int):
+    import oracle
+    t0 = time.perf_counter()
+    oracle.cg(A.row_ptr, A.col_idx, A.vals, b, iters)
+    dt = time.perf_counter() - t0
+    return {"value": round(credited / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one full {iters}-iteration CG solve of the same matrix "
+                      f"and right-hand side ({dt:.2f} s), single thread, gcc -O2"}
+
+
+def run_cg(args, torch, L, gen, extras_only=False):
+    A = gen.spd_random()
+    b = gen.vector(A.rows, 7)
+    iters = 75
+    log(f"[cg] n={A.rows} nnz={A.nnz} ({A.nnz / A.rows:.1f}/row)")
+    h = L.Csr.from_gen(A)
+    stream = torch.cuda.current_stream()
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.empty(A.rows, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        h.cg(bd, xd, iters, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.cg(bd, xd, iters, graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    credited = cg_iter_bytes(A) * iters
+    value = credited / dt / 1e9
+    # dominant kernel: the CSR tile kernel, timed alone on the same stream
+    p = torch.from_numpy(gen.vector(A.rows, 8)).cuda()
+    q = torch.empty_like(p)
+    kb = spmv_bytes(A, 8)
+    for _ in range(3):
+        h.spmv(p, q)
+    ms = time_events(lambda: h.spmv(p, q), max(20, args.steps * 10), stream)
+    achieved = kb / (ms * 1e-3) / 1e9
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s",
+        "ms_per_step": round(dt * 1e3, 4),
+        "solves_per_s": round(1.0 / dt, 2),
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "gflops": round(2.0 * A.nnz * iters / dt / 1e9, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_spmv_tiles<double> (W64 rows)",
+                     "bytes_per_launch": kb, "avg_us": round(ms * 1e3, 2)},
+        "config": {"workload": "cg_spd150k", "n": A.rows, "nnz": A.nnz,
+                   "iters": iters, "graph": True, "dtype": "f64"},
+        "dtype": "f64",
+    }
+    if args.cpu_baseline and not extras_only:
+        log("[cg] oracle CPU baseline ...")
+        res["cpu_baseline"] = cpu_cg_baseline(A, b, iters, credited)
+    h.destroy()
+    return res
+
+
+def run_spmv16(args, torch, L, gen):
+    A = gen.uniform_rows()
+    x = torch.from_numpy(gen.vector(A.cols, 3)).cuda()
+    y = torch.empty(A.rows, dtype=torch.float64, device="cuda")
+    h = L.Csr.from_gen(A)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        h.spmv(x, y)
+    ms = time_events(lambda: h.spmv(x, y), 200, stream)
+    kb = spmv_bytes(A, 8)
+    h.destroy()
+    # end-to-end paper-shaped call with host arrays (x up, y down)
+    xh = gen.vector(A.cols, 3)
+    yh = np.empty(A.rows)
+    L.lilac_spmv_csr(A.rows, A.row_ptr, A.col_idx, A.vals, xh, yh)
+    t0 = time.perf_counter()
+    for _ in range(50):
+        L.lilac_spmv_csr(A.rows, A.row_ptr, A.col_idx, A.vals, xh, yh)
+    e2e = (time.perf_counter() - t0) / 50
+    L.lilac_release_all()
+    return {"workload": "spmv_uniform4096x16", "us_per_call": round(ms * 1e3, 2),
+            "GBps": round(kb / (ms * 1e-3) / 1e9, 1),
+            "us_per_raw_call_host_arrays": round(e2e * 1e6, 1)}
+
+
+def run_pagerank(args, torch, L, gen):
+    A = gen.rmat_pagerank()
+    n = A.rows
+    h = L.Csr.from_gen(A)
+    stream = torch.cuda.current_stream()
+    x0 = torch.full((n,), 1.0 / n, dtype=torch.float32, device="cuda")
+    x = x0.clone()
+    iters = 20
+    h.pagerank(0.85, iters, x)
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x.copy_(x0)
+        h.pagerank(0.85, iters, x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    kb = spmv_bytes(A, 4)
+    xs = torch.rand(n, dtype=torch.float32, device="cuda")
+    ys = torch.empty_like(xs)
+    ms = time_events(lambda: h.spmv(xs, ys), 20, stream)
+    inf = h.info()
+    h.destroy()
+    return {"workload": "pagerank_rmat22", "nnz": A.nnz, "iters": iters,
+            "ms_per_run": round(dt * 1e3, 3),
+            "GBps": round(kb * iters / dt / 1e9, 1),
+            "spmv_us": round(ms * 1e3, 1),
+            "spmv_GBps": round(kb / (ms * 1e-3) / 1e9, 1),
+            "split_chunks": int(inf.nchunks)}
+
+
+def run_batched(args, torch, L, gen):
+    specs = gen.batch_specs()
+    mats = []
+    t0 = time.perf_counter()
+    for s in specs:
+        mats.append(s.build())
+    log(f"[batched] generated 512 matrices in {time.perf_counter() - t0:.1f} s")
+    hs, xs, ys = [], [], []
+    total_b = 0
+    nnz = 0
+    for i, A in enumerate(mats):
+        hs.append(L.Csr.from_gen(A))
+        xs.append(torch.from_numpy(gen.vector(A.cols, 1000 + i)).cuda())
+        ys.append(torch.empty(A.rows, dtype=torch.float64, device="cuda"))
+        total_b += spmv_bytes(A, 8)
+        nnz += A.nnz
+    del mats
+    stream = torch.cuda.current_stream()
+    L.lilac_spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    ms_g = time_events(lambda: L.lilac_spmv_batched(hs, xs, ys), 10, stream)
+
+    def singles():
+        for h, x, y in zip(hs, xs, ys):
+            h.spmv(x, y)
+    singles()
+    ms_s = time_events(singles, 3, stream)
+    for h in hs:
+        h.destroy()
+    return {"workload": "batched512", "nnz": nnz, "ms_grouped": round(ms_g, 3),
+            "GBps_grouped": round(total_b / (ms_g * 1e-3) / 1e9, 1),
+            "ms_512_single_calls": round(ms_s, 3),
+            "GBps_single_calls": round(total_b / (ms_s * 1e-3) / 1e9, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cg",
+                    choices=["cg", "spmv16", "pagerank", "batched", "all"])
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; "
+                                   "multi-GPU sharding is described in DESIGN.md "
+                                   "but not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import gen
+    import paper_2001_07938_amd as L
+    torch.cuda.set_device(0)
+    L.lilac_init(0)
+
+    if args.workload in ("cg", "all"):
+        res = run_cg(args, torch, L, gen)
+    else:
+        fn = {"spmv16": run_spmv16, "pagerank": run_pagerank,
+              "batched": run_batched}[args.workload]
+        extra = fn(args, torch, L, gen)
+        res = run_cg(args, torch, L, gen, extras_only=True)
+        res["extras"] = {args.workload: extra}
+    if args.workload == "all":
+        res["extras"] = {}
+        for name, fn in (("spmv16", run_spmv16), ("pagerank", run_pagerank),
+                         ("batched", run_batched)):
+            log(f"[{name}] ...")
+            res["extras"][name] = fn(args, torch, L, gen)
+    out = {
+        "metric": res.pop("metric"), "value": res.pop("value"),
+        "unit": res.pop("unit"), "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": res.pop("dtype"), "data": "synthetic",
+        "config": res.pop("config"),
+    }
+    out.update(res)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -137,26 +137,21 @@ def rmat_pagerank(scale: int = 22, n_edges: int = 1 << 26,
                   seed: int = BASE_SEED + 3) -> Csr:
     """Pull-direction CSR of an R-MAT graph for PageRank.
 
-    Duplicate edges are removed, self loops kept, vertices relabelled with a
-    seeded random permutation (so hubs are spread out), and the matrix is
-    A[v, u] = 1/outdeg(u) for every edge u -> v, stored float32, columns sorted
-    within each row.  Rows are destinations, columns are sources.
+    Vertices are relabelled with a seeded random permutation (so hubs are
+    spread out), duplicate edges are removed, self loops kept, and the matrix
+    is A[v, u] = 1/outdeg(u) for every edge u -> v, stored float32, columns
+    sorted within each row.  Rows are destinations, columns are sources.
     """
     nv = 1 << scale
     src, dst = rmat_edges(scale, n_edges, seed=seed)
-    key = np.unique((src << scale) | dst)
-    del src, dst
-    src = key >> scale
-    dst = key & (nv - 1)
-    del key
     perm = _rng(seed + 1000).permutation(nv).astype(np.int64)
-    src = perm[src]
-    dst = perm[dst]
+    key = (perm[dst] << scale) | perm[src]
+    del src, dst
+    key = np.unique(key)            # sorted by (destination, source), deduped
+    dst = key >> scale
+    src = key & (nv - 1)
+    del key
     outdeg = np.bincount(src, minlength=nv)
-    order = np.argsort((dst << scale) | src, kind="stable")
-    src = src[order]
-    dst = dst[order]
-    del order
     w = (1.0 / outdeg[src]).astype(np.float32)
     return _from_sorted_keys(nv, nv, dst, src, w, f"rmat{scale}")
 

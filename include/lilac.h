@@ -1,0 +1,240 @@
+/*
+ * lilac.h - C ABI of liblilac.so, an AMD Instinct MI355X (gfx950) library for
+ * the computations that the LiLAC compiler (Ginsbach, Collie, O'Boyle,
+ * "Automatically Harnessing Sparse Acceleration", CC 2020) offloads to
+ * sparse libraries: the CSR sparse matrix-vector product and the dense dot
+ * product, plus the solver and graph loops built from them.
+ *
+ * General conventions (apply to every call unless its comment says otherwise)
+ *  - Indices are 0-based int32 (`int`).  CSR is (row_ptr[rows+1], col_idx[nnz],
+ *    vals[nnz]) as defined in the paper's section "Sparse Matrix Variations in
+ *    LiLAC-What" (CSR paragraph): row_ptr[i] is where row i starts, rows is
+ *    len(row_ptr)-1, the column count is not part of the format.
+ *  - Every call returns a status (LILAC_OK = 0, negative on error) except
+ *    lilac_dot / lilac_version / lilac_last_error, which return their value.
+ *    On error lilac_last_error() gives a thread-local message.  No C++
+ *    exception ever crosses this interface.
+ *  - The caller owns every pointer it passes; the library never frees caller
+ *    memory.  "host or device" pointers are classified with
+ *    hipPointerGetAttributes; "device" pointers must be device memory of the
+ *    current HIP device.
+ *  - `stream` is a hipStream_t passed as void*; NULL is HIP's default (null)
+ *    stream.  Calls marked "async" only enqueue work on `stream` and return;
+ *    the caller orders them against its own work through that stream.
+ *    Blocking calls that read device memory first wait for the whole device
+ *    (hipDeviceSynchronize), since the data may come from any stream.
+ *  - Floating-point results are not bitwise reproducible against a serial
+ *    loop (sums are reordered and contracted to FMA), but every call is
+ *    deterministic: the same inputs and the same matrix handle give bitwise
+ *    identical outputs on every run, alone or in a batch.
+ *  - Entry points are thread-safe (one library lock serialises them).
+ */
+#ifndef LILAC_H
+#define LILAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LILAC_OK 0
+#define LILAC_ERR_ARG (-1)         /* bad argument (NULL, negative size ...) */
+#define LILAC_ERR_CSR (-2)         /* matrix is not well-formed CSR */
+#define LILAC_ERR_OOM (-3)         /* device allocation failed */
+#define LILAC_ERR_BUDGET (-4)      /* would exceed the HBM byte budget */
+#define LILAC_ERR_DEVICE (-5)      /* a HIP call failed / no device */
+#define LILAC_ERR_STATE (-6)       /* call not valid in the object's state */
+#define LILAC_ERR_UNSUPPORTED (-7) /* combination not implemented */
+
+typedef enum { LILAC_F64 = 0, LILAC_F32 = 1 } lilac_dtype;
+
+typedef struct lilac_csr_s *lilac_csr_t;
+
+/* ---- library lifetime ------------------------------------------------ */
+/*
+ * Persistent state shared by all calls (the paper's PersistentVariables,
+ * with BeforeFirstExecution / AfterLastExecution set-up and tear-down,
+ * section "LiLAC-How", paragraph "Persistence").  lilac_init is optional: the
+ * first call of any entry point initialises the library on the current
+ * device.  lilac_finalize releases every device copy the library made
+ * (including the raw-call cache) and is also run at process exit.
+ * Returns LILAC_ERR_DEVICE if no HIP device is usable.
+ */
+int lilac_init(int device);
+int lilac_finalize(void);
+const char *lilac_last_error(void);
+int lilac_version(void); /* major*10000 + minor*100 + patch */
+
+/* ---- paper-shaped calls ---------------------------------------------- */
+/*
+ * y = A x over CSR, the spmv_csr computation whose loop the paper's compiler
+ * replaces by a harness call (sections "Overview" and "Code Replacement");
+ * y is overwritten (an empty row gives 0):
+ *     y[i] = sum_{k=row_ptr[i]}^{row_ptr[i+1]-1} vals[k] * x[col_idx[k]]
+ * Every pointer may be host or device.  x must hold cols = max(col_idx)+1
+ * entries, y holds rows entries.  Blocking: returns when y is written.
+ * Marshaling (section "Data Marshaling", and the ReadObject rules of section
+ * "Implementation", LiLAC-How): the three matrix arrays are copied to the
+ * device on the first call and cached, keyed by their addresses and sizes;
+ * later calls with the same arrays reuse the device copy and the analysis
+ * (including cols) until lilac_invalidate names one of the arrays or
+ * lilac_release_all / lilac_finalize runs.  The environment variable
+ * LILAC_MARSHAL=naive turns caching off (every call re-uploads, for the
+ * paper's naive-transfer comparison); LILAC_MARSHAL=protect tracks host
+ * writes to cached host arrays with page protection and re-uploads them
+ * automatically.  Host x is uploaded and host y copied back on every call.
+ * Errors: LILAC_ERR_ARG (rows < 0, NULL), LILAC_ERR_CSR (validation failed:
+ * row_ptr[0] != 0, row_ptr decreasing, a column index < 0).
+ */
+int lilac_spmv_csr(int rows, const int *row_ptr, const int *col_idx,
+                   const double *vals, const double *x, double *y);
+/* Same with float32 values and vectors; products are accumulated in
+ * binary64 and rounded once to float32 when stored. */
+int lilac_spmv_csr_f32(int rows, const int *row_ptr, const int *col_idx,
+                       const float *vals, const float *x, float *y);
+
+/*
+ * result = sum_{0 <= i < n} a[i] * b[i], the dotproduct computation (section
+ * "Backtracking Search Algorithm", the dotproduct specification).  a and b
+ * may be host or device; the sum is taken on the device in a fixed two-level
+ * order.  n == 0 gives 0.  On error returns NaN and sets lilac_last_error.
+ */
+double lilac_dot(int64_t n, const double *a, const double *b);
+
+/* Marshaling control for the raw calls: the next call that uses the array
+ * containing `ptr` re-uploads it (values only when ptr is a vals array,
+ * full re-analysis when it is row_ptr or col_idx).  Unknown pointers are
+ * ignored.  lilac_release_all frees every cached device copy. */
+int lilac_invalidate(const void *ptr);
+int lilac_release_all(void);
+
+/* ---- device-resident matrix handle ----------------------------------- */
+#define LILAC_KEEP_HOST 1u /* remember the host pointers for invalidate */
+/*
+ * Creates a device copy of a CSR matrix (the ReadObject "construct" +
+ * "update" of the paper's section "Implementation", LiLAC-How): validates
+ * it, uploads it, derives cols = max(col_idx)+1 when cols < 0 (the cached
+ * invariant of section "LiLAC-How", the MKL example), and runs the one-time
+ * row-length analysis (bins of rows by length, chunk table for long rows)
+ * that every later product reuses.  Input pointers may be host or device;
+ * vals is double* for LILAC_F64, float* for LILAC_F32.  nnz must equal
+ * row_ptr[rows].  The handle owns its device memory.  Blocking.
+ * Errors: LILAC_ERR_ARG, LILAC_ERR_CSR, LILAC_ERR_OOM, LILAC_ERR_BUDGET.
+ */
+int lilac_csr_create(lilac_csr_t *h, int rows, int cols, int64_t nnz,
+                     const int *row_ptr, const int *col_idx, const void *vals,
+                     lilac_dtype dt, unsigned flags);
+/* New values for the same structure ("update"); vals host or device. */
+int lilac_csr_update_values(lilac_csr_t h, const void *vals);
+/* With LILAC_KEEP_HOST: re-upload and re-analyse from the remembered host
+ * pointers before the next use.  LILAC_ERR_STATE without it. */
+int lilac_csr_invalidate(lilac_csr_t h);
+/* Waits for the library's work on the handle, then frees it ("destruct"). */
+int lilac_csr_destroy(lilac_csr_t h);
+
+typedef struct {
+    int rows, cols;
+    int64_t nnz;
+    int64_t device_bytes;   /* bytes the handle holds on the device */
+    int dtype;              /* lilac_dtype */
+    int nbins;              /* number of row-length classes (9) */
+    int bin_upper[16];      /* inclusive upper row length of each class */
+    int bin_count[16];      /* rows in each class */
+    int chunk;              /* non-zeros per chunk of a split row */
+    int64_t nchunks;        /* entries of the chunk table */
+    int ntiles;             /* work tiles of one product */
+} lilac_csr_info_t;
+int lilac_csr_info(lilac_csr_t h, lilac_csr_info_t *out);
+
+/*
+ * Copies the handle's analysis to host arrays (for inspection and tests):
+ * bin_off[nbins+1] (row offsets of each class in bin_rows), bin_rows[rows]
+ * (rows grouped by class, ascending inside each class), and the chunk table
+ * c_row/c_k0/c_k1[nchunks] (row and half-open non-zero range of each chunk
+ * of the rows longer than the split threshold).  Any output may be NULL.
+ * Blocking.
+ */
+int lilac_csr_analysis(lilac_csr_t h, int *bin_off, int *bin_rows, int *c_row,
+                       int *c_k0, int *c_k1);
+
+/*
+ * Row-class thresholds: upper[c] is the largest row length handled by class
+ * c (classes use 1, 2, 4, 8, 16, 32, 64 lanes per row, then a whole
+ * workgroup per row, then split rows cut into `chunk`-non-zero pieces);
+ * rows_per_group[c] is how many rows one lane group handles per tile.  Any
+ * change re-runs the analysis.  NULL arguments keep the current values.
+ */
+int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
+                       const int *rows_per_group /* [9] */, int chunk);
+
+/*
+ * y = A x with x (cols entries) and y (rows entries) in device memory, of the
+ * handle's dtype.  Async on `stream`.
+ */
+int lilac_spmv(lilac_csr_t h, const void *x, void *y, void *stream);
+
+/* y = A x and out = sum_i w[i] * y[i] (the fused product + dot a CG step
+ * needs); w, x, y device arrays of the handle's dtype (F64 only), out a
+ * device double.  Async. */
+int lilac_spmv_dot(lilac_csr_t h, const void *x, void *y, const void *w,
+                   double *out, void *stream);
+
+/* out = sum a[i] b[i] with device a, b and a device result.  Async. */
+int lilac_dot_dev(int64_t n, const double *a, const double *b, double *out,
+                  void *stream);
+
+/*
+ * Conjugate gradient on an SPD handle (F64), the solver loop of the paper's
+ * NPB-CG example (sections "Introduction" and "Overview"): from x = 0,
+ * `iters` iterations of
+ *   q = A p; alpha = rho/(p.q); x += alpha p; r -= alpha q;
+ *   rho' = r.r; beta = rho'/rho; p = r + beta p
+ * stopping early (x kept) only if rho or p.q becomes exactly 0.  b and x are
+ * device arrays of rows doubles.  With LILAC_CG_GRAPH the whole solve runs as
+ * one captured HIP graph (scalars stay on the device, no host round trip);
+ * the graph is cached per (handle, b, x, iters).  rho_out / iters_done are
+ * host pointers (may be NULL; if given the call waits for the result).
+ * Async otherwise.
+ */
+#define LILAC_CG_GRAPH 1u
+int lilac_cg(lilac_csr_t h, const double *b, double *x, int iters,
+             unsigned flags, void *stream, double *rho_out, int *iters_done);
+
+/*
+ * PageRank power iteration on a pull-direction F32 handle (rows are
+ * destinations, vals[k] = 1/outdeg of the source), the repeated product of
+ * the paper's PageRank graph kernel (section "Results", graph kernels):
+ *   x <- d * (A x) + (1 - d) / rows      repeated `iters` times
+ * x_inout is a device float array of rows entries holding the start vector
+ * and receiving the result.  Runs as a cached HIP graph.  Async.
+ */
+int lilac_pagerank(lilac_csr_t h, float damping, int iters, float *x_inout,
+                   void *stream);
+
+/*
+ * Many independent products y_j = A_j x_j in one grouped persistent launch
+ * (plus one finaliser launch if any matrix has split rows).  Each y_j is
+ * bitwise equal to what lilac_spmv(h_j, x_j, y_j) gives.  All handles must
+ * share one dtype.  The grouped work list is cached per (handles, x, y)
+ * pointer set.  Async.
+ */
+int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
+                       void *const *ys, void *stream);
+
+/*
+ * Autotuner: times candidate row-class thresholds and tile shapes on the
+ * handle's own matrix (a few products into scratch vectors), keeps the
+ * fastest, and records it in the tuning cache under a key made of the
+ * matrix's shape class, so later handles of the same class start from it.
+ * The cache is read from and written to the JSON file named by
+ * LILAC_TUNE_CACHE when set.  Blocking.  best_us (may be NULL) receives the
+ * time of one product with the chosen plan.
+ */
+int lilac_csr_tune(lilac_csr_t h, double *best_us);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LILAC_H */

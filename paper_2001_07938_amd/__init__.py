@@ -1,0 +1,327 @@
+"""Python binding of liblilac.so (CSR SpMV + dot for AMD Instinct MI355X).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  The names follow the C ABI in ``include/lilac.h``.  PyTorch is
+imported first so that the library shares torch's HIP runtime; torch tensors
+(host or device) and numpy arrays are accepted wherever the C ABI takes a
+pointer.  If the library has not been built this module fails to import
+(there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (shares its HIP runtime with the library)
+
+__all__ = [
+    "LilacError", "lib", "lilac_spmv_csr", "lilac_spmv_csr_f32", "lilac_dot",
+    "lilac_invalidate", "lilac_release_all", "lilac_init", "lilac_finalize",
+    "lilac_dot_dev", "lilac_spmv_batched", "Csr", "F64", "F32",
+    "KEEP_HOST", "CG_GRAPH", "NCLASS", "HEADER_FUNCTIONS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblilac.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lilac.h")
+
+F64, F32 = 0, 1
+KEEP_HOST = 1
+CG_GRAPH = 1
+NCLASS = 9
+
+ERRORS = {-1: "LILAC_ERR_ARG", -2: "LILAC_ERR_CSR", -3: "LILAC_ERR_OOM",
+          -4: "LILAC_ERR_BUDGET", -5: "LILAC_ERR_DEVICE", -6: "LILAC_ERR_STATE",
+          -7: "LILAC_ERR_UNSUPPORTED"}
+
+
+class LilacError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CsrInfo(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int), ("cols", ctypes.c_int),
+                ("nnz", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("dtype", ctypes.c_int), ("nbins", ctypes.c_int),
+                ("bin_upper", ctypes.c_int * 16), ("bin_count", ctypes.c_int * 16),
+                ("chunk", ctypes.c_int), ("nchunks", ctypes.c_int64),
+                ("ntiles", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_SIGS = {
+    "lilac_init": ([_I], _I),
+    "lilac_finalize": ([], _I),
+    "lilac_last_error": ([], ctypes.c_char_p),
+    "lilac_version": ([], _I),
+    "lilac_spmv_csr": ([_I, _P, _P, _P, _P, _P], _I),
+    "lilac_spmv_csr_f32": ([_I, _P, _P, _P, _P, _P], _I),
+    "lilac_dot": ([_I64, _P, _P], ctypes.c_double),
+    "lilac_invalidate": ([_P], _I),
+    "lilac_release_all": ([], _I),
+    "lilac_csr_create": ([ctypes.POINTER(_P), _I, _I, _I64, _P, _P, _P, _I,
+                          ctypes.c_uint], _I),
+    "lilac_csr_update_values": ([_P, _P], _I),
+    "lilac_csr_invalidate": ([_P], _I),
+    "lilac_csr_destroy": ([_P], _I),
+    "lilac_csr_info": ([_P, ctypes.POINTER(CsrInfo)], _I),
+    "lilac_csr_analysis": ([_P, _P, _P, _P, _P, _P], _I),
+    "lilac_csr_set_plan": ([_P, _P, _P, _I], _I),
+    "lilac_spmv": ([_P, _P, _P, _P], _I),
+    "lilac_spmv_dot": ([_P, _P, _P, _P, _P, _P], _I),
+    "lilac_dot_dev": ([_I64, _P, _P, _P, _P], _I),
+    "lilac_cg": ([_P, _P, _P, _I, ctypes.c_uint, _P, _P, _P], _I),
+    "lilac_pagerank": ([_P, ctypes.c_float, _I, _P, _P], _I),
+    "lilac_spmv_batched": ([_I, _P, _P, _P, _P], _I),
+    "lilac_csr_tune": ([_P, _P], _I),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblilac.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2001_07938_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+lib()  # fail at import time when the library is missing
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/lilac.h."""
+    import re
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lilac_[a-z0-9_]+)\s*\(", txt)))
+
+
+HEADER_FUNCTIONS = header_functions()
+
+
+def _check(st: int):
+    if st != 0:
+        raise LilacError(st, lib().lilac_last_error().decode())
+
+
+def _ptr(a) -> Optional[int]:
+    """Address of a numpy array / torch tensor / raw int (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr()
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data
+    if isinstance(a, int):
+        return a
+    raise TypeError(f"unsupported argument type {type(a)}")
+
+
+def _stream(stream) -> Optional[int]:
+    """hipStream_t for an async call: torch's current stream by default, so
+    the work is ordered after the torch operations that produced its
+    inputs."""
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream or None
+    return int(stream) or None
+
+
+def _as_i32(a):
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.int32:
+            raise TypeError("index arrays must be int32")
+        return a
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# ------------------------------------------------------------ paper-shaped
+
+def lilac_init(device: int = -1):
+    _check(lib().lilac_init(device))
+
+
+def lilac_finalize():
+    _check(lib().lilac_finalize())
+
+
+def lilac_spmv_csr(rows: int, row_ptr, col_idx, vals, x, y):
+    """y = A x (float64).  Arguments: numpy arrays or torch tensors, host or
+    device; y is written in place."""
+    _check(lib().lilac_spmv_csr(rows, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
+                                _ptr(x), _ptr(y)))
+    return y
+
+
+def lilac_spmv_csr_f32(rows: int, row_ptr, col_idx, vals, x, y):
+    _check(lib().lilac_spmv_csr_f32(rows, _ptr(row_ptr), _ptr(col_idx),
+                                    _ptr(vals), _ptr(x), _ptr(y)))
+    return y
+
+
+def lilac_dot(n: int, a, b) -> float:
+    r = lib().lilac_dot(n, _ptr(a), _ptr(b))
+    if np.isnan(r):
+        err = lib().lilac_last_error().decode()
+        if err:
+            raise LilacError(-1, err)
+    return r
+
+
+def lilac_dot_dev(n: int, a, b, out, stream=None):
+    _check(lib().lilac_dot_dev(n, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
+
+
+def lilac_invalidate(ptr):
+    _check(lib().lilac_invalidate(_ptr(ptr)))
+
+
+def lilac_release_all():
+    _check(lib().lilac_release_all())
+
+
+def lilac_spmv_batched(handles: Sequence["Csr"], xs, ys, stream=None):
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*[h.handle for h in handles])
+    X = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+    Y = (ctypes.c_void_p * n)(*[_ptr(y) for y in ys])
+    _check(lib().lilac_spmv_batched(n, ctypes.cast(H, _P), ctypes.cast(X, _P),
+                                    ctypes.cast(Y, _P), _stream(stream)))
+
+
+# ------------------------------------------------------------ handle
+
+class Csr:
+    """Device-resident CSR matrix (lilac_csr_create ... lilac_csr_destroy)."""
+
+    def __init__(self, row_ptr, col_idx, vals, cols: int = -1,
+                 flags: int = 0):
+        self._keep = None
+        rp = _as_i32(row_ptr)
+        ci = _as_i32(col_idx)
+        if isinstance(vals, torch.Tensor):
+            dt = F32 if vals.dtype == torch.float32 else F64
+            if vals.dtype not in (torch.float32, torch.float64):
+                raise TypeError("vals must be float32 or float64")
+        else:
+            vals = np.ascontiguousarray(vals)
+            if vals.dtype not in (np.float32, np.float64):
+                vals = vals.astype(np.float64)
+            dt = F32 if vals.dtype == np.float32 else F64
+        rows = (rp.numel() if isinstance(rp, torch.Tensor) else rp.size) - 1
+        nnz = ci.numel() if isinstance(ci, torch.Tensor) else ci.size
+        h = ctypes.c_void_p()
+        if flags & KEEP_HOST:
+            self._keep = (rp, ci, vals)
+        _check(lib().lilac_csr_create(ctypes.byref(h), rows, cols, nnz, _ptr(rp),
+                                      _ptr(ci), _ptr(vals), dt, flags))
+        self.handle = h.value
+        self.dtype = dt
+        self.np_dtype = np.float32 if dt == F32 else np.float64
+        self.torch_dtype = torch.float32 if dt == F32 else torch.float64
+        inf = self.info()
+        self.rows, self.cols, self.nnz = inf.rows, inf.cols, inf.nnz
+
+    @classmethod
+    def from_gen(cls, A, **kw):
+        return cls(A.row_ptr, A.col_idx, A.vals, **kw)
+
+    def info(self) -> CsrInfo:
+        out = CsrInfo()
+        _check(lib().lilac_csr_info(self.handle, ctypes.byref(out)))
+        return out
+
+    def analysis(self):
+        """(bin_off, bin_rows, c_row, c_k0, c_k1) as numpy int32 arrays."""
+        inf = self.info()
+        off = np.empty(NCLASS + 1, dtype=np.int32)
+        br = np.empty(max(inf.rows, 1), dtype=np.int32)
+        m = max(inf.nchunks, 1)
+        cr = np.empty(m, dtype=np.int32)
+        c0 = np.empty(m, dtype=np.int32)
+        c1 = np.empty(m, dtype=np.int32)
+        _check(lib().lilac_csr_analysis(self.handle, _ptr(off), _ptr(br), _ptr(cr),
+                                        _ptr(c0), _ptr(c1)))
+        k = inf.nchunks
+        return off, br[:inf.rows], cr[:k], c0[:k], c1[:k]
+
+    def upper(self) -> np.ndarray:
+        inf = self.info()
+        return np.array(inf.bin_upper[:NCLASS], dtype=np.int32)
+
+    def set_plan(self, upper=None, rows_per_group=None, chunk: int = 0):
+        up = None if upper is None else np.ascontiguousarray(upper, dtype=np.int32)
+        rg = None if rows_per_group is None else \
+            np.ascontiguousarray(rows_per_group, dtype=np.int32)
+        _check(lib().lilac_csr_set_plan(self.handle, _ptr(up), _ptr(rg), chunk))
+
+    def spmv(self, x, y, stream=None):
+        _check(lib().lilac_spmv(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def spmv_dot(self, x, y, w, out, stream=None):
+        _check(lib().lilac_spmv_dot(self.handle, _ptr(x), _ptr(y), _ptr(w),
+                                    _ptr(out), _stream(stream)))
+
+    def update_values(self, vals):
+        _check(lib().lilac_csr_update_values(self.handle, _ptr(vals)))
+        if self._keep is not None:
+            self._keep = (self._keep[0], self._keep[1], vals)
+
+    def invalidate(self):
+        _check(lib().lilac_csr_invalidate(self.handle))
+
+    def cg(self, b, x, iters: int, graph: bool = True, stream=None,
+           want_result: bool = False):
+        rho = ctypes.c_double(0.0)
+        it = ctypes.c_int(0)
+        _check(lib().lilac_cg(self.handle, _ptr(b), _ptr(x), iters,
+                              CG_GRAPH if graph else 0, _stream(stream),
+                              ctypes.addressof(rho) if want_result else None,
+                              ctypes.addressof(it) if want_result else None))
+        return (rho.value, it.value) if want_result else None
+
+    def pagerank(self, damping: float, iters: int, x, stream=None):
+        _check(lib().lilac_pagerank(self.handle, float(damping), iters, _ptr(x),
+                                    _stream(stream)))
+        return x
+
+    def tune(self) -> float:
+        us = ctypes.c_double(0.0)
+        _check(lib().lilac_csr_tune(self.handle, ctypes.addressof(us)))
+        return us.value
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            _check(lib().lilac_csr_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.lilac_csr_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

@@ -1,0 +1,807 @@
+// Device code of liblilac.so for gfx950 (CDNA4, wave64): CSR analysis,
+// the tiled CSR product, the split-row finaliser, dot products and the
+// conjugate-gradient vector kernels.
+//
+// Every reduction here has a fixed shape (lane groups reduce with a xor
+// butterfly, workgroups combine their four wavefronts in index order, split
+// rows add their chunk sums in chunk order), so a given matrix and plan
+// always give bitwise identical results, whatever else runs on the GPU.
+#include "lilac_internal.h"
+
+namespace lilac {
+namespace {
+
+// Streaming loads for data read exactly once per product (vals, col_idx):
+// non-temporal, so they do not push the gathered vector out of the caches.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// Sum over aligned groups of W lanes.  All lanes of a group end with the
+// same value (x + y == y + x bitwise, so both partners agree at each step).
+template <int W>
+__device__ __forceinline__ double lane_group_sum(double v)
+{
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ int32_t lane_group_or(int32_t v)
+{
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1)
+        v |= __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ int32_t lane_group_max(int32_t v)
+{
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1)
+        v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum over a workgroup of NW wavefronts; every thread must call it and every
+// thread receives the total.  lds holds NW doubles.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = lane_group_sum<64>(v);
+    __syncthreads();  // earlier readers of lds are done
+    if ((threadIdx.x & 63) == 0)
+        lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = lds[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i)
+        t += lds[i];
+    return t;
+}
+
+// One lane's share of sum_{k in [k0,k1)} vals[k] * x[col[k]] when W lanes
+// split the range: lane l takes k0+l, k0+l+W, ...  Products are formed and
+// accumulated in binary64 (float32 data is widened exactly).  Four
+// independent loads are in flight per lane before the first use.
+template <typename V, int W>
+__device__ __forceinline__ double row_partial(const int32_t *__restrict__ col,
+                                              const V *__restrict__ vals,
+                                              const V *__restrict__ x,
+                                              int32_t k0, int32_t k1, int lane)
+{
+    double acc = 0.0;
+    int32_t k = k0 + lane;
+    for (; k + 3 * W < k1; k += 4 * W) {
+        const int32_t c0 = ld_stream(col + k);
+        const int32_t c1 = ld_stream(col + k + W);
+        const int32_t c2 = ld_stream(col + k + 2 * W);
+        const int32_t c3 = ld_stream(col + k + 3 * W);
+        const V v0 = ld_stream(vals + k);
+        const V v1 = ld_stream(vals + k + W);
+        const V v2 = ld_stream(vals + k + 2 * W);
+        const V v3 = ld_stream(vals + k + 3 * W);
+        const double x0 = (double)x[c0];
+        const double x1 = (double)x[c1];
+        const double x2 = (double)x[c2];
+        const double x3 = (double)x[c3];
+        acc = fma((double)v0, x0, acc);
+        acc = fma((double)v1, x1, acc);
+        acc = fma((double)v2, x2, acc);
+        acc = fma((double)v3, x3, acc);
+    }
+    for (; k < k1; k += W)
+        acc = fma((double)ld_stream(vals + k), (double)x[ld_stream(col + k)],
+                  acc);
+    return acc;
+}
+
+template <typename V>
+__device__ __forceinline__ V epilogue(double s, const Epi &e)
+{
+    if (e.mode == EPI_PAGERANK)
+        s = e.d * s + e.tele;
+    return (V)s;
+}
+
+// Rows of a tile, W lanes per row (W <= 64): group g of the workgroup takes
+// rows g, g+G, g+2G, ... of the tile, so consecutive groups read consecutive
+// rows of the class list.
+template <typename V, int W, bool DOT>
+__device__ __forceinline__ void rows_by_lanes(const MatDesc &m, const Tile &t,
+                                              const Epi &epi, double &dacc)
+{
+    constexpr int G = kBlock / W;
+    const int g = threadIdx.x / W;
+    const int lane = threadIdx.x % W;
+    const V *vals = (const V *)m.vals;
+    const V *x = (const V *)m.x;
+    V *y = (V *)m.y;
+    for (int j = g; j < t.count; j += G) {
+        const int32_t row = m.bin_rows[t.first + j];
+        const int32_t k0 = m.row_ptr[row];
+        const int32_t k1 = m.row_ptr[row + 1];
+        const double s =
+            lane_group_sum<W>(row_partial<V, W>(m.col, vals, x, k0, k1, lane));
+        if (lane == 0) {
+            const V out = epilogue<V>(s, epi);
+            y[row] = out;
+            if (DOT)
+                dacc = fma((double)((const V *)m.w)[row], (double)out, dacc);
+        }
+    }
+}
+
+// Rows of a tile, one whole workgroup per row.
+template <typename V, bool DOT>
+__device__ __forceinline__ void rows_by_block(const MatDesc &m, const Tile &t,
+                                              const Epi &epi, double &dacc,
+                                              double *lds)
+{
+    const V *vals = (const V *)m.vals;
+    const V *x = (const V *)m.x;
+    V *y = (V *)m.y;
+    for (int j = 0; j < t.count; ++j) {
+        const int32_t row = m.bin_rows[t.first + j];
+        const int32_t k0 = m.row_ptr[row];
+        const int32_t k1 = m.row_ptr[row + 1];
+        const double s = block_sum<kWaves>(
+            row_partial<V, kBlock>(m.col, vals, x, k0, k1, threadIdx.x), lds);
+        if (threadIdx.x == 0) {
+            const V out = epilogue<V>(s, epi);
+            y[row] = out;
+            if (DOT)
+                dacc = fma((double)((const V *)m.w)[row], (double)out, dacc);
+        }
+    }
+}
+
+// One chunk of a split row: the workgroup's sum goes to chunk_part.
+template <typename V>
+__device__ __forceinline__ void split_chunk(const MatDesc &m, const Tile &t,
+                                            double *lds)
+{
+    const int32_t c = t.first;
+    const int32_t k0 = m.c_k0[c];
+    const int32_t k1 = m.c_k1[c];
+    const double s = block_sum<kWaves>(
+        row_partial<V, kBlock>(m.col, (const V *)m.vals, (const V *)m.x, k0,
+                               k1, threadIdx.x),
+        lds);
+    if (threadIdx.x == 0)
+        m.chunk_part[c] = s;
+}
+
+// Persistent tile loop: workgroup b takes tiles b, b+grid, b+2*grid, ...
+// (a static assignment, so the optional fused dot is summed in a fixed
+// order).  Tiles are ordered longest work first.
+template <typename V, bool GROUPED, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_tiles(
+    const Tile *__restrict__ tiles, int32_t ntiles, MatDesc single,
+    const MatDesc *__restrict__ mats, Epi epi, double *__restrict__ dot_part)
+{
+    __shared__ double lds[kWaves];
+    double dacc = 0.0;
+    for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+        const Tile t = tiles[ti];
+        const MatDesc m = GROUPED ? mats[t.mat] : single;
+        switch (t.cls) {
+        case C_W1: rows_by_lanes<V, 1, DOT>(m, t, epi, dacc); break;
+        case C_W2: rows_by_lanes<V, 2, DOT>(m, t, epi, dacc); break;
+        case C_W4: rows_by_lanes<V, 4, DOT>(m, t, epi, dacc); break;
+        case C_W8: rows_by_lanes<V, 8, DOT>(m, t, epi, dacc); break;
+        case C_W16: rows_by_lanes<V, 16, DOT>(m, t, epi, dacc); break;
+        case C_W32: rows_by_lanes<V, 32, DOT>(m, t, epi, dacc); break;
+        case C_W64: rows_by_lanes<V, 64, DOT>(m, t, epi, dacc); break;
+        case C_WG: rows_by_block<V, DOT>(m, t, epi, dacc, lds); break;
+        default: split_chunk<V>(m, t, lds); break;
+        }
+    }
+    if (DOT) {
+        const double tot = block_sum<kWaves>(dacc, lds);
+        if (threadIdx.x == 0)
+            dot_part[blockIdx.x] = tot;
+    }
+}
+
+// Split rows: add the chunk sums of each split row in chunk order, apply the
+// epilogue and store.  One thread per split row.
+template <typename V, bool GROUPED, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_split_finalize(
+    const int32_t *__restrict__ items, int32_t n, MatDesc single,
+    const MatDesc *__restrict__ mats, Epi epi, double *__restrict__ dot_part)
+{
+    __shared__ double lds[kWaves];
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    double dacc = 0.0;
+    if (i < n) {
+        const int32_t mi = GROUPED ? items[2 * i] : 0;
+        const int32_t j = GROUPED ? items[2 * i + 1] : i;
+        const MatDesc m = GROUPED ? mats[mi] : single;
+        const int32_t row = m.bin_rows[m.split_begin + j];
+        double s = 0.0;
+        for (int32_t c = m.s_first[j]; c < m.s_first[j + 1]; ++c)
+            s += m.chunk_part[c];
+        const V out = epilogue<V>(s, epi);
+        ((V *)m.y)[row] = out;
+        if (DOT)
+            dacc = (double)((const V *)m.w)[row] * (double)out;
+    }
+    if (DOT) {
+        const double tot = block_sum<kWaves>(dacc, lds);
+        if (threadIdx.x == 0)
+            dot_part[blockIdx.x] = tot;
+    }
+}
+
+// ---------------------------------------------------------------- analysis
+
+__global__ __launch_bounds__(kBlock) void k_validate(
+    int32_t rows, const int32_t *__restrict__ rp, int64_t nnz,
+    const int32_t *__restrict__ col, int32_t cols_given,
+    int32_t *__restrict__ status)
+{
+    int32_t flags = 0, mx = -1;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = tid; i < rows; i += stride)
+        if (rp[i + 1] < rp[i])
+            flags |= 2;
+    if (tid == 0) {
+        if (rp[0] != 0)
+            flags |= 1;
+        if ((int64_t)rp[rows] != nnz)
+            flags |= 4;
+    }
+    for (int64_t k = tid; k < nnz; k += stride) {
+        const int32_t c = col[k];
+        if (c < 0 || (cols_given >= 0 && c >= cols_given))
+            flags |= 8;
+        mx = max(mx, c);
+    }
+    flags = lane_group_or<64>(flags);
+    mx = lane_group_max<64>(mx);
+    if ((threadIdx.x & 63) == 0) {
+        if (flags)
+            atomicOr(&status[0], flags);
+        atomicMax(&status[1], mx);
+    }
+}
+
+// Class of a row = number of class bounds it exceeds (bounds ascending), i.e.
+// the first class whose inclusive upper bound holds it.
+__device__ __forceinline__ int32_t row_class(int32_t len, const Thresholds &th)
+{
+    int32_t c = 0;
+#pragma unroll
+    for (int b = 0; b < NCLASS - 1; ++b)
+        c += (len > th.upper[b]) ? 1 : 0;
+    return c;
+}
+
+// hist is class-major: hist[c * nblk + block] = rows of class c in block.
+__global__ __launch_bounds__(kBlock) void k_bin_count(
+    int32_t rows, const int32_t *__restrict__ rp, Thresholds th,
+    int32_t *__restrict__ hist, int32_t nblk)
+{
+    __shared__ int32_t cnt[NCLASS];
+    if (threadIdx.x < NCLASS)
+        cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < rows)
+        atomicAdd(&cnt[row_class(rp[i + 1] - rp[i], th)], 1);
+    __syncthreads();
+    if (threadIdx.x < NCLASS)
+        hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: after the exclusive scan, hist[c*nblk+b] is where block
+// b's rows of class c start; inside the block rows keep ascending order
+// (wave by wave, lane by lane, ranks from ballots).
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(
+    int32_t rows, const int32_t *__restrict__ rp, Thresholds th,
+    const int32_t *__restrict__ hist, int32_t nblk,
+    int32_t *__restrict__ bin_rows)
+{
+    __shared__ int32_t wcnt[kWaves][NCLASS];
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t c = (i < rows) ? row_class(rp[i + 1] - rp[i], th) : -1;
+    const unsigned long long below = (lane == 0) ? 0ull : ((1ull << lane) - 1ull);
+    int32_t rank = 0;
+#pragma unroll
+    for (int b = 0; b < NCLASS; ++b) {
+        const unsigned long long m = __ballot(c == b);
+        if (lane == 0)
+            wcnt[wave][b] = __popcll(m);
+        if (c == b)
+            rank = __popcll(m & below);
+    }
+    __syncthreads();
+    if (c >= 0) {
+        int32_t off = hist[c * nblk + blockIdx.x];
+        for (int w = 0; w < wave; ++w)
+            off += wcnt[w][c];
+        bin_rows[off + rank] = i;
+    }
+}
+
+// Exclusive prefix sum of a[0..n) in place by one 1024-thread workgroup;
+// *total (if non-null) receives the sum.
+__global__ __launch_bounds__(1024) void k_scan_excl(int32_t *__restrict__ a,
+                                                    int64_t n,
+                                                    int32_t *__restrict__ total)
+{
+    __shared__ int32_t s[1024];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < n; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int32_t v = (i < n) ? a[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int32_t t = (threadIdx.x >= off) ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n)
+            a[i] = carry + s[threadIdx.x] - v;
+        carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total)
+        *total = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_count(
+    int32_t nsplit, const int32_t *__restrict__ split_rows,
+    const int32_t *__restrict__ rp, int32_t chunk, int32_t *__restrict__ cnt)
+{
+    const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j < nsplit) {
+        const int32_t r = split_rows[j];
+        const int64_t len = (int64_t)rp[r + 1] - rp[r];
+        cnt[j] = (int32_t)((len + chunk - 1) / chunk);
+    } else if (j == nsplit) {
+        cnt[j] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_fill(
+    int32_t nsplit, const int32_t *__restrict__ split_rows,
+    const int32_t *__restrict__ rp, int32_t chunk,
+    const int32_t *__restrict__ s_first, int32_t *__restrict__ c_row,
+    int32_t *__restrict__ c_k0, int32_t *__restrict__ c_k1)
+{
+    const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nsplit)
+        return;
+    const int32_t r = split_rows[j];
+    const int64_t a = rp[r], e = rp[r + 1];
+    int32_t c = s_first[j];
+    for (int64_t k = a; k < e; k += chunk, ++c) {
+        c_row[c] = r;
+        c_k0[c] = (int32_t)k;
+        c_k1[c] = (int32_t)((e - k > chunk) ? k + chunk : e);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *__restrict__ p,
+                                                     int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_bytes(
+    unsigned char *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = 0;
+}
+
+// ---------------------------------------------------------------- BLAS-1
+
+// Sum of part[0..n) by a 1024-thread workgroup in a fixed order.
+__device__ __forceinline__ double sum_parts_1024(const double *__restrict__ part,
+                                                 int32_t n, double *lds)
+{
+    double acc = 0.0;
+    for (int32_t i = threadIdx.x; i < n; i += 1024)
+        acc += part[i];
+    return block_sum<16>(acc, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_parts(
+    int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+    double *__restrict__ part)
+{
+    __shared__ double lds[kWaves];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        acc = fma(a[i], b[i], acc);
+    const double t = block_sum<kWaves>(acc, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_sum_parts(
+    const double *__restrict__ part, int32_t n, double *__restrict__ out)
+{
+    __shared__ double lds[16];
+    const double t = sum_parts_1024(part, n, lds);
+    if (threadIdx.x == 0)
+        *out = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(int64_t n,
+                                                 const T *__restrict__ src,
+                                                 T *__restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+// CG: x = 0, r = b, p = b, partial sums of b.b
+__global__ __launch_bounds__(kBlock) void k_cg_init(
+    int64_t n, const double *__restrict__ b, double *__restrict__ x,
+    double *__restrict__ r, double *__restrict__ p, double *__restrict__ part)
+{
+    __shared__ double lds[kWaves];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double bi = b[i];
+        x[i] = 0.0;
+        r[i] = bi;
+        p[i] = bi;
+        acc = fma(bi, bi, acc);
+    }
+    const double t = block_sum<kWaves>(acc, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_cg_start(
+    const double *__restrict__ part, int32_t n, CgScalars *__restrict__ sc)
+{
+    __shared__ double lds[16];
+    const double rho = sum_parts_1024(part, n, lds);
+    if (threadIdx.x == 0) {
+        sc->rho = rho;
+        sc->pq = 0.0;
+        sc->alpha = 0.0;
+        sc->beta = 0.0;
+        sc->done = 0;
+        sc->iters = 0;
+    }
+}
+
+// alpha = rho / (p.q); a zero rho or p.q ends the solve (x is kept).
+__global__ __launch_bounds__(1024) void k_cg_alpha(
+    const double *__restrict__ part, int32_t n, CgScalars *__restrict__ sc)
+{
+    __shared__ double lds[16];
+    if (sc->done)
+        return;
+    const double pq = sum_parts_1024(part, n, lds);
+    if (threadIdx.x == 0) {
+        const double rho = sc->rho;
+        sc->pq = pq;
+        if (rho == 0.0 || pq == 0.0)
+            sc->done = 1;
+        else
+            sc->alpha = rho / pq;
+    }
+}
+
+// x += alpha p; r -= alpha q; partial sums of r.r
+__global__ __launch_bounds__(kBlock) void k_cg_update(
+    int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ p,
+    const double *__restrict__ q, double *__restrict__ x,
+    double *__restrict__ r, double *__restrict__ part)
+{
+    __shared__ double lds[kWaves];
+    if (sc->done)
+        return;
+    const double alpha = sc->alpha;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        acc = fma(ri, ri, acc);
+    }
+    const double t = block_sum<kWaves>(acc, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = t;
+}
+
+// beta = rho' / rho; rho = rho'
+__global__ __launch_bounds__(1024) void k_cg_beta(
+    const double *__restrict__ part, int32_t n, CgScalars *__restrict__ sc)
+{
+    __shared__ double lds[16];
+    if (sc->done)
+        return;
+    const double rho_new = sum_parts_1024(part, n, lds);
+    if (threadIdx.x == 0) {
+        sc->beta = rho_new / sc->rho;
+        sc->rho = rho_new;
+        sc->iters += 1;
+    }
+}
+
+// p = r + beta p
+__global__ __launch_bounds__(kBlock) void k_cg_xpay(
+    int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ r,
+    double *__restrict__ p)
+{
+    if (sc->done)
+        return;
+    const double beta = sc->beta;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = fma(beta, p[i], r[i]);
+}
+
+inline int32_t grid_for(int64_t n, int32_t per_block, int32_t cap)
+{
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1)
+        g = 1;
+    if (g > cap)
+        g = cap;
+    return (int32_t)g;
+}
+
+inline void check_launch(const char *what)
+{
+    hip_check(hipGetLastError(), what, __FILE__, __LINE__);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+
+int32_t blas1_parts(int64_t n) { return grid_for(n, kBlock, kDotParts); }
+
+int occupancy_tiles(lilac_dtype dt)
+{
+    int n = 0;
+    hipError_t e = (dt == LILAC_F64)
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &n, k_spmv_tiles<double, true, false>, kBlock, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &n, k_spmv_tiles<float, true, false>, kBlock, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBlock, 4096)),
+                       dim3(kBlock), 0, s, p, n, v);
+    check_launch("k_fill_i32");
+}
+
+void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s)
+{
+    if (bytes <= 0)
+        return;
+    hipLaunchKernelGGL(k_zero_bytes, dim3(grid_for(bytes, kBlock, 4096)),
+                       dim3(kBlock), 0, s, (unsigned char *)p, bytes);
+    check_launch("k_zero_bytes");
+}
+
+void launch_validate(int32_t rows, const int32_t *rp, int64_t nnz,
+                     const int32_t *col, int32_t cols_given, int32_t *status,
+                     hipStream_t s)
+{
+    const int64_t work = nnz > rows ? nnz : (int64_t)rows + 1;
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(work, kBlock * 4, 4096)),
+                       dim3(kBlock), 0, s, rows, rp, nnz, col, cols_given,
+                       status);
+    check_launch("k_validate");
+}
+
+void launch_bin_count(int32_t rows, const int32_t *rp, const Thresholds &th,
+                      int32_t *hist, int32_t nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(kBlock), 0, s, rows, rp,
+                       th, hist, nblk);
+    check_launch("k_bin_count");
+}
+
+void launch_scan_excl(int32_t *a, int64_t n, int32_t *total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, a, n, total);
+    check_launch("k_scan_excl");
+}
+
+void launch_bin_scatter(int32_t rows, const int32_t *rp, const Thresholds &th,
+                        const int32_t *hist, int32_t nblk, int32_t *bin_rows,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(kBlock), 0, s, rows, rp,
+                       th, hist, nblk, bin_rows);
+    check_launch("k_bin_scatter");
+}
+
+void launch_chunk_count(int32_t nsplit, const int32_t *split_rows,
+                        const int32_t *rp, int32_t chunk, int32_t *cnt,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_chunk_count, dim3(grid_for((int64_t)nsplit + 1, kBlock, INT_MAX)),
+                       dim3(kBlock), 0, s, nsplit, split_rows, rp, chunk, cnt);
+    check_launch("k_chunk_count");
+}
+
+void launch_chunk_fill(int32_t nsplit, const int32_t *split_rows,
+                       const int32_t *rp, int32_t chunk, const int32_t *s_first,
+                       int32_t *c_row, int32_t *c_k0, int32_t *c_k1,
+                       hipStream_t s)
+{
+    if (nsplit <= 0)
+        return;
+    hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(nsplit, kBlock, INT_MAX)),
+                       dim3(kBlock), 0, s, nsplit, split_rows, rp, chunk,
+                       s_first, c_row, c_k0, c_k1);
+    check_launch("k_chunk_fill");
+}
+
+void launch_spmv_tiles(lilac_dtype dt, const Tile *tiles, int32_t ntiles,
+                       int32_t grid, const MatDesc &single,
+                       const MatDesc *mats, const Epi &epi, double *dot_part,
+                       hipStream_t s)
+{
+    if (ntiles <= 0 || grid <= 0)
+        return;
+    const bool grouped = mats != nullptr;
+    const bool dot = dot_part != nullptr;
+    dim3 g(grid), b(kBlock);
+    if (dt == LILAC_F64) {
+        if (grouped && dot)
+            hipLaunchKernelGGL((k_spmv_tiles<double, true, true>), g, b, 0, s, tiles, ntiles, single, mats, epi, dot_part);
+        else if (grouped)
+            hipLaunchKernelGGL((k_spmv_tiles<double, true, false>), g, b, 0, s, tiles, ntiles, single, mats, epi, dot_part);
+        else if (dot)
+            hipLaunchKernelGGL((k_spmv_tiles<double, false, true>), g, b, 0, s, tiles, ntiles, single, mats, epi, dot_part);
+        else
+            hipLaunchKernelGGL((k_spmv_tiles<double, false, false>), g, b, 0, s, tiles, ntiles, single, mats, epi, dot_part);
+    } else {
+        if (dot)
+            fail(LILAC_ERR_UNSUPPORTED, "fused dot is only provided for float64");
+        if (grouped)
+            hipLaunchKernelGGL((k_spmv_tiles<float, true, false>), g, b, 0, s, tiles, ntiles, single, mats, epi, dot_part);
+        else
+            hipLaunchKernelGGL((k_spmv_tiles<float, false, false>), g, b, 0, s, tiles, ntiles, single, mats, epi, dot_part);
+    }
+    check_launch("k_spmv_tiles");
+}
+
+void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,
+                           const MatDesc &single, const MatDesc *mats,
+                           const Epi &epi, double *dot_part, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    const bool grouped = mats != nullptr;
+    const bool dot = dot_part != nullptr;
+    dim3 g(grid_for(n, kBlock, INT_MAX)), b(kBlock);
+    if (dt == LILAC_F64) {
+        if (grouped)
+            hipLaunchKernelGGL((k_split_finalize<double, true, false>), g, b, 0, s, items, n, single, mats, epi, dot_part);
+        else if (dot)
+            hipLaunchKernelGGL((k_split_finalize<double, false, true>), g, b, 0, s, items, n, single, mats, epi, dot_part);
+        else
+            hipLaunchKernelGGL((k_split_finalize<double, false, false>), g, b, 0, s, items, n, single, mats, epi, dot_part);
+    } else {
+        if (grouped)
+            hipLaunchKernelGGL((k_split_finalize<float, true, false>), g, b, 0, s, items, n, single, mats, epi, dot_part);
+        else
+            hipLaunchKernelGGL((k_split_finalize<float, false, false>), g, b, 0, s, items, n, single, mats, epi, dot_part);
+    }
+    check_launch("k_split_finalize");
+}
+
+void launch_dot_parts(int64_t n, const double *a, const double *b,
+                      double *part, int32_t nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_parts, dim3(nparts), dim3(kBlock), 0, s, n, a, b,
+                       part);
+    check_launch("k_dot_parts");
+}
+
+void launch_sum_parts(const double *part, int32_t nparts, double *out,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, part, nparts,
+                       out);
+    check_launch("k_sum_parts");
+}
+
+void launch_copy_f64(int64_t n, const double *src, double *dst, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_copy<double>, dim3(grid_for(n, kBlock, 8192)),
+                       dim3(kBlock), 0, s, n, src, dst);
+    check_launch("k_copy");
+}
+
+void launch_copy_f32(int64_t n, const float *src, float *dst, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_copy<float>, dim3(grid_for(n, kBlock, 8192)),
+                       dim3(kBlock), 0, s, n, src, dst);
+    check_launch("k_copy");
+}
+
+void launch_cg_init(int64_t n, const double *b, double *x, double *r,
+                    double *p, double *part, int32_t nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_init, dim3(nparts), dim3(kBlock), 0, s, n, b, x, r,
+                       p, part);
+    check_launch("k_cg_init");
+}
+
+void launch_cg_start(const double *part, int32_t nparts, CgScalars *sc,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1024), 0, s, part, nparts, sc);
+    check_launch("k_cg_start");
+}
+
+void launch_cg_alpha(const double *part, int32_t nparts, CgScalars *sc,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, part, nparts, sc);
+    check_launch("k_cg_alpha");
+}
+
+void launch_cg_update(int64_t n, const CgScalars *sc, const double *p,
+                      const double *q, double *x, double *r, double *part,
+                      int32_t nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_update, dim3(nparts), dim3(kBlock), 0, s, n, sc, p,
+                       q, x, r, part);
+    check_launch("k_cg_update");
+}
+
+void launch_cg_beta(const double *part, int32_t nparts, CgScalars *sc,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, part, nparts, sc);
+    check_launch("k_cg_beta");
+}
+
+void launch_cg_xpay(int64_t n, const CgScalars *sc, const double *r,
+                    double *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_xpay, dim3(blas1_parts(n)), dim3(kBlock), 0, s, n,
+                       sc, r, p);
+    check_launch("k_cg_xpay");
+}
+
+}  // namespace lilac

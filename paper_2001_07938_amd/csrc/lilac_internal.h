@@ -1,0 +1,199 @@
+// Internal declarations shared by the HIP sources of liblilac.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lilac.h"
+
+namespace lilac {
+
+// Row classes by row length.  C_W<n>: n lanes of a wavefront share one row
+// (n = 1 is one lane per row, n = 64 a whole wavefront per row).  C_WG: one
+// 256-lane workgroup per row.  C_SPLIT: the row is cut into chunks of
+// `chunk` non-zeros, one workgroup per chunk, partial sums combined by a
+// finaliser in chunk order.
+enum RowClass : int32_t {
+    C_W1 = 0, C_W2, C_W4, C_W8, C_W16, C_W32, C_W64, C_WG, C_SPLIT, NCLASS
+};
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kPad = 64;          // device arrays of nnz are padded to this
+constexpr int kDotParts = 1024;   // partials of a standalone dot
+
+// One unit of work of a product: `count` rows of class `cls`, taken from the
+// class-ordered row list at `first` (for C_SPLIT: chunk index `first`).
+struct Tile {
+    int32_t cls;
+    int32_t mat;
+    int32_t first;
+    int32_t count;
+};
+
+// Everything a kernel needs to know about one matrix of a product.
+struct MatDesc {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const void *vals;
+    const int32_t *bin_rows;  // rows ordered by class, ascending per class
+    const int32_t *c_k0;      // chunk table: first non-zero of each chunk
+    const int32_t *c_k1;      //              one past the last
+    const int32_t *s_first;   // per split row: first chunk (nsplit+1 entries)
+    const void *x;
+    void *y;
+    const void *w;            // second operand of the fused dot (or null)
+    double *chunk_part;       // one partial sum per chunk
+    int32_t split_begin;      // position of the first split row in bin_rows
+    int32_t nsplit;
+};
+
+enum EpiMode : int32_t { EPI_NONE = 0, EPI_PAGERANK = 1 };
+
+// Epilogue applied when a row's sum s is stored:
+//   EPI_NONE:      y = s
+//   EPI_PAGERANK:  y = d * s + tele
+struct Epi {
+    int32_t mode;
+    int32_t pad;
+    double d;
+    double tele;
+};
+
+struct Thresholds {
+    int32_t upper[NCLASS];  // inclusive upper row length per class
+};
+
+// Per-matrix launch plan (row classes and tile shapes).
+struct Plan {
+    int32_t upper[NCLASS];
+    int32_t rpg[NCLASS];    // rows per lane group per tile
+    int32_t chunk;          // non-zeros per split-row chunk
+    int32_t grid_per_cu;    // persistent workgroups per compute unit
+};
+
+Plan default_plan();
+
+struct CgState;      // device buffers + graph cache of a CG solve
+struct PrState;      // graph cache of PageRank
+
+struct CsrHandle {
+    int32_t rows = 0, cols = 0;
+    int32_t cols_given = -1;   // as passed at creation (-1: derived)
+    int64_t nnz = 0;
+    lilac_dtype dt = LILAC_F64;
+    unsigned flags = 0;
+    // device copies
+    int32_t *d_row_ptr = nullptr;
+    int32_t *d_col = nullptr;
+    void *d_vals = nullptr;
+    // analysis
+    int32_t *d_bin_rows = nullptr;
+    int32_t *d_c_row = nullptr, *d_c_k0 = nullptr, *d_c_k1 = nullptr;
+    int32_t *d_s_first = nullptr;
+    double *d_chunk_part = nullptr;
+    Tile *d_tiles = nullptr;
+    double *d_dot_part = nullptr;   // one per persistent workgroup + finaliser
+    std::vector<int32_t> bin_off;   // NCLASS+1
+    int64_t nchunks = 0;
+    int32_t nsplit = 0;
+    int32_t ntiles = 0;
+    int32_t grid = 0;               // workgroups of the tile kernel
+    int32_t fin_blocks = 0;         // workgroups of the finaliser
+    Plan plan;
+    // remembered host arrays (LILAC_KEEP_HOST or raw-call cache)
+    const int32_t *h_row_ptr = nullptr, *h_col = nullptr;
+    const void *h_vals = nullptr;
+    bool dirty_struct = false, dirty_vals = false;
+    int64_t dev_bytes = 0;
+    CgState *cg = nullptr;
+    PrState *pr = nullptr;
+};
+
+size_t dtype_size(lilac_dtype dt);
+
+// ---- errors ---------------------------------------------------------------
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define HIPC(x) ::lilac::hip_check((x), #x, __FILE__, __LINE__)
+
+// ---- device memory with a byte budget -----------------------------------
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+int device_cu_count();
+
+// ---- kernel launchers (kernels.hip) --------------------------------------
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s);
+void launch_validate(int32_t rows, const int32_t *rp, int64_t nnz,
+                     const int32_t *col, int32_t cols_given, int32_t *status,
+                     hipStream_t s);
+void launch_bin_count(int32_t rows, const int32_t *rp, const Thresholds &th,
+                      int32_t *hist, int32_t nblk, hipStream_t s);
+void launch_scan_excl(int32_t *a, int64_t n, int32_t *total, hipStream_t s);
+void launch_bin_scatter(int32_t rows, const int32_t *rp, const Thresholds &th,
+                        const int32_t *hist, int32_t nblk, int32_t *bin_rows,
+                        hipStream_t s);
+void launch_chunk_count(int32_t nsplit, const int32_t *split_rows,
+                        const int32_t *rp, int32_t chunk, int32_t *cnt,
+                        hipStream_t s);
+void launch_chunk_fill(int32_t nsplit, const int32_t *split_rows,
+                       const int32_t *rp, int32_t chunk, const int32_t *s_first,
+                       int32_t *c_row, int32_t *c_k0, int32_t *c_k1,
+                       hipStream_t s);
+
+// Product over the tiles of one matrix (GROUPED = false, desc passed by
+// value) or of many (desc table in device memory).  With dot_part non-null,
+// workgroup g also writes dot_part[g] = sum over its rows of w[i]*y[i] and
+// the finaliser writes dot_part[grid + b].
+void launch_spmv_tiles(lilac_dtype dt, const Tile *tiles, int32_t ntiles,
+                       int32_t grid, const MatDesc &single,
+                       const MatDesc *mats, const Epi &epi, double *dot_part,
+                       hipStream_t s);
+// Finaliser for split rows: single matrix (items == null, n = nsplit) or a
+// list of (matrix, split row) items for grouped launches.
+void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,
+                           const MatDesc &single, const MatDesc *mats,
+                           const Epi &epi, double *dot_part, hipStream_t s);
+
+void launch_dot_parts(int64_t n, const double *a, const double *b,
+                      double *part, int32_t nparts, hipStream_t s);
+void launch_sum_parts(const double *part, int32_t nparts, double *out,
+                      hipStream_t s);
+void launch_copy_f64(int64_t n, const double *src, double *dst, hipStream_t s);
+void launch_copy_f32(int64_t n, const float *src, float *dst, hipStream_t s);
+
+// CG building blocks (device scalars in `CgScalars`)
+struct CgScalars {
+    double rho, pq, alpha, beta;
+    int32_t done, iters;
+    int32_t pad[2];
+};
+void launch_cg_init(int64_t n, const double *b, double *x, double *r,
+                    double *p, double *part, int32_t nparts, hipStream_t s);
+void launch_cg_start(const double *part, int32_t nparts, CgScalars *sc,
+                     hipStream_t s);
+void launch_cg_alpha(const double *part, int32_t nparts, CgScalars *sc,
+                     hipStream_t s);
+void launch_cg_update(int64_t n, const CgScalars *sc, const double *p,
+                      const double *q, double *x, double *r, double *part,
+                      int32_t nparts, hipStream_t s);
+void launch_cg_beta(const double *part, int32_t nparts, CgScalars *sc,
+                    hipStream_t s);
+void launch_cg_xpay(int64_t n, const CgScalars *sc, const double *r,
+                    double *p, hipStream_t s);
+int32_t blas1_parts(int64_t n);
+// Workgroups of the tile kernel resident per compute unit.
+int occupancy_tiles(lilac_dtype dt);
+bool is_device_ptr(const void *p);
+
+}  // namespace lilac

@@ -1,0 +1,1663 @@
+// Host runtime of liblilac.so: library context, device memory with a byte
+// budget, CSR handles (upload, validation, analysis, work tiles), the raw
+// pointer marshaling cache, CG and PageRank drivers (captured as HIP graphs),
+// grouped batched products, the autotuner and the C ABI entry points.
+#include <algorithm>
+#include <cctype>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "lilac_internal.h"
+#include "marshal.h"
+
+namespace lilac {
+
+// ===================================================================== errors
+
+static thread_local std::string g_last_error;
+
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what, const char *file, int line)
+{
+    if (e == hipSuccess)
+        return;
+    const int code = (e == hipErrorOutOfMemory) ? LILAC_ERR_OOM : LILAC_ERR_DEVICE;
+    const char *f = std::strrchr(file, '/');
+    fail(code, std::string(what) + ": " + hipGetErrorString(e) + " (" +
+                   (f ? f + 1 : file) + ":" + std::to_string(line) + ")");
+}
+
+size_t dtype_size(lilac_dtype dt) { return dt == LILAC_F32 ? 4 : 8; }
+
+// ==================================================================== context
+
+// The library's persistent state: the paper's PersistentVariables, created
+// by the first call (BeforeFirstExecution) and torn down by lilac_finalize
+// or at exit (AfterLastExecution).
+struct Context {
+    int device = -1;
+    int cu = 0;
+    hipStream_t stream = nullptr;   // the library's own stream
+    hipStream_t cap = nullptr;      // stream used only for graph capture
+    int64_t budget = INT64_MAX;
+    int64_t in_use = 0;
+    std::unordered_map<void *, size_t> sizes;
+    // scratch for the raw calls
+    void *x_buf = nullptr, *y_buf = nullptr;
+    size_t x_cap = 0, y_cap = 0;
+    double *dot_part = nullptr;     // kDotParts + 1 (result)
+    double *dot_a = nullptr, *dot_b = nullptr;
+    size_t dot_cap = 0;
+    int32_t *status = nullptr;      // 2 ints for validation
+    int32_t *total = nullptr;       // 1 int for scans
+    int occ[2] = {0, 0};            // tile-kernel workgroups per CU (f64, f32)
+};
+
+static std::recursive_mutex g_mu;
+static Context *g_ctx = nullptr;
+static bool g_exit_registered = false;
+
+static int64_t parse_bytes(const char *s)
+{
+    char *end = nullptr;
+    double v = std::strtod(s, &end);
+    if (end && *end) {
+        switch (*end) {
+        case 'k': case 'K': v *= 1024.0; break;
+        case 'm': case 'M': v *= 1024.0 * 1024.0; break;
+        case 'g': case 'G': v *= 1024.0 * 1024.0 * 1024.0; break;
+        case 't': case 'T': v *= 1024.0 * 1024.0 * 1024.0 * 1024.0; break;
+        default: break;
+        }
+    }
+    return v > 0 ? (int64_t)v : INT64_MAX;
+}
+
+void release_all_raw();
+void release_group_plans();
+void tune_cache_load();
+
+static void at_exit_hook()
+{
+    // Host-side tear-down only: the device memory goes with the process, and
+    // HIP calls from exit handlers can race the runtime's own shutdown.
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    marshal_reset();
+}
+
+static Context &init_ctx(int device)
+{
+    if (g_ctx)
+        return *g_ctx;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        fail(LILAC_ERR_DEVICE, "no HIP device available");
+    }
+    auto *c = new Context();
+    if (device < 0)
+        HIPC(hipGetDevice(&device));
+    if (device >= ndev) {
+        delete c;
+        fail(LILAC_ERR_ARG, "device index out of range");
+    }
+    HIPC(hipSetDevice(device));
+    c->device = device;
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, device));
+    c->cu = prop.multiProcessorCount;
+    HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPC(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    if (const char *b = std::getenv("LILAC_HBM_BUDGET"))
+        c->budget = parse_bytes(b);
+    g_ctx = c;
+    c->status = (int32_t *)dev_alloc(2 * sizeof(int32_t));
+    c->total = (int32_t *)dev_alloc(sizeof(int32_t));
+    c->dot_part = (double *)dev_alloc((kDotParts + 1) * sizeof(double));
+    if (!g_exit_registered) {
+        std::atexit(at_exit_hook);
+        g_exit_registered = true;
+    }
+    tune_cache_load();
+    return *c;
+}
+
+static Context &ctx()
+{
+    if (!g_ctx)
+        return init_ctx(-1);
+    return *g_ctx;
+}
+
+int device_cu_count() { return ctx().cu; }
+
+void *dev_alloc(size_t bytes)
+{
+    Context &c = *g_ctx;
+    if (bytes == 0)
+        bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (c.in_use + (int64_t)bytes > c.budget)
+        fail(LILAC_ERR_BUDGET, "allocation of " + std::to_string(bytes) +
+                                   " bytes exceeds the HBM budget (" +
+                                   std::to_string(c.in_use) + " of " +
+                                   std::to_string(c.budget) + " in use)");
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(LILAC_ERR_OOM, "hipMalloc of " + std::to_string(bytes) +
+                                " bytes failed: " + hipGetErrorString(e));
+    }
+    c.sizes[p] = bytes;
+    c.in_use += (int64_t)bytes;
+    return p;
+}
+
+void dev_free(void *p)
+{
+    if (!p || !g_ctx)
+        return;
+    Context &c = *g_ctx;
+    auto it = c.sizes.find(p);
+    if (it != c.sizes.end()) {
+        c.in_use -= (int64_t)it->second;
+        c.sizes.erase(it);
+    }
+    (void)hipFree(p);  // waits for outstanding work on the device
+}
+
+template <typename T>
+static void dev_free_reset(T *&p)
+{
+    dev_free((void *)p);
+    p = nullptr;
+}
+
+bool is_device_ptr(const void *p)
+{
+    if (!p)
+        return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+static void copy_in(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0)
+        return;
+    HIPC(hipMemcpyAsync(dst, src, bytes,
+                        is_device_ptr(src) ? hipMemcpyDeviceToDevice
+                                           : hipMemcpyHostToDevice,
+                        s));
+}
+
+static int tile_occupancy(lilac_dtype dt);
+
+// ============================================================ plan / tiles
+
+Plan default_plan()
+{
+    Plan p;
+    const int32_t up[NCLASS] = {2, 4, 8, 16, 32, 64, 1024, 8192, INT_MAX};
+    const int32_t rpg[NCLASS] = {1, 1, 1, 1, 1, 1, 2, 1, 1};
+    for (int c = 0; c < NCLASS; ++c) {
+        p.upper[c] = up[c];
+        p.rpg[c] = rpg[c];
+    }
+    p.chunk = 4096;
+    p.grid_per_cu = 8;
+    return p;
+}
+
+static void check_plan(const Plan &p)
+{
+    for (int c = 0; c + 1 < NCLASS - 1; ++c)
+        if (p.upper[c] > p.upper[c + 1])
+            fail(LILAC_ERR_ARG, "class bounds must be non-decreasing");
+    if (p.upper[0] < 0)
+        fail(LILAC_ERR_ARG, "class bounds must be >= 0");
+    for (int c = 0; c < NCLASS; ++c)
+        if (p.rpg[c] < 1 || p.rpg[c] > 64)
+            fail(LILAC_ERR_ARG, "rows per group must be in [1, 64]");
+    if (p.chunk < 256 || p.chunk > (1 << 24))
+        fail(LILAC_ERR_ARG, "chunk must be in [256, 2^24]");
+    if (p.grid_per_cu < 1 || p.grid_per_cu > 32)
+        fail(LILAC_ERR_ARG, "grid_per_cu must be in [1, 32]");
+}
+
+static const int kLanes[NCLASS] = {1, 2, 4, 8, 16, 32, 64, kBlock, kBlock};
+
+struct HandleExtra {
+    std::vector<Tile> tiles;   // host copy of the handle's tile list
+};
+static std::unordered_map<const CsrHandle *, HandleExtra> g_extra;
+
+static void free_analysis(CsrHandle &h)
+{
+    dev_free_reset(h.d_bin_rows);
+    dev_free_reset(h.d_c_row);
+    dev_free_reset(h.d_c_k0);
+    dev_free_reset(h.d_c_k1);
+    dev_free_reset(h.d_s_first);
+    dev_free_reset(h.d_chunk_part);
+    dev_free_reset(h.d_tiles);
+    dev_free_reset(h.d_dot_part);
+    h.ntiles = 0;
+    h.nchunks = 0;
+    h.nsplit = 0;
+    h.grid = 0;
+    h.fin_blocks = 0;
+}
+
+static int64_t analysis_bytes(const CsrHandle &h)
+{
+    return (int64_t)h.rows * 4 + h.nchunks * (3 * 4 + 8) +
+           (int64_t)(h.nsplit + 1) * 4 + (int64_t)h.ntiles * sizeof(Tile) +
+           (int64_t)(h.grid + h.fin_blocks) * 8;
+}
+
+// Row-length analysis: class of every row, class-ordered row list, chunk
+// table for split rows, and the tile list of one product.  Runs once per
+// matrix structure (and again after a plan change).
+static void drop_graphs(CsrHandle &h);
+void forget_handle_in_groups(const CsrHandle *h);
+
+static void analyse(CsrHandle &h, hipStream_t s)
+{
+    drop_graphs(h);
+    forget_handle_in_groups(&h);
+    free_analysis(h);
+    Context &c = ctx();
+    h.bin_off.assign(NCLASS + 1, 0);
+    std::vector<Tile> tiles;
+    if (h.rows > 0) {
+        Thresholds th;
+        for (int k = 0; k < NCLASS; ++k)
+            th.upper[k] = h.plan.upper[k];
+        const int32_t nblk = (h.rows + kBlock - 1) / kBlock;
+        const int64_t nh = (int64_t)NCLASS * nblk;
+        int32_t *hist = (int32_t *)dev_alloc(nh * sizeof(int32_t));
+        h.d_bin_rows = (int32_t *)dev_alloc((size_t)h.rows * sizeof(int32_t));
+        try {
+            launch_bin_count(h.rows, h.d_row_ptr, th, hist, nblk, s);
+            launch_scan_excl(hist, nh, nullptr, s);
+            launch_bin_scatter(h.rows, h.d_row_ptr, th, hist, nblk, h.d_bin_rows, s);
+            std::vector<int32_t> hh(nh);
+            HIPC(hipMemcpyAsync(hh.data(), hist, nh * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            for (int k = 0; k < NCLASS; ++k)
+                h.bin_off[k] = hh[(size_t)k * nblk];
+            h.bin_off[NCLASS] = h.rows;
+        } catch (...) {
+            dev_free(hist);
+            throw;
+        }
+        dev_free(hist);
+
+        const int32_t split_begin = h.bin_off[C_SPLIT];
+        h.nsplit = h.rows - split_begin;
+        if (h.nsplit > 0) {
+            h.d_s_first = (int32_t *)dev_alloc((size_t)(h.nsplit + 1) * 4);
+            launch_chunk_count(h.nsplit, h.d_bin_rows + split_begin, h.d_row_ptr,
+                               h.plan.chunk, h.d_s_first, s);
+            launch_scan_excl(h.d_s_first, h.nsplit + 1, c.total, s);
+            int32_t total = 0;
+            HIPC(hipMemcpyAsync(&total, c.total, 4, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            h.nchunks = total;
+            h.d_c_row = (int32_t *)dev_alloc((size_t)total * 4);
+            h.d_c_k0 = (int32_t *)dev_alloc((size_t)total * 4);
+            h.d_c_k1 = (int32_t *)dev_alloc((size_t)total * 4);
+            h.d_chunk_part = (double *)dev_alloc((size_t)total * 8);
+            launch_chunk_fill(h.nsplit, h.d_bin_rows + split_begin, h.d_row_ptr,
+                              h.plan.chunk, h.d_s_first, h.d_c_row, h.d_c_k0,
+                              h.d_c_k1, s);
+        }
+        // Tiles, longest work first: split chunks, whole-workgroup rows, then
+        // lane classes from 64 lanes down to 1.
+        for (int64_t ch = 0; ch < h.nchunks; ++ch)
+            tiles.push_back(Tile{C_SPLIT, 0, (int32_t)ch, 1});
+        for (int cls = C_WG; cls >= C_W1; --cls) {
+            const int32_t a = h.bin_off[cls], e = h.bin_off[cls + 1];
+            const int32_t groups = (cls == C_WG) ? 1 : kBlock / kLanes[cls];
+            const int32_t per = groups * h.plan.rpg[cls];
+            for (int32_t r = a; r < e; r += per)
+                tiles.push_back(Tile{cls, 0, r, std::min(per, e - r)});
+        }
+    }
+    h.ntiles = (int32_t)tiles.size();
+    if (h.ntiles > 0) {
+        h.d_tiles = (Tile *)dev_alloc(tiles.size() * sizeof(Tile));
+        HIPC(hipMemcpyAsync(h.d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
+                            hipMemcpyHostToDevice, s));
+        const int occ = std::max(1, std::min(h.plan.grid_per_cu, tile_occupancy(h.dt)));
+        h.grid = std::min<int32_t>(h.ntiles, c.cu * occ);
+    }
+    h.fin_blocks = (h.nsplit + kBlock - 1) / kBlock;
+    h.d_dot_part = (double *)dev_alloc((size_t)(h.grid + h.fin_blocks + 1) * 8);
+    HIPC(hipStreamSynchronize(s));
+    g_extra[&h].tiles = std::move(tiles);
+}
+
+// ============================================================ handle create
+
+struct TuneKey;
+bool tune_cache_lookup(const CsrHandle &h, Plan &out);
+
+static void upload_values(CsrHandle &h, const void *vals, hipStream_t s)
+{
+    copy_in(h.d_vals, vals, (size_t)h.nnz * dtype_size(h.dt), s);
+}
+
+static void construct(CsrHandle &h, int cols_given, const int32_t *rp,
+                      const int32_t *col, const void *vals, hipStream_t s)
+{
+    Context &c = ctx();
+    const size_t vs = dtype_size(h.dt);
+    const int64_t npad = ((h.nnz + kPad - 1) / kPad) * kPad + kPad;
+    if (!h.d_row_ptr) {
+        h.d_row_ptr = (int32_t *)dev_alloc((size_t)(h.rows + 1) * 4);
+        h.d_col = (int32_t *)dev_alloc((size_t)npad * 4);
+        h.d_vals = dev_alloc((size_t)npad * vs);
+    }
+    h.dev_bytes = (int64_t)(h.rows + 1) * 4 + npad * (4 + (int64_t)vs);
+    copy_in(h.d_row_ptr, rp, (size_t)(h.rows + 1) * 4, s);
+    copy_in(h.d_col, col, (size_t)h.nnz * 4, s);
+    upload_values(h, vals, s);
+    // padding past nnz is read (and discarded) by nothing, but keep it defined
+    launch_fill_i32(h.d_col + h.nnz, npad - h.nnz, 0, s);
+    launch_fill_bytes_zero((char *)h.d_vals + h.nnz * vs, (npad - h.nnz) * vs, s);
+    // validation + column count (one pass over row_ptr and col_idx)
+    launch_fill_i32(c.status, 1, 0, s);
+    launch_fill_i32(c.status + 1, 1, -1, s);
+    launch_validate(h.rows, h.d_row_ptr, h.nnz, h.d_col, cols_given, c.status, s);
+    int32_t st[2] = {0, -1};
+    HIPC(hipMemcpyAsync(st, c.status, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (st[0]) {
+        std::string why;
+        if (st[0] & 1) why += " row_ptr[0] != 0;";
+        if (st[0] & 2) why += " row_ptr decreases;";
+        if (st[0] & 4) why += " row_ptr[rows] != nnz;";
+        if (st[0] & 8) why += " column index out of range;";
+        fail(LILAC_ERR_CSR, "invalid CSR:" + why);
+    }
+    h.cols = cols_given >= 0 ? cols_given : st[1] + 1;
+    Plan tuned;
+    if (tune_cache_lookup(h, tuned))
+        h.plan = tuned;
+    analyse(h, s);
+    h.dev_bytes += analysis_bytes(h);
+    h.dirty_struct = h.dirty_vals = false;
+}
+
+static void destroy_handle(CsrHandle *h);
+
+static CsrHandle *create_handle(int rows, int cols, int64_t nnz,
+                                const int32_t *rp, const int32_t *col,
+                                const void *vals, lilac_dtype dt,
+                                unsigned flags)
+{
+    if (rows < 0)
+        fail(LILAC_ERR_ARG, "rows must be >= 0");
+    if (nnz < 0 || nnz > (int64_t)INT32_MAX - 8192)
+        fail(LILAC_ERR_ARG, "nnz must be in [0, 2^31 - 8192)");
+    if (cols < -1)
+        cols = -1;
+    if (!rp)
+        fail(LILAC_ERR_ARG, "row_ptr is NULL");
+    if (nnz > 0 && (!col || !vals))
+        fail(LILAC_ERR_ARG, "col_idx or vals is NULL");
+    if (dt != LILAC_F64 && dt != LILAC_F32)
+        fail(LILAC_ERR_ARG, "unknown dtype");
+    Context &c = ctx();
+    // device inputs may still be in flight on the caller's streams
+    if (is_device_ptr(rp) || is_device_ptr(col) || is_device_ptr(vals))
+        HIPC(hipDeviceSynchronize());
+    auto *h = new CsrHandle();
+    h->rows = rows;
+    h->nnz = nnz;
+    h->dt = dt;
+    h->flags = flags;
+    h->cols_given = cols;
+    h->plan = default_plan();
+    try {
+        construct(*h, cols, rp, col, vals, c.stream);
+    } catch (...) {
+        destroy_handle(h);
+        throw;
+    }
+    if (flags & LILAC_KEEP_HOST) {
+        h->h_row_ptr = rp;
+        h->h_col = col;
+        h->h_vals = vals;
+    }
+    return h;
+}
+
+struct CgState {
+    int64_t n = 0;
+    double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+    CgScalars *sc = nullptr;
+    struct G {
+        const double *b;
+        double *x;
+        int iters;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<G> graphs;
+};
+
+struct PrState {
+    float *tmp = nullptr;
+    struct G {
+        float *x;
+        int iters;
+        float d;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<G> graphs;
+};
+
+static void drop_graphs(CsrHandle &h)
+{
+    if (h.cg) {
+        for (auto &g : h.cg->graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        h.cg->graphs.clear();
+    }
+    if (h.pr) {
+        for (auto &g : h.pr->graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        h.pr->graphs.clear();
+    }
+}
+
+static void destroy_handle(CsrHandle *h)
+{
+    if (!h)
+        return;
+    if (g_ctx)
+        (void)hipStreamSynchronize(g_ctx->stream);
+    marshal_forget(h);
+    forget_handle_in_groups(h);
+    drop_graphs(*h);
+    if (h->cg) {
+        dev_free(h->cg->r);
+        dev_free(h->cg->p);
+        dev_free(h->cg->q);
+        dev_free(h->cg->part);
+        dev_free(h->cg->sc);
+        delete h->cg;
+    }
+    if (h->pr) {
+        dev_free(h->pr->tmp);
+        delete h->pr;
+    }
+    free_analysis(*h);
+    dev_free(h->d_row_ptr);
+    dev_free(h->d_col);
+    dev_free(h->d_vals);
+    g_extra.erase(h);
+    delete h;
+}
+
+// Bring a handle up to date before use (ReadObject: re-construct after a
+// structural change, update after a value change).
+static void refresh(CsrHandle &h, hipStream_t s)
+{
+    if (h.dirty_struct) {
+        if (!h.h_row_ptr)
+            fail(LILAC_ERR_STATE, "handle invalidated without remembered host arrays");
+        drop_graphs(h);
+        forget_handle_in_groups(&h);
+        construct(h, h.cols_given, h.h_row_ptr, h.h_col, h.h_vals, s);
+    } else if (h.dirty_vals) {
+        upload_values(h, h.h_vals, s);
+        h.dirty_vals = false;
+    }
+}
+
+// ================================================================ products
+
+static MatDesc make_desc(const CsrHandle &h, const void *x, void *y,
+                         const void *w, double *chunk_part)
+{
+    MatDesc d;
+    d.row_ptr = h.d_row_ptr;
+    d.col = h.d_col;
+    d.vals = h.d_vals;
+    d.bin_rows = h.d_bin_rows;
+    d.c_k0 = h.d_c_k0;
+    d.c_k1 = h.d_c_k1;
+    d.s_first = h.d_s_first;
+    d.x = x;
+    d.y = y;
+    d.w = w;
+    d.chunk_part = chunk_part;
+    d.split_begin = h.bin_off.empty() ? 0 : h.bin_off[C_SPLIT];
+    d.nsplit = h.nsplit;
+    return d;
+}
+
+static void spmv_enqueue(const CsrHandle &h, const void *x, void *y,
+                         const Epi &epi, const void *w, bool dot,
+                         hipStream_t s)
+{
+    if (h.rows == 0)
+        return;
+    const MatDesc d = make_desc(h, x, y, w, h.d_chunk_part);
+    launch_spmv_tiles(h.dt, h.d_tiles, h.ntiles, h.grid, d, nullptr, epi,
+                      dot ? h.d_dot_part : nullptr, s);
+    if (h.nsplit > 0)
+        launch_split_finalize(h.dt, nullptr, h.nsplit, d, nullptr, epi,
+                              dot ? h.d_dot_part + h.grid : nullptr, s);
+}
+
+static Epi epi_none() { return Epi{EPI_NONE, 0, 0.0, 0.0}; }
+
+// Workgroups of the tile kernel that fit on one CU at once.
+static int tile_occupancy(lilac_dtype dt)
+{
+    Context &c = *g_ctx;
+    int &o = c.occ[dt == LILAC_F32 ? 1 : 0];
+    if (o == 0) {
+        o = occupancy_tiles(dt);
+        if (o <= 0)
+            o = 4;
+    }
+    return o;
+}
+
+// =============================================================== raw calls
+
+struct RawKey {
+    const void *rp, *col, *vals;
+    int32_t rows;
+    int64_t nnz;
+    int dt;
+    bool operator<(const RawKey &o) const
+    {
+        return std::tie(rp, col, vals, rows, nnz, dt) <
+               std::tie(o.rp, o.col, o.vals, o.rows, o.nnz, o.dt);
+    }
+};
+static std::map<RawKey, CsrHandle *> g_raw;
+
+void release_all_raw()
+{
+    for (auto &kv : g_raw)
+        destroy_handle(kv.second);
+    g_raw.clear();
+}
+
+static int marshal_mode()
+{
+    const char *m = std::getenv("LILAC_MARSHAL");
+    if (!m)
+        return 0;
+    if (!std::strcmp(m, "naive"))
+        return 1;
+    if (!std::strcmp(m, "protect"))
+        return 2;
+    return 0;
+}
+
+static void *scratch(void *&buf, size_t &cap, size_t bytes)
+{
+    if (bytes > cap) {
+        dev_free(buf);
+        buf = nullptr;
+        cap = 0;
+        buf = dev_alloc(bytes);
+        cap = bytes;
+    }
+    return buf;
+}
+
+static void raw_spmv(int rows, const int32_t *rp, const int32_t *col,
+                     const void *vals, const void *x, void *y, lilac_dtype dt)
+{
+    if (rows < 0)
+        fail(LILAC_ERR_ARG, "rows must be >= 0");
+    if (!rp || !y)
+        fail(LILAC_ERR_ARG, "row_ptr or y is NULL");
+    Context &c = ctx();
+    hipStream_t s = c.stream;
+    if (rows == 0)
+        return;
+    int32_t last = 0;
+    const bool rp_dev = is_device_ptr(rp);
+    // a blocking call: device operands written on other streams must be done
+    if (rp_dev || is_device_ptr(x) || is_device_ptr(y) || is_device_ptr(vals))
+        HIPC(hipDeviceSynchronize());
+    if (rp_dev) {
+        HIPC(hipMemcpyAsync(&last, rp + rows, 4, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    } else {
+        last = rp[rows];
+    }
+    if (last < 0)
+        fail(LILAC_ERR_CSR, "invalid CSR: row_ptr[rows] < 0");
+    const int64_t nnz = last;
+    const int mode = marshal_mode();
+    CsrHandle *h = nullptr;
+    std::unique_ptr<CsrHandle, void (*)(CsrHandle *)> temp(nullptr, destroy_handle);
+    if (mode == 1) {
+        temp.reset(create_handle(rows, -1, nnz, rp, col, vals, dt, 0));
+        h = temp.get();
+    } else {
+        RawKey key{rp, col, vals, rows, nnz, (int)dt};
+        auto it = g_raw.find(key);
+        if (it == g_raw.end()) {
+            h = create_handle(rows, -1, nnz, rp, col, vals, dt, LILAC_KEEP_HOST);
+            g_raw[key] = h;
+            if (mode == 2) {
+                if (!rp_dev)
+                    marshal_track_range(h, MARSHAL_STRUCT, rp, (size_t)(rows + 1) * 4);
+                if (col && !is_device_ptr(col))
+                    marshal_track_range(h, MARSHAL_STRUCT, col, (size_t)nnz * 4);
+                if (vals && !is_device_ptr(vals))
+                    marshal_track_range(h, MARSHAL_VALS, vals, (size_t)nnz * dtype_size(dt));
+            }
+        } else {
+            h = it->second;
+            if (mode == 2) {
+                const int k = marshal_take_dirty(h);
+                if (k & MARSHAL_STRUCT)
+                    h->dirty_struct = true;
+                if (k & MARSHAL_VALS)
+                    h->dirty_vals = true;
+            }
+            const bool was_dirty = h->dirty_struct || h->dirty_vals;
+            refresh(*h, s);
+            if (mode == 2 && was_dirty)
+                marshal_arm(h);
+        }
+    }
+    const size_t vs = dtype_size(dt);
+    const void *dx = x;
+    if (h->cols > 0 && !x)
+        fail(LILAC_ERR_ARG, "x is NULL");
+    if (x && !is_device_ptr(x)) {
+        void *b = scratch(c.x_buf, c.x_cap, (size_t)h->cols * vs);
+        HIPC(hipMemcpyAsync(b, x, (size_t)h->cols * vs, hipMemcpyHostToDevice, s));
+        dx = b;
+    }
+    const bool y_dev = is_device_ptr(y);
+    void *dy = y_dev ? y : scratch(c.y_buf, c.y_cap, (size_t)rows * vs);
+    spmv_enqueue(*h, dx, dy, epi_none(), nullptr, false, s);
+    if (!y_dev)
+        HIPC(hipMemcpyAsync(y, dy, (size_t)rows * vs, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+}
+
+static void invalidate_ptr(const void *ptr)
+{
+    const char *p = (const char *)ptr;
+    for (auto &kv : g_raw) {
+        const RawKey &k = kv.first;
+        CsrHandle *h = kv.second;
+        const size_t vs = dtype_size((lilac_dtype)k.dt);
+        auto inside = [&](const void *base, size_t bytes) {
+            const char *b = (const char *)base;
+            return b && p >= b && p < b + std::max<size_t>(bytes, 1);
+        };
+        if (inside(k.rp, (size_t)(k.rows + 1) * 4) || inside(k.col, (size_t)k.nnz * 4))
+            h->dirty_struct = true;
+        else if (inside(k.vals, (size_t)k.nnz * vs))
+            h->dirty_vals = true;
+    }
+}
+
+// ===================================================================== dot
+
+static double raw_dot(int64_t n, const double *a, const double *b)
+{
+    if (n < 0)
+        fail(LILAC_ERR_ARG, "n must be >= 0");
+    if (n == 0)
+        return 0.0;
+    if (!a || !b)
+        fail(LILAC_ERR_ARG, "a or b is NULL");
+    Context &c = ctx();
+    hipStream_t s = c.stream;
+    const double *da = a, *db = b;
+    const size_t bytes = (size_t)n * 8;
+    const bool ad = is_device_ptr(a), bd = is_device_ptr(b);
+    if (ad || bd)
+        HIPC(hipDeviceSynchronize());
+    if (!ad || !bd) {
+        if (bytes > c.dot_cap) {
+            dev_free_reset(c.dot_a);
+            dev_free_reset(c.dot_b);
+            c.dot_cap = 0;
+            c.dot_a = (double *)dev_alloc(bytes);
+            c.dot_b = (double *)dev_alloc(bytes);
+            c.dot_cap = bytes;
+        }
+        if (!ad) {
+            HIPC(hipMemcpyAsync(c.dot_a, a, bytes, hipMemcpyHostToDevice, s));
+            da = c.dot_a;
+        }
+        if (!bd) {
+            HIPC(hipMemcpyAsync(c.dot_b, b, bytes, hipMemcpyHostToDevice, s));
+            db = c.dot_b;
+        }
+    }
+    const int32_t np = blas1_parts(n);
+    launch_dot_parts(n, da, db, c.dot_part, np, s);
+    launch_sum_parts(c.dot_part, np, c.dot_part + kDotParts, s);
+    double r = 0.0;
+    HIPC(hipMemcpyAsync(&r, c.dot_part + kDotParts, 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return r;
+}
+
+// ====================================================================== CG
+
+static void cg_prepare(CsrHandle &h)
+{
+    if (h.cg)
+        return;
+    auto *st = new CgState();
+    st->n = h.rows;
+    try {
+        st->r = (double *)dev_alloc((size_t)h.rows * 8);
+        st->p = (double *)dev_alloc((size_t)h.rows * 8);
+        st->q = (double *)dev_alloc((size_t)h.rows * 8);
+        st->part = (double *)dev_alloc((size_t)kDotParts * 8);
+        st->sc = (CgScalars *)dev_alloc(sizeof(CgScalars));
+    } catch (...) {
+        dev_free(st->r);
+        dev_free(st->p);
+        dev_free(st->q);
+        dev_free(st->part);
+        delete st;
+        throw;
+    }
+    h.cg = st;
+}
+
+// One whole solve: initialisation, then `iters` iterations of five kernels
+// (product with fused p.q partials, alpha, x/r update with r.r partials,
+// beta, direction update).  Scalars never leave the device.
+static void cg_enqueue(const CsrHandle &h, const double *b, double *x,
+                       int iters, hipStream_t s)
+{
+    const CgState &st = *h.cg;
+    const int64_t n = h.rows;
+    const int32_t np = blas1_parts(n);
+    const int32_t ndot = h.grid + h.fin_blocks;
+    launch_cg_init(n, b, x, st.r, st.p, st.part, np, s);
+    launch_cg_start(st.part, np, st.sc, s);
+    for (int it = 0; it < iters; ++it) {
+        spmv_enqueue(h, st.p, st.q, epi_none(), st.p, true, s);
+        launch_cg_alpha(h.d_dot_part, ndot, st.sc, s);
+        launch_cg_update(n, st.sc, st.p, st.q, x, st.r, st.part, np, s);
+        launch_cg_beta(st.part, np, st.sc, s);
+        launch_cg_xpay(n, st.sc, st.r, st.p, s);
+    }
+}
+
+template <typename Enq>
+static void capture(hipGraph_t &graph, hipGraphExec_t &exec, Enq enq)
+{
+    Context &c = ctx();
+    HIPC(hipStreamBeginCapture(c.cap, hipStreamCaptureModeRelaxed));
+    try {
+        enq(c.cap);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(c.cap, &g);
+        if (g)
+            (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        throw;
+    }
+    HIPC(hipStreamEndCapture(c.cap, &graph));
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        hip_check(e, "hipGraphInstantiate", __FILE__, __LINE__);
+    }
+}
+
+static void run_cg(CsrHandle &h, const double *b, double *x, int iters,
+                   unsigned flags, hipStream_t s, double *rho_out,
+                   int *iters_done)
+{
+    if (h.dt != LILAC_F64)
+        fail(LILAC_ERR_UNSUPPORTED, "CG needs a float64 handle");
+    if (h.rows != h.cols)
+        fail(LILAC_ERR_ARG, "CG needs a square matrix");
+    if (iters < 0)
+        fail(LILAC_ERR_ARG, "iters must be >= 0");
+    if (h.rows > 0 && (!b || !x))
+        fail(LILAC_ERR_ARG, "b or x is NULL");
+    if (h.rows > 0 && (!is_device_ptr(b) || !is_device_ptr(x)))
+        fail(LILAC_ERR_ARG, "b and x must be device arrays");
+    refresh(h, s);
+    if (h.rows == 0) {
+        if (rho_out)
+            *rho_out = 0.0;
+        if (iters_done)
+            *iters_done = 0;
+        return;
+    }
+    cg_prepare(h);
+    if (flags & LILAC_CG_GRAPH) {
+        CgState &st = *h.cg;
+        CgState::G *hit = nullptr;
+        for (auto &g : st.graphs)
+            if (g.b == b && g.x == x && g.iters == iters)
+                hit = &g;
+        if (!hit) {
+            if (st.graphs.size() >= 4) {
+                (void)hipGraphExecDestroy(st.graphs.front().exec);
+                (void)hipGraphDestroy(st.graphs.front().graph);
+                st.graphs.erase(st.graphs.begin());
+            }
+            CgState::G g{b, x, iters, nullptr, nullptr};
+            capture(g.graph, g.exec,
+                    [&](hipStream_t cs) { cg_enqueue(h, b, x, iters, cs); });
+            st.graphs.push_back(g);
+            hit = &st.graphs.back();
+        }
+        HIPC(hipGraphLaunch(hit->exec, s));
+    } else {
+        cg_enqueue(h, b, x, iters, s);
+    }
+    if (rho_out || iters_done) {
+        CgScalars sc;
+        HIPC(hipMemcpyAsync(&sc, h.cg->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        if (rho_out)
+            *rho_out = sc.rho;
+        if (iters_done)
+            *iters_done = sc.iters;
+    }
+}
+
+// ================================================================ PageRank
+
+static void run_pagerank(CsrHandle &h, float d, int iters, float *x,
+                         hipStream_t s)
+{
+    if (h.dt != LILAC_F32)
+        fail(LILAC_ERR_UNSUPPORTED, "PageRank needs a float32 handle");
+    if (h.rows != h.cols && h.nnz > 0 && h.cols > h.rows)
+        fail(LILAC_ERR_ARG, "PageRank needs a square matrix");
+    if (iters < 0)
+        fail(LILAC_ERR_ARG, "iters must be >= 0");
+    if (h.rows == 0 || iters == 0)
+        return;
+    if (!x || !is_device_ptr(x))
+        fail(LILAC_ERR_ARG, "x_inout must be a device array");
+    refresh(h, s);
+    if (!h.pr) {
+        auto *st = new PrState();
+        try {
+            st->tmp = (float *)dev_alloc((size_t)h.rows * 4);
+        } catch (...) {
+            delete st;
+            throw;
+        }
+        h.pr = st;
+    }
+    PrState &st = *h.pr;
+    PrState::G *hit = nullptr;
+    for (auto &g : st.graphs)
+        if (g.x == x && g.iters == iters && g.d == d)
+            hit = &g;
+    if (!hit) {
+        if (st.graphs.size() >= 4) {
+            (void)hipGraphExecDestroy(st.graphs.front().exec);
+            (void)hipGraphDestroy(st.graphs.front().graph);
+            st.graphs.erase(st.graphs.begin());
+        }
+        PrState::G g{x, iters, d, nullptr, nullptr};
+        const Epi epi{EPI_PAGERANK, 0, (double)d,
+                      (1.0 - (double)d) / (double)h.rows};
+        capture(g.graph, g.exec, [&](hipStream_t cs) {
+            float *cur = x, *nxt = st.tmp;
+            for (int it = 0; it < iters; ++it) {
+                spmv_enqueue(h, cur, nxt, epi, nullptr, false, cs);
+                std::swap(cur, nxt);
+            }
+            if (cur != x)
+                launch_copy_f32(h.rows, cur, x, cs);
+        });
+        st.graphs.push_back(g);
+        hit = &st.graphs.back();
+    }
+    HIPC(hipGraphLaunch(hit->exec, s));
+}
+
+// ================================================================= batched
+
+struct GroupPlan {
+    std::vector<const CsrHandle *> hs;
+    std::vector<const void *> xs;
+    std::vector<void *> ys;
+    lilac_dtype dt;
+    MatDesc *d_mats = nullptr;
+    Tile *d_tiles = nullptr;
+    int32_t *d_items = nullptr;
+    double *d_chunk = nullptr;
+    int32_t ntiles = 0, grid = 0, nitems = 0;
+};
+static std::vector<GroupPlan *> g_groups;
+
+static void free_group(GroupPlan *g)
+{
+    dev_free(g->d_mats);
+    dev_free(g->d_tiles);
+    dev_free(g->d_items);
+    dev_free(g->d_chunk);
+    delete g;
+}
+
+void release_group_plans()
+{
+    for (auto *g : g_groups)
+        free_group(g);
+    g_groups.clear();
+}
+
+void forget_handle_in_groups(const CsrHandle *h)
+{
+    for (size_t i = 0; i < g_groups.size();) {
+        GroupPlan *g = g_groups[i];
+        if (std::find(g->hs.begin(), g->hs.end(), h) != g->hs.end()) {
+            free_group(g);
+            g_groups.erase(g_groups.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+// One work list over all matrices: tiles of every matrix, class by class
+// from the longest work down, so the persistent workgroups drain the big
+// items first.  Each matrix keeps its own plan (and so its own reduction
+// order); split rows get chunk-partial space private to this group.
+static GroupPlan *build_group(int count, const lilac_csr_t *hs,
+                              const void *const *xs, void *const *ys,
+                              hipStream_t s)
+{
+    auto *g = new GroupPlan();
+    g->dt = ((const CsrHandle *)hs[0])->dt;
+    std::vector<MatDesc> descs(count);
+    std::vector<int64_t> chunk_off(count, 0);
+    int64_t nchunk_total = 0;
+    for (int j = 0; j < count; ++j) {
+        const CsrHandle *h = (const CsrHandle *)hs[j];
+        g->hs.push_back(h);
+        g->xs.push_back(xs[j]);
+        g->ys.push_back(ys[j]);
+        chunk_off[j] = nchunk_total;
+        nchunk_total += h->nchunks;
+    }
+    std::vector<int32_t> items;
+    try {
+        if (nchunk_total > 0)
+            g->d_chunk = (double *)dev_alloc((size_t)nchunk_total * 8);
+        for (int j = 0; j < count; ++j) {
+            const CsrHandle *h = g->hs[j];
+            descs[j] = make_desc(*h, xs[j], ys[j], nullptr,
+                                 g->d_chunk ? g->d_chunk + chunk_off[j] : nullptr);
+            for (int32_t k = 0; k < h->nsplit; ++k) {
+                items.push_back(j);
+                items.push_back(k);
+            }
+        }
+        std::vector<Tile> tiles;
+        for (int cls = C_SPLIT; cls >= C_W1; --cls)
+            for (int j = 0; j < count; ++j)
+                for (const Tile &t : g_extra[g->hs[j]].tiles)
+                    if (t.cls == cls) {
+                        Tile u = t;
+                        u.mat = j;
+                        tiles.push_back(u);
+                    }
+        g->ntiles = (int32_t)tiles.size();
+        g->nitems = (int32_t)(items.size() / 2);
+        g->d_mats = (MatDesc *)dev_alloc(descs.size() * sizeof(MatDesc));
+        HIPC(hipMemcpyAsync(g->d_mats, descs.data(), descs.size() * sizeof(MatDesc),
+                            hipMemcpyHostToDevice, s));
+        if (g->ntiles) {
+            g->d_tiles = (Tile *)dev_alloc(tiles.size() * sizeof(Tile));
+            HIPC(hipMemcpyAsync(g->d_tiles, tiles.data(), tiles.size() * sizeof(Tile),
+                                hipMemcpyHostToDevice, s));
+        }
+        if (g->nitems) {
+            g->d_items = (int32_t *)dev_alloc(items.size() * 4);
+            HIPC(hipMemcpyAsync(g->d_items, items.data(), items.size() * 4,
+                                hipMemcpyHostToDevice, s));
+        }
+        HIPC(hipStreamSynchronize(s));
+    } catch (...) {
+        free_group(g);
+        throw;
+    }
+    const int occ = std::max(1, std::min(8, tile_occupancy(g->dt)));
+    g->grid = std::min<int32_t>(g->ntiles, ctx().cu * occ);
+    return g;
+}
+
+static void run_batched(int count, const lilac_csr_t *hs, const void *const *xs,
+                        void *const *ys, hipStream_t s)
+{
+    if (count < 0)
+        fail(LILAC_ERR_ARG, "count must be >= 0");
+    if (count == 0)
+        return;
+    if (!hs || !xs || !ys)
+        fail(LILAC_ERR_ARG, "NULL array");
+    const lilac_dtype dt = ((const CsrHandle *)hs[0])->dt;
+    for (int j = 0; j < count; ++j) {
+        CsrHandle *h = (CsrHandle *)hs[j];
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        if (h->dt != dt)
+            fail(LILAC_ERR_ARG, "all handles of a batch must share one dtype");
+        if (h->rows > 0 && (!ys[j] || (h->cols > 0 && !xs[j])))
+            fail(LILAC_ERR_ARG, "NULL vector in batch");
+        refresh(*h, s);
+    }
+    GroupPlan *hit = nullptr;
+    for (auto *g : g_groups) {
+        if ((int)g->hs.size() != count)
+            continue;
+        bool same = true;
+        for (int j = 0; j < count && same; ++j)
+            same = g->hs[j] == (const CsrHandle *)hs[j] && g->xs[j] == xs[j] &&
+                   g->ys[j] == ys[j];
+        if (same) {
+            hit = g;
+            break;
+        }
+    }
+    if (!hit) {
+        if (g_groups.size() >= 8) {
+            free_group(g_groups.front());
+            g_groups.erase(g_groups.begin());
+        }
+        hit = build_group(count, hs, xs, ys, s);
+        g_groups.push_back(hit);
+    }
+    MatDesc none{};
+    launch_spmv_tiles(hit->dt, hit->d_tiles, hit->ntiles, hit->grid, none,
+                      hit->d_mats, epi_none(), nullptr, s);
+    if (hit->nitems)
+        launch_split_finalize(hit->dt, hit->d_items, hit->nitems, none,
+                              hit->d_mats, epi_none(), nullptr, s);
+}
+
+// ================================================================ tuning
+
+// Shape class of a matrix: dtype, log2 of rows, log2 of the mean row length
+// and of the longest-to-mean ratio.  Handles of one class share a plan.
+static std::string tune_key(const CsrHandle &h)
+{
+    const double mean = h.rows ? (double)h.nnz / h.rows : 0.0;
+    int32_t maxlen = 0;
+    if (!h.bin_off.empty()) {
+        for (int c = NCLASS - 1; c >= 0; --c)
+            if (h.bin_off[c + 1] > h.bin_off[c]) {
+                maxlen = h.plan.upper[c];
+                break;
+            }
+    }
+    (void)maxlen;
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "%s/r%d/m%d", h.dt == LILAC_F32 ? "f32" : "f64",
+                  (int)std::lround(std::log2(std::max(1, h.rows))),
+                  (int)std::lround(2.0 * std::log2(std::max(1.0, mean))));
+    return buf;
+}
+
+static std::map<std::string, Plan> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string plan_to_json(const Plan &p)
+{
+    std::ostringstream o;
+    o << "{\"upper\":[";
+    for (int c = 0; c < NCLASS - 1; ++c)
+        o << (c ? "," : "") << p.upper[c];
+    o << "],\"rpg\":[";
+    for (int c = 0; c < NCLASS; ++c)
+        o << (c ? "," : "") << p.rpg[c];
+    o << "],\"chunk\":" << p.chunk << ",\"grid_per_cu\":" << p.grid_per_cu << "}";
+    return o.str();
+}
+
+// Minimal reader for the cache file this library writes (one entry per
+// line: "key" followed by the plan's integers in a fixed order).
+void tune_cache_load()
+{
+    if (g_tune_loaded)
+        return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("LILAC_TUNE_CACHE");
+    if (!path)
+        return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t q0 = line.find('"');
+        const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+        if (q1 == std::string::npos)
+            continue;
+        const std::string key = line.substr(q0 + 1, q1 - q0 - 1);
+        std::vector<long> nums;
+        std::string rest = line.substr(q1 + 1);
+        for (size_t i = 0; i < rest.size();) {
+            if (std::isdigit((unsigned char)rest[i]) || (rest[i] == '-' && i + 1 < rest.size() &&
+                                                         std::isdigit((unsigned char)rest[i + 1]))) {
+                size_t used = 0;
+                nums.push_back(std::stol(rest.substr(i), &used));
+                i += used;
+            } else {
+                ++i;
+            }
+        }
+        if (nums.size() != (size_t)(NCLASS - 1 + NCLASS + 2))
+            continue;
+        Plan p = default_plan();
+        size_t k = 0;
+        for (int c = 0; c < NCLASS - 1; ++c)
+            p.upper[c] = (int32_t)nums[k++];
+        for (int c = 0; c < NCLASS; ++c)
+            p.rpg[c] = (int32_t)nums[k++];
+        p.chunk = (int32_t)nums[k++];
+        p.grid_per_cu = (int32_t)nums[k++];
+        try {
+            check_plan(p);
+            g_tune[key] = p;
+        } catch (const Error &) {
+        }
+    }
+}
+
+static void tune_cache_save()
+{
+    const char *path = std::getenv("LILAC_TUNE_CACHE");
+    if (!path)
+        return;
+    std::ofstream f(path);
+    f << "{\n";
+    size_t i = 0;
+    for (auto &kv : g_tune)
+        f << "\"" << kv.first << "\": " << plan_to_json(kv.second)
+          << (++i < g_tune.size() ? "," : "") << "\n";
+    f << "}\n";
+}
+
+bool tune_cache_lookup(const CsrHandle &h, Plan &out)
+{
+    if (g_tune.empty())
+        return false;
+    // the key needs the row count and mean length only, available here
+    auto it = g_tune.find(tune_key(h));
+    if (it == g_tune.end())
+        return false;
+    out = it->second;
+    return true;
+}
+
+static double time_spmv(CsrHandle &h, const void *x, void *y, int reps)
+{
+    Context &c = ctx();
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    for (int i = 0; i < 2; ++i)
+        spmv_enqueue(h, x, y, epi_none(), nullptr, false, c.stream);
+    HIPC(hipEventRecord(e0, c.stream));
+    for (int i = 0; i < reps; ++i)
+        spmv_enqueue(h, x, y, epi_none(), nullptr, false, c.stream);
+    HIPC(hipEventRecord(e1, c.stream));
+    HIPC(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return 1000.0 * ms / reps;
+}
+
+// Coordinate search over the plan: elements per lane of the lane classes,
+// the wavefront / workgroup / split bounds, the chunk size, rows per group
+// of the wavefront class and the persistent grid size.  Each candidate is
+// re-analysed and timed on the matrix itself.
+static double tune_handle(CsrHandle &h)
+{
+    Context &c = ctx();
+    refresh(h, c.stream);
+    if (h.rows == 0)
+        return 0.0;
+    const size_t vs = dtype_size(h.dt);
+    void *x = dev_alloc((size_t)std::max(1, h.cols) * vs);
+    void *y = dev_alloc((size_t)h.rows * vs);
+    launch_fill_bytes_zero(x, (int64_t)std::max(1, h.cols) * vs, c.stream);
+    const int reps = h.nnz > (1 << 22) ? 10 : 30;
+    Plan best = h.plan;
+    double best_us = 1e300;
+    auto trial = [&](const Plan &p) {
+        try {
+            check_plan(p);
+        } catch (const Error &) {
+            return;
+        }
+        h.plan = p;
+        analyse(h, c.stream);
+        const double us = time_spmv(h, x, y, reps);
+        if (us < best_us) {
+            best_us = us;
+            best = p;
+        }
+    };
+    try {
+        trial(best);
+        for (int epl : {1, 2, 4, 8}) {
+            Plan p = best;
+            for (int cl = C_W1; cl <= C_W32; ++cl)
+                p.upper[cl] = epl * kLanes[cl];
+            trial(p);
+        }
+        for (int w64 : {256, 512, 1024, 2048, 4096}) {
+            Plan p = best;
+            p.upper[C_W64] = std::max(w64, p.upper[C_W32]);
+            trial(p);
+        }
+        for (int wg : {4096, 8192, 16384, 65536}) {
+            Plan p = best;
+            p.upper[C_WG] = std::max(wg, p.upper[C_W64]);
+            trial(p);
+        }
+        for (int ch : {2048, 4096, 8192, 16384}) {
+            Plan p = best;
+            p.chunk = ch;
+            trial(p);
+        }
+        for (int r : {1, 2, 4, 8}) {
+            Plan p = best;
+            p.rpg[C_W64] = r;
+            trial(p);
+        }
+        for (int gp : {2, 4, 8, 16}) {
+            Plan p = best;
+            p.grid_per_cu = gp;
+            trial(p);
+        }
+    } catch (...) {
+        dev_free(x);
+        dev_free(y);
+        h.plan = best;
+        analyse(h, c.stream);
+        throw;
+    }
+    dev_free(x);
+    dev_free(y);
+    h.plan = best;
+    drop_graphs(h);
+    forget_handle_in_groups(&h);
+    analyse(h, c.stream);
+    g_tune[tune_key(h)] = best;
+    tune_cache_save();
+    return best_us;
+}
+
+// ================================================================== C ABI
+
+template <typename F>
+static int guard(F &&f)
+{
+    try {
+        std::lock_guard<std::recursive_mutex> lk(g_mu);
+        f();
+        return LILAC_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return LILAC_ERR_OOM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return LILAC_ERR_DEVICE;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return LILAC_ERR_DEVICE;
+    }
+}
+
+// NULL is HIP's default (null) stream, as for other HIP libraries.
+static hipStream_t pick_stream(void *s)
+{
+    ctx();
+    return (hipStream_t)s;
+}
+
+}  // namespace lilac
+
+using namespace lilac;
+
+extern "C" {
+
+int lilac_init(int device)
+{
+    return guard([&] { init_ctx(device); });
+}
+
+int lilac_finalize(void)
+{
+    return guard([&] {
+        if (!g_ctx)
+            return;
+        (void)hipDeviceSynchronize();
+        marshal_reset();
+        release_all_raw();
+        release_group_plans();
+        Context &c = *g_ctx;
+        dev_free(c.x_buf);
+        dev_free(c.y_buf);
+        dev_free(c.dot_a);
+        dev_free(c.dot_b);
+        c.x_buf = c.y_buf = nullptr;
+        c.dot_a = c.dot_b = nullptr;
+        c.x_cap = c.y_cap = c.dot_cap = 0;
+    });
+}
+
+const char *lilac_last_error(void) { return g_last_error.c_str(); }
+
+int lilac_version(void) { return 10000; }
+
+int lilac_spmv_csr(int rows, const int *row_ptr, const int *col_idx,
+                   const double *vals, const double *x, double *y)
+{
+    return guard([&] { raw_spmv(rows, row_ptr, col_idx, vals, x, y, LILAC_F64); });
+}
+
+int lilac_spmv_csr_f32(int rows, const int *row_ptr, const int *col_idx,
+                       const float *vals, const float *x, float *y)
+{
+    return guard([&] { raw_spmv(rows, row_ptr, col_idx, vals, x, y, LILAC_F32); });
+}
+
+double lilac_dot(int64_t n, const double *a, const double *b)
+{
+    double r = NAN;
+    const int st = guard([&] { r = raw_dot(n, a, b); });
+    return st == LILAC_OK ? r : NAN;
+}
+
+int lilac_invalidate(const void *ptr)
+{
+    return guard([&] {
+        if (ptr)
+            invalidate_ptr(ptr);
+    });
+}
+
+int lilac_release_all(void)
+{
+    return guard([&] {
+        if (!g_ctx)
+            return;
+        marshal_reset();
+        release_all_raw();
+    });
+}
+
+int lilac_csr_create(lilac_csr_t *h, int rows, int cols, int64_t nnz,
+                     const int *row_ptr, const int *col_idx, const void *vals,
+                     lilac_dtype dt, unsigned flags)
+{
+    return guard([&] {
+        if (!h)
+            fail(LILAC_ERR_ARG, "handle pointer is NULL");
+        *h = nullptr;
+        *h = (lilac_csr_t)create_handle(rows, cols, nnz, row_ptr, col_idx, vals,
+                                        dt, flags);
+    });
+}
+
+int lilac_csr_update_values(lilac_csr_t hh, const void *vals)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h || (!vals && h->nnz > 0))
+            fail(LILAC_ERR_ARG, "NULL handle or vals");
+        if (is_device_ptr(vals))
+            HIPC(hipDeviceSynchronize());
+        upload_values(*h, vals, ctx().stream);
+        HIPC(hipStreamSynchronize(ctx().stream));
+        if (h->flags & LILAC_KEEP_HOST)
+            h->h_vals = vals;
+        h->dirty_vals = false;
+    });
+}
+
+int lilac_csr_invalidate(lilac_csr_t hh)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        if (!(h->flags & LILAC_KEEP_HOST))
+            fail(LILAC_ERR_STATE, "handle was created without LILAC_KEEP_HOST");
+        h->dirty_struct = true;
+    });
+}
+
+int lilac_csr_destroy(lilac_csr_t hh)
+{
+    return guard([&] { destroy_handle((CsrHandle *)hh); });
+}
+
+int lilac_csr_info(lilac_csr_t hh, lilac_csr_info_t *out)
+{
+    return guard([&] {
+        const CsrHandle *h = (const CsrHandle *)hh;
+        if (!h || !out)
+            fail(LILAC_ERR_ARG, "NULL argument");
+        std::memset(out, 0, sizeof(*out));
+        out->rows = h->rows;
+        out->cols = h->cols;
+        out->nnz = h->nnz;
+        out->device_bytes = h->dev_bytes;
+        out->dtype = h->dt;
+        out->nbins = NCLASS;
+        for (int c = 0; c < NCLASS; ++c) {
+            out->bin_upper[c] = h->plan.upper[c];
+            out->bin_count[c] = h->bin_off.empty() ? 0 : h->bin_off[c + 1] - h->bin_off[c];
+        }
+        out->chunk = h->plan.chunk;
+        out->nchunks = h->nchunks;
+        out->ntiles = h->ntiles;
+    });
+}
+
+int lilac_csr_analysis(lilac_csr_t hh, int *bin_off, int *bin_rows, int *c_row,
+                       int *c_k0, int *c_k1)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        hipStream_t s = ctx().stream;
+        refresh(*h, s);
+        if (bin_off)
+            std::memcpy(bin_off, h->bin_off.data(), (NCLASS + 1) * sizeof(int));
+        if (bin_rows && h->rows)
+            HIPC(hipMemcpyAsync(bin_rows, h->d_bin_rows, (size_t)h->rows * 4,
+                                hipMemcpyDeviceToHost, s));
+        const size_t cb = (size_t)h->nchunks * 4;
+        if (cb && c_row)
+            HIPC(hipMemcpyAsync(c_row, h->d_c_row, cb, hipMemcpyDeviceToHost, s));
+        if (cb && c_k0)
+            HIPC(hipMemcpyAsync(c_k0, h->d_c_k0, cb, hipMemcpyDeviceToHost, s));
+        if (cb && c_k1)
+            HIPC(hipMemcpyAsync(c_k1, h->d_c_k1, cb, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    });
+}
+
+int lilac_csr_set_plan(lilac_csr_t hh, const int *upper, const int *rpg, int chunk)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        Plan p = h->plan;
+        if (upper)
+            for (int c = 0; c < NCLASS - 1; ++c)
+                p.upper[c] = upper[c];
+        if (rpg)
+            for (int c = 0; c < NCLASS; ++c)
+                p.rpg[c] = rpg[c];
+        if (chunk > 0)
+            p.chunk = chunk;
+        check_plan(p);
+        hipStream_t s = ctx().stream;
+        refresh(*h, s);
+        drop_graphs(*h);
+        forget_handle_in_groups(h);
+        h->plan = p;
+        h->dev_bytes -= analysis_bytes(*h);
+        analyse(*h, s);
+        h->dev_bytes += analysis_bytes(*h);
+    });
+}
+
+int lilac_spmv(lilac_csr_t hh, const void *x, void *y, void *stream)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        if (h->rows > 0 && (!y || (h->cols > 0 && !x)))
+            fail(LILAC_ERR_ARG, "NULL vector");
+        hipStream_t s = pick_stream(stream);
+        refresh(*h, s);
+        spmv_enqueue(*h, x, y, epi_none(), nullptr, false, s);
+    });
+}
+
+int lilac_spmv_dot(lilac_csr_t hh, const void *x, void *y, const void *w,
+                   double *out, void *stream)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h || !out)
+            fail(LILAC_ERR_ARG, "NULL argument");
+        if (h->dt != LILAC_F64)
+            fail(LILAC_ERR_UNSUPPORTED, "fused dot is only provided for float64");
+        if (h->rows > 0 && (!y || !w || (h->cols > 0 && !x)))
+            fail(LILAC_ERR_ARG, "NULL vector");
+        hipStream_t s = pick_stream(stream);
+        refresh(*h, s);
+        if (h->rows == 0) {
+            launch_fill_bytes_zero(out, 8, s);
+            return;
+        }
+        spmv_enqueue(*h, x, y, epi_none(), w, true, s);
+        launch_sum_parts(h->d_dot_part, h->grid + h->fin_blocks, out, s);
+    });
+}
+
+int lilac_dot_dev(int64_t n, const double *a, const double *b, double *out,
+                  void *stream)
+{
+    return guard([&] {
+        if (n < 0 || !out)
+            fail(LILAC_ERR_ARG, "bad argument");
+        hipStream_t s = pick_stream(stream);
+        if (n == 0) {
+            launch_fill_bytes_zero(out, 8, s);
+            return;
+        }
+        if (!a || !b)
+            fail(LILAC_ERR_ARG, "NULL vector");
+        Context &c = ctx();
+        const int32_t np = blas1_parts(n);
+        // partials in the library's scratch: calls on different streams
+        // must not overlap
+        launch_dot_parts(n, a, b, c.dot_part, np, s);
+        launch_sum_parts(c.dot_part, np, out, s);
+    });
+}
+
+int lilac_cg(lilac_csr_t hh, const double *b, double *x, int iters,
+             unsigned flags, void *stream, double *rho_out, int *iters_done)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        run_cg(*h, b, x, iters, flags, pick_stream(stream), rho_out, iters_done);
+    });
+}
+
+int lilac_pagerank(lilac_csr_t hh, float damping, int iters, float *x_inout,
+                   void *stream)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        run_pagerank(*h, damping, iters, x_inout, pick_stream(stream));
+    });
+}
+
+int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
+                       void *const *ys, void *stream)
+{
+    return guard([&] { run_batched(count, hs, xs, ys, pick_stream(stream)); });
+}
+
+int lilac_csr_tune(lilac_csr_t hh, double *best_us)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        const double us = tune_handle(*h);
+        if (best_us)
+            *best_us = us;
+    });
+}
+
+}  // extern "C"

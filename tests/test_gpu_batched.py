@@ -1,0 +1,85 @@
+"""Grouped batched products and the autotuner on the GPU: every matrix of a
+batch must equal its own single-call result bitwise, and the oracle within
+tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import paper_2001_07938_amd as L
+from tests.helpers import TOL_F32, TOL_F64, check_spmv
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _batch(count, seed, dtype=np.float64, n_hi=20000):
+    specs = gen.batch_specs(count, n_lo=200, n_hi=n_hi, seed=seed)
+    mats = [s.build().astype(dtype) for s in specs]
+    # a few matrices with split rows and empty rows
+    mats.append(gen.ragged(3000, 30000, seed=seed + 1, long_rows=2,
+                           long_len=20000).astype(dtype))
+    mats.append(gen.empty_matrix(10, 5).astype(dtype))
+    return mats
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batched_equals_single_bitwise(dtype):
+    mats = _batch(40, 5, dtype)
+    hs = [L.Csr.from_gen(A) for A in mats]
+    xs_h = [gen.vector(max(A.cols, 1), 100 + i, dtype=dtype) for i, A in enumerate(mats)]
+    xs = [_dev(x) for x in xs_h]
+    ys = [torch.empty(max(A.rows, 1), dtype=hs[0].torch_dtype, device=DEV) for A in mats]
+    ys1 = [torch.empty_like(y) for y in ys]
+    for h, x, y in zip(hs, xs, ys1):
+        h.spmv(x, y)
+    for rep in range(2):
+        L.lilac_spmv_batched(hs, xs, ys)
+        torch.cuda.synchronize()
+        for A, y, y1 in zip(mats, ys, ys1):
+            assert torch.equal(y[:A.rows], y1[:A.rows]), A.name
+    tol = TOL_F64 if dtype == np.float64 else TOL_F32
+    for A, x, y in zip(mats, xs_h, ys):
+        check_spmv(A, x[:A.cols], y[:A.rows].cpu().numpy(), tol)
+    for h in hs:
+        h.destroy()
+
+
+def test_batched_same_matrix_twice_with_split_rows():
+    A = gen.ragged(2000, 40000, seed=9, long_rows=3, long_len=25000)
+    h = L.Csr.from_gen(A)
+    x1, x2 = gen.vector(A.cols, 1), gen.vector(A.cols, 2)
+    y1 = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    y2 = torch.empty_like(y1)
+    L.lilac_spmv_batched([h, h], [_dev(x1), _dev(x2)], [y1, y2])
+    torch.cuda.synchronize()
+    check_spmv(A, x1, y1.cpu().numpy(), TOL_F64)
+    check_spmv(A, x2, y2.cpu().numpy(), TOL_F64)
+    h.destroy()
+
+
+def test_mixed_dtypes_rejected():
+    a = L.Csr.from_gen(gen.stencil(5, 7))
+    b = L.Csr.from_gen(gen.stencil(5, 7).astype(np.float32))
+    x = torch.zeros(125, dtype=torch.float64, device=DEV)
+    with pytest.raises(L.LilacError):
+        L.lilac_spmv_batched([a, b], [x, x], [x, x])
+    a.destroy()
+    b.destroy()
+
+
+def test_tuner_keeps_results_in_tolerance():
+    A = gen.random_rows(50000, 5, 60, seed=3)
+    x = gen.vector(A.cols, 4)
+    h = L.Csr.from_gen(A)
+    us = h.tune()
+    assert us > 0
+    y = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(x), y)
+    torch.cuda.synchronize()
+    check_spmv(A, x, y.cpu().numpy(), TOL_F64)
+    h.destroy()

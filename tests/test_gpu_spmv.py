@@ -1,0 +1,248 @@
+"""GPU parity of the CSR analysis and product against the oracle, through the
+C ABI (the paper-shaped raw call and the device-resident handle)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2001_07938_amd as L
+from tests.helpers import TOL_F32, TOL_F64, check_spmv
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _matrices():
+    return {
+        "ragged_split": lambda: gen.ragged(3000, 40000, seed=1, max_len=300,
+                                           long_rows=3, long_len=20000),
+        "ragged_dup_unsorted": lambda: gen.ragged(2000, 700, seed=2, max_len=150,
+                                                  dup=True, sort_cols=False,
+                                                  long_rows=2, long_len=9000),
+        "mostly_empty": lambda: gen.ragged(5000, 5000, seed=3, empty_frac=0.7),
+        "one_long_row": lambda: gen.ragged(1, 200000, seed=4, long_rows=1,
+                                           long_len=150000, empty_frac=0.0),
+        "uniform16": lambda: gen.uniform_rows(4096, 16),
+        "stencil7": lambda: gen.stencil(20, 7),
+        "stencil27": lambda: gen.stencil(12, 27),
+        "rmat16": lambda: gen.rmat_pagerank(16, 1 << 20, seed=5).astype(np.float64),
+        "spd_small": lambda: gen.spd_random(20000, 60, seed=6),
+        "random5_60": lambda: gen.random_rows(30000, 5, 60, seed=7),
+        "all_empty": lambda: gen.empty_matrix(1000, 10),
+    }
+
+
+MATS = _matrices()
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_analysis_bit_exact(name):
+    A = MATS[name]()
+    h = L.Csr.from_gen(A)
+    up = h.upper()
+    bor, off, br = oracle.bins(A.row_ptr, up)
+    g_off, g_br, g_cr, g_c0, g_c1 = h.analysis()
+    assert np.array_equal(g_off, off)
+    assert np.array_equal(g_br, br)
+    inf = h.info()
+    cr, c0, c1 = oracle.split_chunks(A.row_ptr, int(up[7]), inf.chunk)
+    assert np.array_equal(g_cr, cr) and np.array_equal(g_c0, c0) and \
+        np.array_equal(g_c1, c1)
+    assert h.cols == oracle.cols(A.col_idx) and h.nnz == A.nnz
+    h.destroy()
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_spmv_f64_handle(name):
+    A = MATS[name]()
+    x = gen.vector(max(A.cols, 1), 11)[:A.cols]
+    h = L.Csr.from_gen(A)
+    xd = _dev(x) if A.cols else torch.zeros(1, dtype=torch.float64, device=DEV)
+    yd = torch.full((A.rows,), np.nan, dtype=torch.float64, device=DEV)
+    h.spmv(xd, yd)
+    check_spmv(A, x, _host(yd), TOL_F64)
+    # deterministic: a second product is bitwise identical
+    y2 = torch.empty_like(yd)
+    h.spmv(xd, y2)
+    assert torch.equal(yd, y2)
+    h.destroy()
+
+
+@pytest.mark.parametrize("name", ["ragged_split", "rmat16", "stencil27",
+                                  "ragged_dup_unsorted"])
+def test_spmv_f32_handle(name):
+    A = MATS[name]().astype(np.float32)
+    x = gen.vector(A.cols, 12, dtype=np.float32)
+    h = L.Csr.from_gen(A)
+    yd = torch.empty(A.rows, dtype=torch.float32, device=DEV)
+    h.spmv(_dev(x), yd)
+    check_spmv(A, x, _host(yd), TOL_F32)
+    h.destroy()
+
+
+@pytest.mark.parametrize("name", ["ragged_split", "random5_60", "stencil7",
+                                  "one_long_row"])
+def test_integer_inputs_bitwise(name):
+    """Integer values and vector: every summation order gives the same exact
+    integers, so every class of row must equal the oracle bitwise."""
+    A = MATS[name]()
+    A.vals = gen.int_vector(A.nnz, 13)
+    x = gen.int_vector(A.cols, 14)
+    h = L.Csr.from_gen(A)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(x), yd)
+    assert np.array_equal(_host(yd), oracle.spmv_csr(A.row_ptr, A.col_idx, A.vals, x))
+    h.destroy()
+
+
+def test_identity_and_permutation_bitwise():
+    x = gen.vector(100_000, 15)
+    for A, ref in ((gen.identity(100_000), x),
+                   (gen.permutation(100_000, 16), None)):
+        h = L.Csr.from_gen(A)
+        yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+        h.spmv(_dev(x), yd)
+        want = x if ref is not None else x[A.col_idx]
+        assert np.array_equal(_host(yd), want)
+        h.destroy()
+
+
+def test_paper_example_raw_call(golden_dir):
+    with open(os.path.join(golden_dir, "csr_5x5.json")) as f:
+        g = json.load(f)
+    rp = np.array(g["row_ptr"], np.int32)
+    ci = np.array(g["col_ind"], np.int32)
+    v = np.array(g["val"], np.float64)
+    for xs, ys in ((g["x_ones"], g["y_ones"]), (g["x_ramp"], g["y_ramp"])):
+        y = np.zeros(5)
+        L.lilac_spmv_csr(5, rp, ci, v, np.array(xs, np.float64), y)
+        assert list(y) == ys
+        y32 = np.zeros(5, np.float32)
+        L.lilac_spmv_csr_f32(5, rp, ci, v.astype(np.float32),
+                             np.array(xs, np.float32), y32)
+        assert list(y32) == ys
+    L.lilac_release_all()
+
+
+def test_raw_call_device_pointers_and_cache():
+    A = gen.ragged(4000, 30000, seed=21, max_len=200, long_rows=2, long_len=12000)
+    x = gen.vector(A.cols, 22)
+    rp, ci, v, xd = _dev(A.row_ptr), _dev(A.col_idx), _dev(A.vals), _dev(x)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    L.lilac_spmv_csr(A.rows, rp, ci, v, xd, yd)
+    check_spmv(A, x, _host(yd), TOL_F64)
+    # host arrays, then change values and invalidate: the cached copy updates
+    y = np.empty(A.rows)
+    vals = A.vals.copy()
+    L.lilac_spmv_csr(A.rows, A.row_ptr, A.col_idx, vals, x, y)
+    check_spmv(A, x, y, TOL_F64)
+    vals *= 2.0
+    L.lilac_spmv_csr(A.rows, A.row_ptr, A.col_idx, vals, x, y)  # stale copy
+    check_spmv(A, x, y, TOL_F64)
+    L.lilac_invalidate(vals)
+    L.lilac_spmv_csr(A.rows, A.row_ptr, A.col_idx, vals, x, y)
+    A2 = gen.Csr(A.rows, A.cols, A.row_ptr, A.col_idx, vals, "x2")
+    check_spmv(A2, x, y, TOL_F64)
+    L.lilac_release_all()
+
+
+def test_invalid_csr_rejected():
+    A = gen.ragged(100, 50, seed=30, empty_frac=0.0)
+    bad = A.row_ptr.copy()
+    bad[0] = 1
+    cases = [bad]
+    mono = A.row_ptr.copy()
+    mono[5] = mono[4] - 1
+    cases.append(mono)
+    for rp in cases:
+        assert oracle.validate(rp, A.col_idx) != 0
+        with pytest.raises(L.LilacError) as e:
+            L.Csr(rp, A.col_idx, A.vals)
+        assert e.value.code == -2
+    ci = A.col_idx.copy()
+    ci[7] = -3
+    assert oracle.validate(A.row_ptr, ci) != 0
+    with pytest.raises(L.LilacError) as e:
+        L.Csr(A.row_ptr, ci, A.vals)
+    assert e.value.code == -2
+    with pytest.raises(L.LilacError) as e:
+        L.Csr(A.row_ptr, A.col_idx, A.vals, cols=int(A.col_idx.max()))
+    assert e.value.code == -2
+
+
+def test_plan_changes_keep_results_in_tolerance():
+    A = gen.ragged(6000, 60000, seed=31, max_len=600, long_rows=4, long_len=30000)
+    x = gen.vector(A.cols, 32)
+    h = L.Csr.from_gen(A)
+    xd = _dev(x)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    for upper, chunk in (([1, 2, 4, 8, 16, 32, 256, 2048], 1024),
+                         ([4, 8, 16, 32, 64, 128, 4096, 65536], 8192),
+                         ([0, 0, 0, 0, 0, 0, 0, 0], 256)):
+        h.set_plan(upper=upper, chunk=chunk)
+        g_off, g_br, g_cr, g_c0, g_c1 = h.analysis()
+        _, off, br = oracle.bins(A.row_ptr, np.array(upper + [2**31 - 1], np.int32))
+        assert np.array_equal(g_off, off) and np.array_equal(g_br, br)
+        h.spmv(xd, yd)
+        check_spmv(A, x, _host(yd), TOL_F64)
+    h.destroy()
+
+
+def test_full_size_uniform16_and_spd150k():
+    """The single-product workloads at full size, every row checked."""
+    A = gen.uniform_rows()
+    x = gen.vector(A.cols, 41)
+    h = L.Csr.from_gen(A)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(x), yd)
+    check_spmv(A, x, _host(yd), TOL_F64)
+    h.destroy()
+    A = gen.spd_random()
+    x = gen.vector(A.cols, 42)
+    h = L.Csr.from_gen(A)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(x), yd)
+    check_spmv(A, x, _host(yd), TOL_F64)
+    h.destroy()
+
+
+def test_full_size_rmat22_f32():
+    A = gen.rmat_pagerank()
+    x = gen.vector(A.cols, 43, dtype=np.float32, lo=0.0, hi=1.0)
+    h = L.Csr.from_gen(A)
+    yd = torch.empty(A.rows, dtype=torch.float32, device=DEV)
+    h.spmv(_dev(x), yd)
+    check_spmv(A, x, _host(yd), TOL_F32)
+    inf = h.info()
+    assert inf.nchunks > 0  # the hubs take the split path
+    h.destroy()
+
+
+def test_dot_raw_and_device():
+    for n in (0, 1, 1000, 150_000, 3_000_001):
+        a = gen.vector(n, 50)
+        b = gen.vector(n, 51)
+        ref = oracle.dot(a, b)
+        mag = oracle.dot_abs(a, b)
+        got = L.lilac_dot(n, a, b)
+        assert abs(got - ref) <= TOL_F64 * mag
+        if n:
+            ad, bd = _dev(a), _dev(b)
+            out = torch.empty(1, dtype=torch.float64, device=DEV)
+            L.lilac_dot_dev(n, ad, bd, out)
+            assert _host(out)[0] == L.lilac_dot(n, ad, bd)
+    assert L.lilac_dot(1 << 20, np.ones(1 << 20), np.ones(1 << 20)) == float(1 << 20)
