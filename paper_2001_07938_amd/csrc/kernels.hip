@@ -19,14 +19,46 @@ __device__ __forceinline__ T ld_stream(const T *p)
     return __builtin_nontemporal_load(p);
 }
 
-// Sum over aligned groups of W lanes.  All lanes of a group end with the
-// same value (x + y == y + x bitwise, so both partners agree at each step).
+// Cross-lane move of a double with a DPP pattern (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __double2loint(v);
+    const int hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over aligned groups of W lanes (W a power of two <= 64).  Inside a
+// row of 16 lanes: neighbours (quad_perm 1,0,3,2), pairs (2,3,0,1), then the
+// half-row and row mirrors, each adding the partner's partial; across rows
+// the four row sums are read as uniform values and added in lane order.
+// All lanes of a group end with the same value (x + y == y + x bitwise).
 template <int W>
 __device__ __forceinline__ double lane_group_sum(double v)
 {
-#pragma unroll
-    for (int off = W / 2; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off, 64);
+    if (W >= 2)
+        v += dpp_f64<0xB1>(v);
+    if (W >= 4)
+        v += dpp_f64<0x4E>(v);
+    if (W >= 8)
+        v += dpp_f64<0x141>(v);
+    if (W >= 16)
+        v += dpp_f64<0x140>(v);
+    if (W >= 32) {
+        const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+        const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+        if (W == 32)
+            v = (threadIdx.x & 32) ? r2 + r3 : r0 + r1;
+        else
+            v = (r0 + r1) + (r2 + r3);
+    }
     return v;
 }
 
@@ -65,41 +97,108 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return t;
 }
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+// VEC consecutive values / column indices in one 16-byte (8-byte for the
+// float64 indices) streaming load.  `p` is VEC-element aligned.
+template <typename V, int VEC> struct Lanes;
+template <typename V> struct Lanes<V, 1> {
+    V v[1];
+    int32_t c[1];
+    __device__ __forceinline__ void load(const V *vp, const int32_t *cp)
+    {
+        v[0] = ld_stream(vp);
+        c[0] = ld_stream(cp);
+    }
+};
+template <> struct Lanes<double, 2> {
+    double v[2];
+    int32_t c[2];
+    __device__ __forceinline__ void load(const double *vp, const int32_t *cp)
+    {
+        const f64x2 a = ld_stream((const f64x2 *)vp);
+        const i32x2 b = ld_stream((const i32x2 *)cp);
+        v[0] = a.x;
+        v[1] = a.y;
+        c[0] = b.x;
+        c[1] = b.y;
+    }
+};
+template <> struct Lanes<float, 4> {
+    float v[4];
+    int32_t c[4];
+    __device__ __forceinline__ void load(const float *vp, const int32_t *cp)
+    {
+        const f32x4 a = ld_stream((const f32x4 *)vp);
+        const i32x4 b = ld_stream((const i32x4 *)cp);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = a.z;
+        v[3] = a.w;
+        c[0] = b.x;
+        c[1] = b.y;
+        c[2] = b.z;
+        c[3] = b.w;
+    }
+};
+
 // One lane's share of sum_{k in [k0,k1)} vals[k] * x[col[k]] when W lanes
-// split the range: lane l takes k0+l, k0+l+W, ...  Products are formed and
-// accumulated in binary64 (float32 data is widened exactly).  Four
-// independent loads are in flight per lane before the first use.
-template <typename V, int W>
+// split the range.  The range is walked in passes over an aligned window
+// starting at k0 rounded down to VEC: in a pass, lane l loads the VEC-element
+// vectors at base + (j*W + l)*VEC for j < U, all issued before any is used
+// (so U*VEC elements per lane are in flight), then gathers x for the
+// elements that belong to the row.  Elements of a loaded vector outside
+// [k0, k1) belong to neighbouring rows (or the array padding) and are
+// skipped.  Products are formed and accumulated in binary64 (float32 data is
+// widened exactly), in the order j, then element within the vector.
+template <typename V, int W, int VEC, int U>
 __device__ __forceinline__ double row_partial(const int32_t *__restrict__ col,
                                               const V *__restrict__ vals,
                                               const V *__restrict__ x,
                                               int32_t k0, int32_t k1, int lane)
 {
     double acc = 0.0;
-    int32_t k = k0 + lane;
-    for (; k + 3 * W < k1; k += 4 * W) {
-        const int32_t c0 = ld_stream(col + k);
-        const int32_t c1 = ld_stream(col + k + W);
-        const int32_t c2 = ld_stream(col + k + 2 * W);
-        const int32_t c3 = ld_stream(col + k + 3 * W);
-        const V v0 = ld_stream(vals + k);
-        const V v1 = ld_stream(vals + k + W);
-        const V v2 = ld_stream(vals + k + 2 * W);
-        const V v3 = ld_stream(vals + k + 3 * W);
-        const double x0 = (double)x[c0];
-        const double x1 = (double)x[c1];
-        const double x2 = (double)x[c2];
-        const double x3 = (double)x[c3];
-        acc = fma((double)v0, x0, acc);
-        acc = fma((double)v1, x1, acc);
-        acc = fma((double)v2, x2, acc);
-        acc = fma((double)v3, x3, acc);
+    const int32_t kb = k0 & ~(VEC - 1);
+    for (int32_t base = kb; base < k1; base += U * W * VEC) {
+        // every load is issued unconditionally (vectors past the row end
+        // re-read the first one), so all U loads are in flight together
+        Lanes<V, VEC> d[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int32_t e0 = base + (j * W + lane) * VEC;
+            const int32_t ea = (e0 < k1) ? e0 : kb;
+            d[j].load(vals + ea, col + ea);
+        }
+        // column indices of loaded vectors are all valid (real entries of
+        // some row or the zero padding), so the gathers need no guard
+        double xv[U][VEC];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+#pragma unroll
+            for (int t = 0; t < VEC; ++t)
+                xv[j][t] = (double)x[d[j].c[t]];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) {
+                const int32_t e = base + (j * W + lane) * VEC + t;
+                if (e >= k0 && e < k1)
+                    acc = fma((double)d[j].v[t], xv[j][t], acc);
+            }
     }
-    for (; k < k1; k += W)
-        acc = fma((double)ld_stream(vals + k), (double)x[ld_stream(col + k)],
-                  acc);
     return acc;
 }
+
+// Vector width used by a class: 16-byte value loads for groups of 8 lanes
+// or more, single elements for narrower groups (rows of a few non-zeros).
+template <typename V, int W>
+struct VecOf {
+    static constexpr int value = (W >= 8) ? (int)(16 / sizeof(V)) : 1;
+};
+constexpr int kUnroll = 2;
 
 template <typename V>
 __device__ __forceinline__ V epilogue(double s, const Epi &e)
@@ -109,30 +208,59 @@ __device__ __forceinline__ V epilogue(double s, const Epi &e)
     return (V)s;
 }
 
-// Rows of a tile, W lanes per row (W <= 64): group g of the workgroup takes
+// Row number of position p of a tile: contiguous tiles store the first row
+// itself, others index the class-ordered row list.
+__device__ __forceinline__ int32_t tile_row(const MatDesc &m, const Tile &t,
+                                            int32_t p)
+{
+    return (t.cls & kTileContig) ? t.first + p : m.bin_rows[t.first + p];
+}
+
+// Rows of a tile, W lanes per row (W <= 64).  Group g of the workgroup takes
 // rows g, g+G, g+2G, ... of the tile, so consecutive groups read consecutive
-// rows of the class list.
+// rows.  Each wavefront first loads the row numbers and bounds of all the
+// rows its groups will handle (one lane per row) and hands them to the
+// groups with lane shuffles, so no row waits on its own pointer loads.
 template <typename V, int W, bool DOT>
 __device__ __forceinline__ void rows_by_lanes(const MatDesc &m, const Tile &t,
                                               const Epi &epi, double &dacc)
 {
-    constexpr int G = kBlock / W;
-    const int g = threadIdx.x / W;
-    const int lane = threadIdx.x % W;
+    constexpr int G = kBlock / W;   // groups per workgroup
+    constexpr int GPW = 64 / W;     // groups per wavefront
+    const int wave = threadIdx.x >> 6;
+    const int wl = threadIdx.x & 63;
+    const int q = wl / W;           // group within the wavefront
+    const int lane = wl % W;
+    const int g = wave * GPW + q;
     const V *vals = (const V *)m.vals;
     const V *x = (const V *)m.x;
     V *y = (V *)m.y;
-    for (int j = g; j < t.count; j += G) {
-        const int32_t row = m.bin_rows[t.first + j];
-        const int32_t k0 = m.row_ptr[row];
-        const int32_t k1 = m.row_ptr[row + 1];
-        const double s =
-            lane_group_sum<W>(row_partial<V, W>(m.col, vals, x, k0, k1, lane));
-        if (lane == 0) {
-            const V out = epilogue<V>(s, epi);
-            y[row] = out;
-            if (DOT)
-                dacc = fma((double)((const V *)m.w)[row], (double)out, dacc);
+    const int32_t count = t.count;
+    // prefetch: lane wl holds row i_p*G + wave*GPW + (wl % GPW)
+    const int32_t jp = (wl / GPW) * G + wave * GPW + (wl % GPW);
+    int32_t pr = 0, pk0 = 0, pk1 = 0;
+    if (jp < count) {
+        pr = tile_row(m, t, jp);
+        pk0 = m.row_ptr[pr];
+        pk1 = m.row_ptr[pr + 1];
+    }
+    const int32_t g0 = wave * GPW;
+    const int32_t iters = (count > g0) ? (count - g0 + G - 1) / G : 0;
+    for (int32_t i = 0; i < iters; ++i) {
+        const int src = i * GPW + q;
+        const int32_t row = __shfl(pr, src, 64);
+        const int32_t k0 = __shfl(pk0, src, 64);
+        const int32_t k1 = __shfl(pk1, src, 64);
+        if (g + i * G < count) {
+            const double s = lane_group_sum<W>(
+                row_partial<V, W, VecOf<V, W>::value, kUnroll>(m.col, vals, x,
+                                                                k0, k1, lane));
+            if (lane == 0) {
+                const V out = epilogue<V>(s, epi);
+                y[row] = out;
+                if (DOT)
+                    dacc = fma((double)((const V *)m.w)[row], (double)out, dacc);
+            }
         }
     }
 }
@@ -147,11 +275,13 @@ __device__ __forceinline__ void rows_by_block(const MatDesc &m, const Tile &t,
     const V *x = (const V *)m.x;
     V *y = (V *)m.y;
     for (int j = 0; j < t.count; ++j) {
-        const int32_t row = m.bin_rows[t.first + j];
+        const int32_t row = tile_row(m, t, j);
         const int32_t k0 = m.row_ptr[row];
         const int32_t k1 = m.row_ptr[row + 1];
         const double s = block_sum<kWaves>(
-            row_partial<V, kBlock>(m.col, vals, x, k0, k1, threadIdx.x), lds);
+            row_partial<V, kBlock, VecOf<V, kBlock>::value, kUnroll>(
+                m.col, vals, x, k0, k1, threadIdx.x),
+            lds);
         if (threadIdx.x == 0) {
             const V out = epilogue<V>(s, epi);
             y[row] = out;
@@ -170,8 +300,8 @@ __device__ __forceinline__ void split_chunk(const MatDesc &m, const Tile &t,
     const int32_t k0 = m.c_k0[c];
     const int32_t k1 = m.c_k1[c];
     const double s = block_sum<kWaves>(
-        row_partial<V, kBlock>(m.col, (const V *)m.vals, (const V *)m.x, k0,
-                               k1, threadIdx.x),
+        row_partial<V, kBlock, VecOf<V, kBlock>::value, kUnroll>(
+            m.col, (const V *)m.vals, (const V *)m.x, k0, k1, threadIdx.x),
         lds);
     if (threadIdx.x == 0)
         m.chunk_part[c] = s;
@@ -190,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
     for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
         const Tile t = tiles[ti];
         const MatDesc m = GROUPED ? mats[t.mat] : single;
-        switch (t.cls) {
+        switch (t.cls & kTileClassMask) {
         case C_W1: rows_by_lanes<V, 1, DOT>(m, t, epi, dacc); break;
         case C_W2: rows_by_lanes<V, 2, DOT>(m, t, epi, dacc); break;
         case C_W4: rows_by_lanes<V, 4, DOT>(m, t, epi, dacc); break;

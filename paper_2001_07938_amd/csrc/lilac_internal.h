@@ -29,6 +29,10 @@ constexpr int kDotParts = 1024;   // partials of a standalone dot
 
 // One unit of work of a product: `count` rows of class `cls`, taken from the
 // class-ordered row list at `first` (for C_SPLIT: chunk index `first`).
+// When the tile's rows are consecutive matrix rows, cls carries
+// kTileContig and `first` is the first row itself.
+constexpr int32_t kTileClassMask = 0xFF;
+constexpr int32_t kTileContig = 0x100;
 struct Tile {
     int32_t cls;
     int32_t mat;

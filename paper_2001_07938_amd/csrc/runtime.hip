@@ -237,9 +237,11 @@ static void check_plan(const Plan &p)
             fail(LILAC_ERR_ARG, "class bounds must be non-decreasing");
     if (p.upper[0] < 0)
         fail(LILAC_ERR_ARG, "class bounds must be >= 0");
+    static const int lanes[NCLASS] = {1, 2, 4, 8, 16, 32, 64, 64, 1};
     for (int c = 0; c < NCLASS; ++c)
-        if (p.rpg[c] < 1 || p.rpg[c] > 64)
-            fail(LILAC_ERR_ARG, "rows per group must be in [1, 64]");
+        if (p.rpg[c] < 1 || p.rpg[c] > lanes[c])
+            fail(LILAC_ERR_ARG, "rows per group must be in [1, lanes of the class]"
+                                " (one for the single-lane and split classes)");
     if (p.chunk < 256 || p.chunk > (1 << 24))
         fail(LILAC_ERR_ARG, "chunk must be in [256, 2^24]");
     if (p.grid_per_cu < 1 || p.grid_per_cu > 32)
@@ -291,6 +293,7 @@ static void analyse(CsrHandle &h, hipStream_t s)
     Context &c = ctx();
     h.bin_off.assign(NCLASS + 1, 0);
     std::vector<Tile> tiles;
+    std::vector<int32_t> host_rows;
     if (h.rows > 0) {
         Thresholds th;
         for (int k = 0; k < NCLASS; ++k)
@@ -305,6 +308,10 @@ static void analyse(CsrHandle &h, hipStream_t s)
             launch_bin_scatter(h.rows, h.d_row_ptr, th, hist, nblk, h.d_bin_rows, s);
             std::vector<int32_t> hh(nh);
             HIPC(hipMemcpyAsync(hh.data(), hist, nh * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+            host_rows.resize(h.rows);
+            HIPC(hipMemcpyAsync(host_rows.data(), h.d_bin_rows,
+                                (size_t)h.rows * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
             for (int k = 0; k < NCLASS; ++k)
@@ -343,8 +350,15 @@ static void analyse(CsrHandle &h, hipStream_t s)
             const int32_t a = h.bin_off[cls], e = h.bin_off[cls + 1];
             const int32_t groups = (cls == C_WG) ? 1 : kBlock / kLanes[cls];
             const int32_t per = groups * h.plan.rpg[cls];
-            for (int32_t r = a; r < e; r += per)
-                tiles.push_back(Tile{cls, 0, r, std::min(per, e - r)});
+            for (int32_t r = a; r < e; r += per) {
+                const int32_t cnt = std::min(per, e - r);
+                // rows listed in ascending order: consecutive iff the span
+                // equals the count
+                if (host_rows[r + cnt - 1] - host_rows[r] == cnt - 1)
+                    tiles.push_back(Tile{cls | kTileContig, 0, host_rows[r], cnt});
+                else
+                    tiles.push_back(Tile{cls, 0, r, cnt});
+            }
         }
     }
     h.ntiles = (int32_t)tiles.size();
@@ -1044,7 +1058,7 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
         for (int cls = C_SPLIT; cls >= C_W1; --cls)
             for (int j = 0; j < count; ++j)
                 for (const Tile &t : g_extra[g->hs[j]].tiles)
-                    if (t.cls == cls) {
+                    if ((t.cls & kTileClassMask) == cls) {
                         Tile u = t;
                         u.mat = j;
                         tiles.push_back(u);
