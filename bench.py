@@ -217,13 +217,59 @@ def run_batched(args, torch, L, gen):
             "GBps_single_calls": round(total_b / (ms_s * 1e-3) / 1e9, 1)}
 
 
+def run_serve(args, torch, L, gen):
+    """Poisson request stream over a pool of 64 resident float64 matrices
+    (4 of the CG type, 60 of the batched type) plus 16 more that have to be
+    uploaded on demand; 80% SpMV / 20% 50-iteration CG (CG only on the SPD
+    matrices); lambda swept; the same trace also run through the plain
+    one-request-at-a-time path at the lower rates."""
+    pool = [gen.spd_random(seed=gen.BASE_SEED + 50 + i) for i in range(4)]
+    specs = gen.batch_specs(76, seed=gen.BASE_SEED + 60)
+    pool += [sp.build() for sp in specs]
+    spd = np.array([True] * 4 + [sp.kind != "rand" for sp in specs])
+    n_pool, n_extra = 64, len(pool) - 64
+
+    def trace(lam, n_req, seed):
+        tr = gen.poisson_trace(lam, n_req, pool_size=n_pool, seed=seed)
+        m = tr.matrix.copy()
+        new = m >= n_pool
+        m[new] = n_pool + (m[new] - n_pool) % n_extra
+        kind = np.where(spd[m], tr.kind, 0)
+        return tr.arrival_ns, kind, m
+
+    out = {"workload": "serve_pool64", "cg_iters": 50, "points": []}
+    for fifo in (False, True):
+        S = L.Server(fifo=fifo)
+        for A in pool:
+            S.add_matrix(A)
+        # warm-up: touch every pool matrix once
+        a, k, m = trace(2000.0, 200, 1)
+        S.run_trace(a, np.zeros_like(k), np.arange(200) % n_pool, 50)
+        lams = (1000, 2000, 5000, 10000, 20000, 50000) if not fifo else (1000, 5000)
+        for lam in lams:
+            n_req = int(min(max(lam * 1.0, 500), 6000))
+            a, k, m = trace(float(lam), n_req, 100 + lam)
+            st = S.run_trace(a, k, m, 50)
+            pt = {"lambda": lam, "mode": "fifo" if fifo else "batched",
+                  "requests": st["completed"], "p50_ms": round(st["p50_us"] / 1e3, 3),
+                  "p99_ms": round(st["p99_us"] / 1e3, 3),
+                  "req_per_s": round(st["req_per_s"], 1),
+                  "solves_per_s": round(st["solves_per_s"], 1),
+                  "GBps": round(st["gbytes_per_s"], 1), "uploads": st["uploads"],
+                  "evictions": st["evictions"], "ticks": st["ticks"]}
+            log(f"[serve] {pt}")
+            out["points"].append(pt)
+        S.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cg",
-                    choices=["cg", "spmv16", "pagerank", "batched", "all"])
+                    choices=["cg", "spmv16", "pagerank", "batched", "serve", "all"])
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -241,14 +287,14 @@ def main():
         res = run_cg(args, torch, L, gen)
     else:
         fn = {"spmv16": run_spmv16, "pagerank": run_pagerank,
-              "batched": run_batched}[args.workload]
+              "batched": run_batched, "serve": run_serve}[args.workload]
         extra = fn(args, torch, L, gen)
         res = run_cg(args, torch, L, gen, extras_only=True)
         res["extras"] = {args.workload: extra}
     if args.workload == "all":
         res["extras"] = {}
         for name, fn in (("spmv16", run_spmv16), ("pagerank", run_pagerank),
-                         ("batched", run_batched)):
+                         ("batched", run_batched), ("serve", run_serve)):
             log(f"[{name}] ...")
             res["extras"][name] = fn(args, torch, L, gen)
     out = {

@@ -234,6 +234,81 @@ int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
  */
 int lilac_csr_tune(lilac_csr_t h, double *best_us);
 
+/* ---- request server (continuous batching) ----------------------------- */
+/*
+ * A server keeps a pool of matrices resident on the device and runs SpMV and
+ * CG-solve requests as they arrive: a scheduler thread admits requests whose
+ * matrix is resident while request slots and the HBM budget allow, and
+ * advances all admitted requests together, one grouped product plus one CG
+ * iteration per request per step, so requests that arrive while others run
+ * join the next step.  Matrices not resident are uploaded by a second thread
+ * (overlapping the steps); idle ones are evicted least recently used first
+ * when the pool or the budget is full.  A request's result does not depend
+ * on what it was batched with.  This is the persistent-state, upload-once
+ * marshaling of the paper (section "LiLAC-How", "Data Marshaling") applied
+ * to a stream of independent calls.  Thread-safe.
+ */
+typedef struct lilac_server_s *lilac_server_t;
+
+typedef struct {
+    int64_t hbm_budget;  /* device bytes for matrices + request state; <= 0: 200 GiB */
+    int max_active;      /* requests admitted at once (slots); <= 0: 256 */
+    int pool_capacity;   /* resident matrices before eviction; <= 0: 64 */
+    int fifo;            /* 1: no batching, one request at a time with the
+                            single-matrix calls (the plain path, for comparison) */
+} lilac_server_config;
+
+#define LILAC_REQ_SPMV 0
+#define LILAC_REQ_CG 1
+
+typedef struct {
+    int kind;            /* LILAC_REQ_SPMV or LILAC_REQ_CG */
+    int matrix;          /* id from lilac_server_add_matrix */
+    int iters;           /* CG iterations (CG only) */
+    const double *in;    /* device: x (SpMV, cols entries) or b (CG, rows) */
+    double *out;         /* device: y (SpMV, rows entries) or x (CG, rows) */
+    int64_t arrival_ns;  /* arrival time on lilac_server_now's clock; 0 = now */
+} lilac_request;
+
+typedef struct {
+    int64_t completed, spmv_done, cg_done, failed;
+    double p50_us, p99_us, mean_us, max_us;  /* arrival -> completion */
+    double wall_s;       /* first arrival -> last completion */
+    double req_per_s, solves_per_s;
+    double gbytes_per_s; /* credited algorithmic bytes of the work done / wall */
+    int64_t uploads, evictions, ticks, peak_device_bytes;
+} lilac_server_stats;
+
+int lilac_server_create(lilac_server_t *s, const lilac_server_config *cfg);
+/* Registers a float64 CSR matrix by its host arrays, which the caller keeps
+ * valid and unchanged until lilac_server_destroy; it is uploaded when a
+ * request first needs it.  cols < 0 means cols = rows.  Must be called
+ * before the first request is submitted. */
+int lilac_server_add_matrix(lilac_server_t s, int rows, int cols, int64_t nnz,
+                            const int *row_ptr, const int *col_idx,
+                            const double *vals, int *id);
+/* Queues a request (non-blocking); the device vectors must stay valid until
+ * it completes.  ticket (may be NULL) identifies it. */
+int lilac_server_submit(lilac_server_t s, const lilac_request *r,
+                        uint64_t *ticket);
+/* done: 0 pending, 1 completed, -1 failed (e.g. matrix beyond the budget). */
+int lilac_server_poll(lilac_server_t s, uint64_t ticket, int *done);
+/* Blocks until the request completed; LILAC_ERR_STATE if it failed. */
+int lilac_server_wait(lilac_server_t s, uint64_t ticket);
+int lilac_server_now(lilac_server_t s, int64_t *ns);
+/* Latency and throughput of the requests completed since the last reset. */
+int lilac_server_stats_get(lilac_server_t s, lilac_server_stats *out);
+int lilac_server_reset_stats(lilac_server_t s);
+/* Open-loop replay: request i (kind[i], matrix[i]) arrives arrival_ns[i]
+ * after the start; CG requests run cg_iters iterations.  Operands are the
+ * server's own per-matrix vectors (x = b = 1).  Blocks until every request
+ * completed, then fills *out. */
+int lilac_server_run_trace(lilac_server_t s, int n, const int64_t *arrival_ns,
+                           const int *kind, const int *matrix, int cg_iters,
+                           lilac_server_stats *out);
+/* Finishes the requests already running, fails the queued ones, frees all. */
+int lilac_server_destroy(lilac_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

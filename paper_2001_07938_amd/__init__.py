@@ -325,3 +325,114 @@ class Csr:
                 self.handle = None
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ request server
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("max_active", ctypes.c_int),
+                ("pool_capacity", ctypes.c_int), ("fifo", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("matrix", ctypes.c_int),
+                ("iters", ctypes.c_int), ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("arrival_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("spmv_done", ctypes.c_int64),
+                ("cg_done", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("req_per_s", ctypes.c_double),
+                ("solves_per_s", ctypes.c_double),
+                ("gbytes_per_s", ctypes.c_double), ("uploads", ctypes.c_int64),
+                ("evictions", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("peak_device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+REQ_SPMV, REQ_CG = 0, 1
+
+_SIGS.update({
+    "lilac_server_create": ([_P, ctypes.POINTER(ServerConfig)], _I),
+    "lilac_server_add_matrix": ([_P, _I, _I, _I64, _P, _P, _P, ctypes.POINTER(_I)], _I),
+    "lilac_server_submit": ([_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _I),
+    "lilac_server_poll": ([_P, ctypes.c_uint64, ctypes.POINTER(_I)], _I),
+    "lilac_server_wait": ([_P, ctypes.c_uint64], _I),
+    "lilac_server_now": ([_P, ctypes.POINTER(_I64)], _I),
+    "lilac_server_stats_get": ([_P, ctypes.POINTER(ServerStats)], _I),
+    "lilac_server_reset_stats": ([_P], _I),
+    "lilac_server_run_trace": ([_P, _I, _P, _P, _P, _I, ctypes.POINTER(ServerStats)], _I),
+    "lilac_server_destroy": ([_P], _I),
+})
+for _name in [n for n in _SIGS if n.startswith("lilac_server_")]:
+    _f = getattr(lib(), _name)
+    _f.argtypes, _f.restype = _SIGS[_name]
+
+
+class Server:
+    """lilac_server_* wrapper.  Host matrices passed to add_matrix are kept
+    alive by this object."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 0,
+                 pool_capacity: int = 0, fifo: bool = False):
+        cfg = ServerConfig(hbm_budget, max_active, pool_capacity, int(fifo))
+        h = ctypes.c_void_p()
+        _check(lib().lilac_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self.handle = h.value
+        self._keep = []
+
+    def add_matrix(self, A) -> int:
+        rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+        v = np.ascontiguousarray(A.vals, dtype=np.float64)
+        self._keep.append((rp, ci, v))
+        mid = ctypes.c_int(-1)
+        _check(lib().lilac_server_add_matrix(self.handle, rp.size - 1, A.cols,
+                                             ci.size, _ptr(rp), _ptr(ci), _ptr(v),
+                                             ctypes.byref(mid)))
+        return mid.value
+
+    def submit(self, kind: int, matrix: int, inp, out, iters: int = 0,
+               arrival_ns: int = 0) -> int:
+        r = Request(kind, matrix, iters, _ptr(inp), _ptr(out), arrival_ns)
+        t = ctypes.c_uint64(0)
+        _check(lib().lilac_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        d = ctypes.c_int(0)
+        _check(lib().lilac_server_poll(self.handle, ticket, ctypes.byref(d)))
+        return d.value
+
+    def wait(self, ticket: int):
+        _check(lib().lilac_server_wait(self.handle, ticket))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().lilac_server_stats_get(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        _check(lib().lilac_server_reset_stats(self.handle))
+
+    def run_trace(self, arrival_ns, kind, matrix, cg_iters: int) -> dict:
+        a = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+        k = np.ascontiguousarray(kind, dtype=np.int32)
+        m = np.ascontiguousarray(matrix, dtype=np.int32)
+        s = ServerStats()
+        _check(lib().lilac_server_run_trace(self.handle, a.size, _ptr(a), _ptr(k),
+                                            _ptr(m), cg_iters, ctypes.byref(s)))
+        return s.as_dict()
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            _check(lib().lilac_server_destroy(self.handle))
+            self.handle = None
+
+
+HEADER_FUNCTIONS = header_functions()

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblilac.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["kernels.hip", "runtime.hip"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip"]
 CXX_SOURCES = ["marshal.cpp"]
 
 ARCH = os.environ.get("LILAC_ARCH", "gfx950")
@@ -29,7 +29,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]
-DEVICE = [f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+DEVICE = [f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

@@ -6,6 +6,8 @@
 // butterfly, workgroups combine their four wavefronts in index order, split
 // rows add their chunk sums in chunk order), so a given matrix and plan
 // always give bitwise identical results, whatever else runs on the GPU.
+#include <algorithm>
+
 #include "lilac_internal.h"
 
 namespace lilac {
@@ -367,6 +369,155 @@ __global__ __launch_bounds__(kBlock) void k_split_finalize(
         if (threadIdx.x == 0)
             dot_part[blockIdx.x] = tot;
     }
+}
+
+// Several matrices in one launch, each with its own tile list; workgroup b
+// takes virtual tiles b, b+grid, ...; virtual tile v is tile v - prefix[j]
+// of matrix j (binary search over the prefix).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_spmv_segments(
+    const MatDesc *__restrict__ mats, const int32_t *__restrict__ prefix,
+    int32_t nseg, int32_t total)
+{
+    __shared__ double lds[kWaves];
+    const Epi epi{EPI_NONE, 0, 0.0, 0.0};
+    double dacc = 0.0;
+    for (int32_t v = blockIdx.x; v < total; v += gridDim.x) {
+        int32_t lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (prefix[mid] <= v)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const MatDesc m = mats[lo];
+        const Tile t = m.tiles[v - prefix[lo]];
+        switch (t.cls & kTileClassMask) {
+        case C_W1: rows_by_lanes<V, 1, false>(m, t, epi, dacc); break;
+        case C_W2: rows_by_lanes<V, 2, false>(m, t, epi, dacc); break;
+        case C_W4: rows_by_lanes<V, 4, false>(m, t, epi, dacc); break;
+        case C_W8: rows_by_lanes<V, 8, false>(m, t, epi, dacc); break;
+        case C_W16: rows_by_lanes<V, 16, false>(m, t, epi, dacc); break;
+        case C_W32: rows_by_lanes<V, 32, false>(m, t, epi, dacc); break;
+        case C_W64: rows_by_lanes<V, 64, false>(m, t, epi, dacc); break;
+        case C_WG: rows_by_block<V, false>(m, t, epi, dacc, lds); break;
+        default: split_chunk<V>(m, t, lds); break;
+        }
+    }
+}
+
+// ---------------------------------------------------------- batched CG
+
+// Segment of workgroup blockIdx.x (segments ordered by blk0).
+__device__ __forceinline__ int32_t cg_seg_of(const CgSeg *__restrict__ segs,
+                                             int32_t nseg)
+{
+    int32_t lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (segs[mid].blk0 <= (int32_t)blockIdx.x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Sum of part[0..n) (n <= kBlock) by one workgroup, the same in every
+// workgroup that calls it.
+__device__ __forceinline__ double sum_small(const double *__restrict__ part,
+                                            int32_t n, double *lds)
+{
+    const double v = ((int32_t)threadIdx.x < n) ? part[threadIdx.x] : 0.0;
+    return block_sum<kWaves>(v, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cgb_init(const CgSeg *__restrict__ segs,
+                                                     int32_t nseg)
+{
+    __shared__ double lds[kWaves];
+    const CgSeg sg = segs[cg_seg_of(segs, nseg)];
+    const int32_t lb = blockIdx.x - sg.blk0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
+         i += (int64_t)sg.nb * kBlock) {
+        const double bi = sg.b[i];
+        sg.x[i] = 0.0;
+        sg.r[i] = bi;
+        sg.p[i] = bi;
+        acc = fma(bi, bi, acc);
+    }
+    const double t = block_sum<kWaves>(acc, lds);
+    if (threadIdx.x == 0) {
+        sg.rr_part[lb] = t;  // parity of iteration 0
+        if (lb == 0)
+            *sg.done = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cgb_pq(const CgSeg *__restrict__ segs,
+                                                   int32_t nseg)
+{
+    __shared__ double lds[kWaves];
+    const CgSeg sg = segs[cg_seg_of(segs, nseg)];
+    const int32_t lb = blockIdx.x - sg.blk0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
+         i += (int64_t)sg.nb * kBlock)
+        acc = fma(sg.p[i], sg.q[i], acc);
+    const double t = block_sum<kWaves>(acc, lds);
+    if (threadIdx.x == 0)
+        sg.pq_part[lb] = t;
+}
+
+// alpha = rho/(p.q); x += alpha p; r -= alpha q; partial r.r for k+1.
+__global__ __launch_bounds__(kBlock) void k_cgb_update(const CgSeg *__restrict__ segs,
+                                                       int32_t nseg)
+{
+    __shared__ double lds[kWaves];
+    const CgSeg sg = segs[cg_seg_of(segs, nseg)];
+    if (*sg.done)
+        return;
+    const int32_t lb = blockIdx.x - sg.blk0;
+    const int par = sg.iter & 1;
+    const double rho = sum_small(sg.rr_part + par * sg.nb, sg.nb, lds);
+    const double pq = sum_small(sg.pq_part, sg.nb, lds);
+    if (rho == 0.0 || pq == 0.0) {
+        if (lb == 0 && threadIdx.x == 0)
+            *sg.done = 1;
+        return;
+    }
+    const double alpha = rho / pq;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
+         i += (int64_t)sg.nb * kBlock) {
+        sg.x[i] = fma(alpha, sg.p[i], sg.x[i]);
+        const double ri = fma(-alpha, sg.q[i], sg.r[i]);
+        sg.r[i] = ri;
+        acc = fma(ri, ri, acc);
+    }
+    const double t = block_sum<kWaves>(acc, lds);
+    if (threadIdx.x == 0)
+        sg.rr_part[(par ^ 1) * sg.nb + lb] = t;
+}
+
+// beta = rho'/rho; p = r + beta p.
+__global__ __launch_bounds__(kBlock) void k_cgb_xpay(const CgSeg *__restrict__ segs,
+                                                     int32_t nseg)
+{
+    __shared__ double lds[kWaves];
+    const CgSeg sg = segs[cg_seg_of(segs, nseg)];
+    if (*sg.done)
+        return;
+    const int32_t lb = blockIdx.x - sg.blk0;
+    const int par = sg.iter & 1;
+    const double rho = sum_small(sg.rr_part + par * sg.nb, sg.nb, lds);
+    const double rho_new = sum_small(sg.rr_part + (par ^ 1) * sg.nb, sg.nb, lds);
+    const double beta = rho_new / rho;
+    for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
+         i += (int64_t)sg.nb * kBlock)
+        sg.p[i] = fma(beta, sg.p[i], sg.r[i]);
 }
 
 // ---------------------------------------------------------------- analysis
@@ -852,6 +1003,56 @@ void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,
             hipLaunchKernelGGL((k_split_finalize<float, false, false>), g, b, 0, s, items, n, single, mats, epi, dot_part);
     }
     check_launch("k_split_finalize");
+}
+
+void launch_spmv_segments(lilac_dtype dt, const MatDesc *mats,
+                          const int32_t *prefix, int32_t nseg, int32_t total,
+                          int32_t grid, hipStream_t s)
+{
+    if (total <= 0 || nseg <= 0)
+        return;
+    grid = std::min(grid, total);
+    if (dt == LILAC_F64)
+        hipLaunchKernelGGL(k_spmv_segments<double>, dim3(grid), dim3(kBlock), 0, s,
+                           mats, prefix, nseg, total);
+    else
+        hipLaunchKernelGGL(k_spmv_segments<float>, dim3(grid), dim3(kBlock), 0, s,
+                           mats, prefix, nseg, total);
+    check_launch("k_spmv_segments");
+}
+
+int32_t cg_seg_blocks(int64_t n) { return grid_for(n, kBlock, kBlock); }
+
+void launch_cgb_init(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
+{
+    if (blocks <= 0)
+        return;
+    hipLaunchKernelGGL(k_cgb_init, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
+    check_launch("k_cgb_init");
+}
+
+void launch_cgb_pq(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
+{
+    if (blocks <= 0)
+        return;
+    hipLaunchKernelGGL(k_cgb_pq, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
+    check_launch("k_cgb_pq");
+}
+
+void launch_cgb_update(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
+{
+    if (blocks <= 0)
+        return;
+    hipLaunchKernelGGL(k_cgb_update, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
+    check_launch("k_cgb_update");
+}
+
+void launch_cgb_xpay(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
+{
+    if (blocks <= 0)
+        return;
+    hipLaunchKernelGGL(k_cgb_xpay, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
+    check_launch("k_cgb_xpay");
 }
 
 void launch_dot_parts(int64_t n, const double *a, const double *b,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <mutex>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -55,6 +56,9 @@ struct MatDesc {
     double *chunk_part;       // one partial sum per chunk
     int32_t split_begin;      // position of the first split row in bin_rows
     int32_t nsplit;
+    const Tile *tiles;        // the matrix's own tile list (segment launches)
+    int32_t ntiles;
+    int32_t pad;
 };
 
 enum EpiMode : int32_t { EPI_NONE = 0, EPI_PAGERANK = 1 };
@@ -169,6 +173,32 @@ void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,
                            const MatDesc &single, const MatDesc *mats,
                            const Epi &epi, double *dot_part, hipStream_t s);
 
+// Product over several matrices whose own tile lists are concatenated
+// virtually: tile v belongs to matrix j with prefix[j] <= v < prefix[j+1].
+void launch_spmv_segments(lilac_dtype dt, const MatDesc *mats,
+                          const int32_t *prefix, int32_t nseg, int32_t total,
+                          int32_t grid, hipStream_t s);
+
+// Many CG solves advanced together, one iteration per call sequence
+// (init once, then pq -> update -> xpay after each product q = A p).
+struct CgSeg {
+    const double *b;
+    double *x, *r, *p, *q;
+    double *pq_part;    // nb partial sums of p.q
+    double *rr_part;    // 2*nb partial sums of r.r (by iteration parity)
+    int32_t *done;      // set once the solve stopped (rho or p.q zero)
+    int64_t n;
+    int32_t nb;         // workgroups of this solve (fixed by n)
+    int32_t iter;       // iteration index k of this step
+    int32_t blk0;       // first workgroup of this solve in the launch
+    int32_t pad;
+};
+int32_t cg_seg_blocks(int64_t n);
+void launch_cgb_init(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
+void launch_cgb_pq(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
+void launch_cgb_update(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
+void launch_cgb_xpay(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
+
 void launch_dot_parts(int64_t n, const double *a, const double *b,
                       double *part, int32_t nparts, hipStream_t s);
 void launch_sum_parts(const double *part, int32_t nparts, double *out,
@@ -199,5 +229,21 @@ int32_t blas1_parts(int64_t n);
 // Workgroups of the tile kernel resident per compute unit.
 int occupancy_tiles(lilac_dtype dt);
 bool is_device_ptr(const void *p);
+
+// ---- runtime services shared with the request server ----------------------
+std::recursive_mutex &lib_mutex();
+void set_last_error(const std::string &msg);
+int lib_device();
+CsrHandle *create_handle(int rows, int cols, int64_t nnz, const int32_t *rp,
+                         const int32_t *col, const void *vals, lilac_dtype dt,
+                         unsigned flags);
+void destroy_handle(CsrHandle *h);
+MatDesc make_desc(const CsrHandle &h, const void *x, void *y, const void *w,
+                  double *chunk_part);
+void spmv_enqueue(const CsrHandle &h, const void *x, void *y, const Epi &epi,
+                  const void *w, bool dot, hipStream_t s);
+void run_cg(CsrHandle &h, const double *b, double *x, int iters,
+            unsigned flags, hipStream_t s, double *rho_out, int *iters_done);
+int tile_grid(lilac_dtype dt);   // persistent workgroups for a grouped launch
 
 }  // namespace lilac

@@ -29,6 +29,8 @@ namespace lilac {
 
 static thread_local std::string g_last_error;
 
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
 void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
 void hip_check(hipError_t e, const char *what, const char *file, int line)
@@ -68,6 +70,7 @@ struct Context {
 };
 
 static std::recursive_mutex g_mu;
+std::recursive_mutex &lib_mutex() { return g_mu; }
 static Context *g_ctx = nullptr;
 static bool g_exit_registered = false;
 
@@ -145,6 +148,7 @@ static Context &ctx()
 }
 
 int device_cu_count() { return ctx().cu; }
+int lib_device() { return ctx().device; }
 
 void *dev_alloc(size_t bytes)
 {
@@ -427,9 +431,9 @@ static void construct(CsrHandle &h, int cols_given, const int32_t *rp,
     h.dirty_struct = h.dirty_vals = false;
 }
 
-static void destroy_handle(CsrHandle *h);
+void destroy_handle(CsrHandle *h);
 
-static CsrHandle *create_handle(int rows, int cols, int64_t nnz,
+CsrHandle *create_handle(int rows, int cols, int64_t nnz,
                                 const int32_t *rp, const int32_t *col,
                                 const void *vals, lilac_dtype dt,
                                 unsigned flags)
@@ -515,7 +519,7 @@ static void drop_graphs(CsrHandle &h)
     }
 }
 
-static void destroy_handle(CsrHandle *h)
+void destroy_handle(CsrHandle *h)
 {
     if (!h)
         return;
@@ -562,7 +566,7 @@ static void refresh(CsrHandle &h, hipStream_t s)
 
 // ================================================================ products
 
-static MatDesc make_desc(const CsrHandle &h, const void *x, void *y,
+MatDesc make_desc(const CsrHandle &h, const void *x, void *y,
                          const void *w, double *chunk_part)
 {
     MatDesc d;
@@ -579,10 +583,13 @@ static MatDesc make_desc(const CsrHandle &h, const void *x, void *y,
     d.chunk_part = chunk_part;
     d.split_begin = h.bin_off.empty() ? 0 : h.bin_off[C_SPLIT];
     d.nsplit = h.nsplit;
+    d.tiles = h.d_tiles;
+    d.ntiles = h.ntiles;
+    d.pad = 0;
     return d;
 }
 
-static void spmv_enqueue(const CsrHandle &h, const void *x, void *y,
+void spmv_enqueue(const CsrHandle &h, const void *x, void *y,
                          const Epi &epi, const void *w, bool dot,
                          hipStream_t s)
 {
@@ -597,6 +604,11 @@ static void spmv_enqueue(const CsrHandle &h, const void *x, void *y,
 }
 
 static Epi epi_none() { return Epi{EPI_NONE, 0, 0.0, 0.0}; }
+
+int tile_grid(lilac_dtype dt)
+{
+    return ctx().cu * std::max(1, std::min(8, tile_occupancy(dt)));
+}
 
 // Workgroups of the tile kernel that fit on one CU at once.
 static int tile_occupancy(lilac_dtype dt)
@@ -865,7 +877,7 @@ static void capture(hipGraph_t &graph, hipGraphExec_t &exec, Enq enq)
     }
 }
 
-static void run_cg(CsrHandle &h, const double *b, double *x, int iters,
+void run_cg(CsrHandle &h, const double *b, double *x, int iters,
                    unsigned flags, hipStream_t s, double *rho_out,
                    int *iters_done)
 {

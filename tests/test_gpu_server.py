@@ -1,0 +1,134 @@
+"""The request server on the GPU: results are the same alone and in the mix
+(bitwise), agree with the oracle, and admission, eviction, failure and the
+trace replay behave."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2001_07938_amd as L
+from tests.helpers import TOL_F64, check_spmv
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _workload():
+    spd = [gen.spd_random(6000, 30, seed=1), gen.stencil(16, 7), gen.stencil(10, 27)]
+    other = [gen.random_rows(9000, 5, 60, seed=2),
+             gen.ragged(2500, 30000, seed=3, long_rows=2, long_len=20000)]
+    return spd, other
+
+
+def _requests(spd, other, ids_spd, ids_other, iters=30):
+    reqs = []
+    for A, mid in zip(spd + other, ids_spd + ids_other):
+        x = gen.vector(A.cols, 100 + mid)
+        reqs.append((L.REQ_SPMV, mid, A, x))
+    for A, mid in zip(spd, ids_spd):
+        b = gen.vector(A.rows, 200 + mid)
+        reqs.append((L.REQ_CG, mid, A, b))
+    return reqs
+
+
+def _run(S, reqs, iters, together):
+    outs, tickets = [], []
+    ins = [_dev(v) for (_, _, _, v) in reqs]
+    for (kind, mid, A, v), vin in zip(reqs, ins):
+        out = torch.full((A.rows,), np.nan, dtype=torch.float64, device=DEV)
+        torch.cuda.synchronize()
+        t = S.submit(kind, mid, vin, out, iters=iters)
+        if not together:
+            S.wait(t)
+        outs.append(out)
+        tickets.append(t)
+    for t in tickets:
+        S.wait(t)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+def test_alone_equals_mix_and_oracle():
+    spd, other = _workload()
+    S = L.Server()
+    ids_spd = [S.add_matrix(A) for A in spd]
+    ids_other = [S.add_matrix(A) for A in other]
+    iters = 30
+    reqs = _requests(spd, other, ids_spd, ids_other, iters)
+    alone = _run(S, reqs, iters, together=False)
+    mix = _run(S, reqs, iters, together=True)
+    mix2 = _run(S, reqs[::-1], iters, together=True)[::-1]
+    for a, m, m2 in zip(alone, mix, mix2):
+        assert np.array_equal(a, m) and np.array_equal(a, m2)
+    for (kind, mid, A, v), y in zip(reqs, alone):
+        if kind == L.REQ_SPMV:
+            check_spmv(A, v, y, TOL_F64)
+        else:
+            x_or, _, _ = oracle.cg(A.row_ptr, A.col_idx, A.vals, v, iters)
+            assert np.max(np.abs(y - x_or)) <= 1e-10 * np.max(np.abs(x_or))
+    st = S.stats()
+    assert st["completed"] == 3 * len(reqs) and st["failed"] == 0
+    assert st["p99_us"] >= st["p50_us"] > 0
+    S.destroy()
+
+
+def test_eviction_keeps_results():
+    spd, other = _workload()
+    S = L.Server(pool_capacity=2)
+    ids = [S.add_matrix(A) for A in spd + other]
+    reqs = [(L.REQ_SPMV, mid, A, gen.vector(A.cols, 300 + mid))
+            for A, mid in zip(spd + other, ids)] * 2
+    ys = _run(S, reqs, 1, together=True)
+    for (kind, mid, A, v), y in zip(reqs, ys):
+        check_spmv(A, v, y, TOL_F64)
+    assert S.stats()["evictions"] > 0
+    S.destroy()
+
+
+def test_budget_too_small_fails_cleanly():
+    A = gen.spd_random(20000, 40, seed=5)
+    S = L.Server(hbm_budget=1 << 20)
+    mid = S.add_matrix(A)
+    x = _dev(gen.vector(A.cols, 6))
+    y = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    t = S.submit(L.REQ_SPMV, mid, x, y)
+    with pytest.raises(L.LilacError):
+        S.wait(t)
+    assert S.poll(t) == -1
+    S.destroy()
+
+
+def test_fifo_mode_matches_oracle():
+    spd, other = _workload()
+    S = L.Server(fifo=True)
+    ids_spd = [S.add_matrix(A) for A in spd]
+    ids_other = [S.add_matrix(A) for A in other]
+    iters = 20
+    reqs = _requests(spd, other, ids_spd, ids_other, iters)
+    ys = _run(S, reqs, iters, together=True)
+    for (kind, mid, A, v), y in zip(reqs, ys):
+        if kind == L.REQ_SPMV:
+            check_spmv(A, v, y, TOL_F64)
+        else:
+            x_or, _, _ = oracle.cg(A.row_ptr, A.col_idx, A.vals, v, iters)
+            assert np.max(np.abs(y - x_or)) <= 1e-10 * np.max(np.abs(x_or))
+    S.destroy()
+
+
+def test_trace_replay_small():
+    spd, other = _workload()
+    S = L.Server()
+    ids = [S.add_matrix(A) for A in spd + other]
+    tr = gen.poisson_trace(2000.0, 400, pool_size=len(ids), seed=9)
+    mats = np.array(ids)[tr.matrix % len(ids)]
+    kind = np.where(np.isin(mats, ids[:3]), tr.kind, 0)  # CG only on SPD ones
+    st = S.run_trace(tr.arrival_ns, kind, mats, 10)
+    assert st["completed"] == 400 and st["failed"] == 0
+    assert st["cg_done"] == int(kind.sum())
+    assert st["p99_us"] >= st["p50_us"] > 0 and st["req_per_s"] > 0
+    S.destroy()
