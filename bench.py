@@ -104,6 +104,13 @@ def run_cg(args, torch, L, gen, extras_only=False):
         h.spmv(p, q)
     ms = time_events(lambda: h.spmv(p, q), max(20, args.steps * 10), stream)
     achieved = kb / (ms * 1e-3) / 1e9
+    # calibration for hardware byte counters: a plain copy of known size
+    # (256 MiB read + 256 MiB written) run in the same process
+    ca = torch.empty(32 << 20, dtype=torch.float64, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    del ca, cb
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s",
         "ms_per_step": round(dt * 1e3, 4),
