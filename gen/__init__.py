@@ -343,3 +343,36 @@ def poisson_trace(lam: float, n_req: int, pool_size: int = 64,
     mat = rng.integers(0, pool_size, n_req).astype(np.int32)
     mat[new] = pool_size + np.arange(int(new.sum()), dtype=np.int32)
     return Trace(arrival, kind, mat, cg_iters)
+
+
+@dataclasses.dataclass
+class Jds:
+    rows: int
+    cols: int
+    max_len: int
+    perm: np.ndarray     # int32 [rows]: position of original row i
+    nzcnt: np.ndarray    # int32 [rows]: entries of the row at position p
+    jd_ptr: np.ndarray   # int32 [max_len+1]
+    jd_col: np.ndarray   # int32 [nnz]
+    jd_val: np.ndarray   # float64 [nnz]
+
+
+def random_jds(rows: int, cols: int, max_len: int, seed: int,
+               empty_frac: float = 0.1) -> Jds:
+    """A random matrix drawn directly in Jagged Diagonal Storage: row
+    lengths (a tenth empty by default) sorted in decreasing order, a random
+    row permutation, and diagonal j listing the j-th entry of every row with
+    more than j entries (random columns, values U[-1,1))."""
+    rng = _rng(seed)
+    lens = rng.integers(0, max_len + 1, rows)
+    lens[rng.random(rows) < empty_frac] = 0
+    nzcnt = np.sort(lens)[::-1].astype(np.int32)
+    perm = rng.permutation(rows).astype(np.int32)
+    ml = int(nzcnt.max()) if rows else 0
+    per_diag = np.array([int(np.sum(nzcnt > j)) for j in range(ml)], dtype=np.int64)
+    jd_ptr = np.zeros(ml + 1, dtype=np.int64)
+    np.cumsum(per_diag, out=jd_ptr[1:])
+    nnz = int(jd_ptr[-1])
+    return Jds(rows, cols, ml, perm, nzcnt, jd_ptr.astype(np.int32),
+               rng.integers(0, cols, nnz).astype(np.int32),
+               rng.uniform(-1.0, 1.0, nnz))

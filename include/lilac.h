@@ -145,6 +145,8 @@ typedef struct {
     int chunk;              /* non-zeros per chunk of a split row */
     int64_t nchunks;        /* entries of the chunk table */
     int ntiles;             /* work tiles of one product */
+    int layout;             /* LILAC_LAYOUT_ROWS or LILAC_LAYOUT_PANELS in use */
+    int npanels;            /* column panels (panel layout), else 0 */
 } lilac_csr_info_t;
 int lilac_csr_info(lilac_csr_t h, lilac_csr_info_t *out);
 
@@ -168,6 +170,22 @@ int lilac_csr_analysis(lilac_csr_t h, int *bin_off, int *bin_rows, int *c_row,
  */
 int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
                        const int *rows_per_group /* [9] */, int chunk);
+
+/*
+ * Device layout used by the product.  LILAC_LAYOUT_ROWS: the CSR arrays with
+ * the row-class tiles above.  LILAC_LAYOUT_PANELS: a second, column-panel
+ * copy of the matrix in which the columns are cut into panels that fit the
+ * LDS and the rows into blocks; each workgroup stages one panel of x in LDS
+ * at a time and gathers from there, with 16-bit column offsets.  It suits
+ * matrices with many entries per row and panel (scattered columns); for
+ * other matrices it is not built.  LILAC_LAYOUT_AUTO (the default) picks it
+ * when the matrix has at least 8 entries per row and panel on average, at
+ * most 64 panels and no row longer than 1024.  Re-runs the analysis.
+ */
+#define LILAC_LAYOUT_AUTO (-1)
+#define LILAC_LAYOUT_ROWS 0
+#define LILAC_LAYOUT_PANELS 1
+int lilac_csr_set_layout(lilac_csr_t h, int layout);
 
 /*
  * y = A x with x (cols entries) and y (rows entries) in device memory, of the
@@ -233,6 +251,36 @@ int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
  * time of one product with the chosen plan.
  */
 int lilac_csr_tune(lilac_csr_t h, double *best_us);
+
+/* ---- second format and graph traversal -------------------------------- */
+/*
+ * y = A x with A in Jagged Diagonal Storage (section "Sparse Matrix
+ * Variations in LiLAC-What", JDS paragraph and the JDS figure): rows are
+ * ordered by decreasing non-zero count, perm[i] is the position of original
+ * row i in that order, nzcnt[p] the count of the row at position p, diagonal
+ * j (j < max_len) holds the j-th entry of every row that has one, in
+ * position order, starting at jd_ptr[j]; jd_ptr has max_len+1 entries and
+ * jd_ptr[max_len] is the number of entries.  Each row's sum is taken in
+ * diagonal order without fused multiply-add, so y equals the sequential
+ * definition bitwise.  Pointers host or device; host arrays are copied for
+ * the call (JDS inputs are not cached).  Blocking.  Errors: LILAC_ERR_ARG,
+ * LILAC_ERR_CSR (negative column index).
+ */
+int lilac_spmv_jds(int rows, int max_len, const int *perm, const int *nzcnt,
+                   const int *jd_ptr, const int *jd_col, const double *jd_val,
+                   const double *x, double *y);
+
+/*
+ * Breadth-first search levels from `source` by repeated Boolean sparse
+ * products over the handle's pull-direction CSR (row v lists the sources u
+ * of edges u -> v), the SpMV-based BFS graph kernel of the paper's
+ * evaluation (section "Results", graph kernels): level[v] = 0 for the
+ * source, depth+1 for a vertex first reached from a vertex of level depth,
+ * -1 if unreachable.  level is a device int array of rows entries; nlevels
+ * (host, may be NULL) receives the number of levels.  Needs cols <= rows.
+ * Blocking (one host check per level).
+ */
+int lilac_bfs(lilac_csr_t h, int source, int *level, int *nlevels, void *stream);
 
 /* ---- request server (continuous batching) ----------------------------- */
 /*

@@ -4,8 +4,8 @@ Argument marshalling only: every computation runs in the library's HIP
 kernels.  The names follow the C ABI in ``include/lilac.h``.  PyTorch is
 imported first so that the library shares torch's HIP runtime; torch tensors
 (host or device) and numpy arrays are accepted wherever the C ABI takes a
-pointer.  If the library has not been built this module fails to import
-(there is no fallback).
+pointer.  The library is loaded on first use; if it has not been built that
+first call raises ImportError (there is no fallback).
 """
 from __future__ import annotations
 
@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_HERE, "liblilac.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "lilac.h")
 
 F64, F32 = 0, 1
+LAYOUT_AUTO, LAYOUT_ROWS, LAYOUT_PANELS = -1, 0, 1
 KEEP_HOST = 1
 CG_GRAPH = 1
 NCLASS = 9
@@ -49,7 +50,8 @@ class CsrInfo(ctypes.Structure):
                 ("dtype", ctypes.c_int), ("nbins", ctypes.c_int),
                 ("bin_upper", ctypes.c_int * 16), ("bin_count", ctypes.c_int * 16),
                 ("chunk", ctypes.c_int), ("nchunks", ctypes.c_int64),
-                ("ntiles", ctypes.c_int)]
+                ("ntiles", ctypes.c_int), ("layout", ctypes.c_int),
+                ("npanels", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -73,6 +75,7 @@ _SIGS = {
     "lilac_csr_info": ([_P, ctypes.POINTER(CsrInfo)], _I),
     "lilac_csr_analysis": ([_P, _P, _P, _P, _P, _P], _I),
     "lilac_csr_set_plan": ([_P, _P, _P, _I], _I),
+    "lilac_csr_set_layout": ([_P, _I], _I),
     "lilac_spmv": ([_P, _P, _P, _P], _I),
     "lilac_spmv_dot": ([_P, _P, _P, _P, _P, _P], _I),
     "lilac_dot_dev": ([_I64, _P, _P, _P, _P], _I),
@@ -80,6 +83,8 @@ _SIGS = {
     "lilac_pagerank": ([_P, ctypes.c_float, _I, _P, _P], _I),
     "lilac_spmv_batched": ([_I, _P, _P, _P, _P], _I),
     "lilac_csr_tune": ([_P, _P], _I),
+    "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
+    "lilac_spmv_jds": ([_I, _I, _P, _P, _P, _P, _P, _P, _P], _I),
 }
 
 _lib = None
@@ -102,7 +107,6 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
-lib()  # fail at import time when the library is missing
 
 
 def header_functions() -> list:
@@ -202,6 +206,15 @@ def lilac_release_all():
     _check(lib().lilac_release_all())
 
 
+def lilac_spmv_jds(rows: int, max_len: int, perm, nzcnt, jd_ptr, jd_col,
+                   jd_val, x, y):
+    """y = A x with A in Jagged Diagonal Storage (see include/lilac.h)."""
+    _check(lib().lilac_spmv_jds(rows, max_len, _ptr(perm), _ptr(nzcnt),
+                                _ptr(jd_ptr), _ptr(jd_col), _ptr(jd_val),
+                                _ptr(x), _ptr(y)))
+    return y
+
+
 def lilac_spmv_batched(handles: Sequence["Csr"], xs, ys, stream=None):
     n = len(handles)
     H = (ctypes.c_void_p * n)(*[h.handle for h in handles])
@@ -277,6 +290,10 @@ class Csr:
             np.ascontiguousarray(rows_per_group, dtype=np.int32)
         _check(lib().lilac_csr_set_plan(self.handle, _ptr(up), _ptr(rg), chunk))
 
+    def set_layout(self, layout: int):
+        """LAYOUT_AUTO (-1), LAYOUT_ROWS (0) or LAYOUT_PANELS (1)."""
+        _check(lib().lilac_csr_set_layout(self.handle, layout))
+
     def spmv(self, x, y, stream=None):
         _check(lib().lilac_spmv(self.handle, _ptr(x), _ptr(y), _stream(stream)))
         return y
@@ -307,6 +324,13 @@ class Csr:
         _check(lib().lilac_pagerank(self.handle, float(damping), iters, _ptr(x),
                                     _stream(stream)))
         return x
+
+    def bfs(self, source: int, level, stream=None) -> int:
+        """Fills the device int32 tensor `level`; returns the level count."""
+        n = ctypes.c_int(0)
+        _check(lib().lilac_bfs(self.handle, source, _ptr(level),
+                               ctypes.addressof(n), _stream(stream)))
+        return n.value
 
     def tune(self) -> float:
         us = ctypes.c_double(0.0)
@@ -369,9 +393,6 @@ _SIGS.update({
     "lilac_server_run_trace": ([_P, _I, _P, _P, _P, _I, ctypes.POINTER(ServerStats)], _I),
     "lilac_server_destroy": ([_P], _I),
 })
-for _name in [n for n in _SIGS if n.startswith("lilac_server_")]:
-    _f = getattr(lib(), _name)
-    _f.argtypes, _f.restype = _SIGS[_name]
 
 
 class Server:

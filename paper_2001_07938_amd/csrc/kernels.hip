@@ -407,6 +407,267 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
     }
 }
 
+// ------------------------------------------------------- column panels
+
+// Product over the column-panel layout.  Workgroup b owns row block b.  For
+// each panel it stages that slice of x in LDS (coalesced 16-byte loads), then
+// every group of 16 lanes walks the panel entries of its rows, gathering x
+// from LDS; each lane keeps one running sum per row across all panels, and
+// the 16 lane sums of a row are combined once at the end.  The order of the
+// additions depends only on the matrix and the layout.
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kPanelThreads, 4) void k_spmv_panels(
+    PanelDesc pd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
+    const V *__restrict__ w, double *__restrict__ dot_part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    V *xs = (V *)smem;
+    constexpr int G = kPanelThreads / kPanelLanes;  // lane groups
+    const int g = threadIdx.x / kPanelLanes;
+    const int l = threadIdx.x % kPanelLanes;
+    const int32_t b = blockIdx.x;
+    const int32_t r0 = b * pd.rb;
+    const int32_t nr = min(pd.rb, pd.rows - r0);
+    const V *pv = (const V *)pd.vals;
+    const int32_t pw = 1 << pd.log2w;
+    double acc[kPanelRpg];
+#pragma unroll
+    for (int k = 0; k < kPanelRpg; ++k)
+        acc[k] = 0.0;
+    for (int32_t p = 0; p < pd.np; ++p) {
+        // stage x[p*pw, p*pw + width) in LDS
+        const int32_t c0 = p * pw;
+        const int32_t width = min(pw, pd.cols - c0);
+        __syncthreads();
+        constexpr int VV = 16 / sizeof(V);
+        const bool aligned = (((uintptr_t)(x + c0)) & 15) == 0;
+        const int32_t nvec = aligned ? width / VV : 0;
+        for (int32_t i = threadIdx.x; i < nvec; i += kPanelThreads) {
+            typedef V vec_t __attribute__((ext_vector_type(VV)));
+            *(vec_t *)(xs + i * VV) = *(const vec_t *)(x + c0 + i * VV);
+        }
+        for (int32_t i = nvec * VV + threadIdx.x; i < width; i += kPanelThreads)
+            xs[i] = x[c0 + i];
+        __syncthreads();
+        const int32_t *ptr = pd.ptr + (int64_t)(b * pd.np + p) * (pd.rb + 1);
+        // lane l of the group fetches the bounds of the group's row l
+        const int32_t rl = g + l * G;
+        int32_t ps = 0, pe = 0;
+        if (l < kPanelRpg && rl < nr) {
+            ps = ptr[rl];
+            pe = ptr[rl + 1];
+        }
+        // rows in two halves of eight: the first entry of each row is
+        // loaded for all eight rows before any is used
+#pragma unroll
+        for (int h0 = 0; h0 < kPanelRpg; h0 += 8) {
+            int32_t s[8], e[8];
+            V v[8];
+            uint16_t c[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                s[k] = __shfl(ps, h0 + k, kPanelLanes);
+                e[k] = __shfl(pe, h0 + k, kPanelLanes);
+                const int32_t j = s[k] + l;
+                const int32_t ja = (j < e[k]) ? j : s[k];
+                v[k] = ld_stream(pv + ja);
+                c[k] = ld_stream(pd.col + ja);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (s[k] + l < e[k])
+                    acc[h0 + k] = fma((double)v[k], (double)xs[c[k]], acc[h0 + k]);
+            // rows with more than 16 entries in this panel
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                for (int32_t j = s[k] + kPanelLanes + l; j < e[k]; j += kPanelLanes)
+                    acc[h0 + k] = fma((double)ld_stream(pv + j),
+                                      (double)xs[ld_stream(pd.col + j)], acc[h0 + k]);
+        }
+    }
+    double dacc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPanelRpg; ++k) {
+        const double sum = lane_group_sum<kPanelLanes>(acc[k]);
+        const int32_t rl = g + k * G;
+        if (l == 0 && rl < nr) {
+            const V out = epilogue<V>(sum, epi);
+            y[r0 + rl] = out;
+            if (DOT)
+                dacc = fma((double)w[r0 + rl], (double)out, dacc);
+        }
+    }
+    if (DOT) {
+        __syncthreads();  // the panel buffer is reused for the reduction
+        const double tot = block_sum<kPanelThreads / 64>(dacc, (double *)smem);
+        if (threadIdx.x == 0)
+            dot_part[blockIdx.x] = tot;
+    }
+}
+
+// Entries of each row per panel (one thread per row; cnt pre-zeroed).
+__global__ __launch_bounds__(kBlock) void k_panel_count(PanelDesc pd,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col,
+                                                        int32_t *__restrict__ cnt)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= pd.rows)
+        return;
+    const int32_t b = i / pd.rb, rl = i - b * pd.rb;
+    const int32_t a = rp[i], e = rp[i + 1];
+    for (int32_t p = 0; p < pd.np; ++p) {
+        int32_t n = 0;
+        for (int32_t k = a; k < e; ++k)
+            n += ((col[k] >> pd.log2w) == p) ? 1 : 0;
+        cnt[(int64_t)(b * pd.np + p) * (pd.rb + 1) + rl] = n;
+    }
+}
+
+// Move each row's entries to their panels (stable inside a row).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_panel_scatter(
+    PanelDesc pd, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ vals, const int32_t *__restrict__ ptr,
+    V *__restrict__ pv, uint16_t *__restrict__ pc)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= pd.rows)
+        return;
+    const int32_t b = i / pd.rb, rl = i - b * pd.rb;
+    const int32_t a = rp[i], e = rp[i + 1];
+    const int32_t mask = (1 << pd.log2w) - 1;
+    for (int32_t p = 0; p < pd.np; ++p) {
+        int32_t pos = ptr[(int64_t)(b * pd.np + p) * (pd.rb + 1) + rl];
+        for (int32_t k = a; k < e; ++k) {
+            const int32_t cc = col[k];
+            if ((cc >> pd.log2w) == p) {
+                pv[pos] = vals[k];
+                pc[pos] = (uint16_t)(cc & mask);
+                ++pos;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ BFS
+
+// Rows of a tile, W lanes per row, Boolean (or, and) product against the
+// current frontier {u : level[u] == depth}.
+template <int W>
+__device__ __forceinline__ void bfs_rows(const MatDesc &m, const Tile &t,
+                                         int32_t *__restrict__ level,
+                                         int32_t depth, int32_t *changed)
+{
+    constexpr int G = kBlock / W;
+    const int g = threadIdx.x / W;
+    const int lane = threadIdx.x % W;
+    for (int j = g; j < t.count; j += G) {
+        const int32_t row = tile_row(m, t, j);
+        if (level[row] != -1)
+            continue;  // uniform over the group
+        const int32_t k0 = m.row_ptr[row], k1 = m.row_ptr[row + 1];
+        int32_t hit = 0;
+        for (int32_t k = k0 + lane; k < k1 && !hit; k += W)
+            hit = (level[m.col[k]] == depth) ? 1 : 0;
+        hit = lane_group_or<W>(hit);
+        if (hit && lane == 0) {
+            level[row] = depth + 1;
+            *changed = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bfs_step(
+    const Tile *__restrict__ tiles, int32_t ntiles, MatDesc m,
+    int32_t *__restrict__ level, int32_t depth, int32_t *__restrict__ changed)
+{
+    for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+        const Tile t = tiles[ti];
+        switch (t.cls & kTileClassMask) {
+        case C_W1: bfs_rows<1>(m, t, level, depth, changed); break;
+        case C_W2: bfs_rows<2>(m, t, level, depth, changed); break;
+        case C_W4: bfs_rows<4>(m, t, level, depth, changed); break;
+        case C_W8: bfs_rows<8>(m, t, level, depth, changed); break;
+        case C_W16: bfs_rows<16>(m, t, level, depth, changed); break;
+        case C_W32: bfs_rows<32>(m, t, level, depth, changed); break;
+        case C_W64: bfs_rows<64>(m, t, level, depth, changed); break;
+        case C_WG: {
+            for (int j = 0; j < t.count; ++j) {
+                const int32_t row = tile_row(m, t, j);
+                if (level[row] != -1)
+                    continue;  // uniform over the workgroup
+                int32_t hit = 0;
+                for (int32_t k = m.row_ptr[row] + threadIdx.x; k < m.row_ptr[row + 1];
+                     k += kBlock)
+                    hit |= (level[m.col[k]] == depth) ? 1 : 0;
+                if (__syncthreads_or(hit) && threadIdx.x == 0) {
+                    level[row] = depth + 1;
+                    *changed = 1;
+                }
+            }
+            break;
+        }
+        default: {  // one chunk of a split row
+            const int32_t c = t.first;
+            const int32_t row = m.c_row[c];
+            if (level[row] != -1)
+                break;
+            int32_t hit = 0;
+            for (int32_t k = m.c_k0[c] + threadIdx.x; k < m.c_k1[c]; k += kBlock)
+                hit |= (level[m.col[k]] == depth) ? 1 : 0;
+            if (__syncthreads_or(hit) && threadIdx.x == 0) {
+                level[row] = depth + 1;
+                *changed = 1;
+            }
+            break;
+        }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ JDS
+
+// Thread p handles the row at JDS position p: diagonal j holds its j-th
+// entry at jd_ptr[j] + p, so consecutive threads read consecutive entries.
+// Entries outside [0, nnz) and diagonals past max_len are never touched,
+// whatever the arrays hold; a position whose original row is unknown (perm
+// not a permutation) is not stored.
+__global__ __launch_bounds__(kBlock) void k_spmv_jds(
+    int32_t rows, int32_t max_len, int32_t nnz, const int32_t *__restrict__ iperm,
+    const int32_t *__restrict__ nzcnt, const int32_t *__restrict__ jd_ptr,
+    const int32_t *__restrict__ jd_col, const double *__restrict__ jd_val,
+    const double *__restrict__ x, double *__restrict__ y)
+{
+#pragma clang fp contract(off)
+    const int32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= rows)
+        return;
+    const int32_t n = min(nzcnt[p], max_len);
+    double s = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+        const int32_t k = jd_ptr[j] + p;
+        if (k < 0 || k >= nnz)
+            break;
+        const double prod = jd_val[k] * x[jd_col[k]];
+        s = s + prod;
+    }
+    const int32_t i = iperm[p];
+    if (i >= 0 && i < rows)
+        y[i] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_invert_perm(
+    int32_t rows, const int32_t *__restrict__ perm, int32_t *__restrict__ iperm)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < rows) {
+        const int32_t q = perm[i];
+        if (q >= 0 && q < rows)
+            iperm[q] = i;
+    }
+}
+
 // ---------------------------------------------------------- batched CG
 
 // Segment of workgroup blockIdx.x (segments ordered by blk0).
@@ -1019,6 +1280,86 @@ void launch_spmv_segments(lilac_dtype dt, const MatDesc *mats,
         hipLaunchKernelGGL(k_spmv_segments<float>, dim3(grid), dim3(kBlock), 0, s,
                            mats, prefix, nseg, total);
     check_launch("k_spmv_segments");
+}
+
+void launch_spmv_panels(lilac_dtype dt, const PanelDesc &pd, const void *x,
+                        void *y, const Epi &epi, const void *w, double *dot_part,
+                        hipStream_t s)
+{
+    if (pd.nblk <= 0)
+        return;
+    dim3 g(pd.nblk), b(kPanelThreads);
+    if (dt == LILAC_F64) {
+        if (dot_part)
+            hipLaunchKernelGGL((k_spmv_panels<double, true>), g, b, kPanelBytes, s, pd,
+                               (const double *)x, (double *)y, epi, (const double *)w, dot_part);
+        else
+            hipLaunchKernelGGL((k_spmv_panels<double, false>), g, b, kPanelBytes, s, pd,
+                               (const double *)x, (double *)y, epi, (const double *)w, dot_part);
+    } else {
+        if (dot_part)
+            fail(LILAC_ERR_UNSUPPORTED, "fused dot is only provided for float64");
+        hipLaunchKernelGGL((k_spmv_panels<float, false>), g, b, kPanelBytes, s, pd,
+                           (const float *)x, (float *)y, epi, (const float *)w, dot_part);
+    }
+    check_launch("k_spmv_panels");
+}
+
+void launch_panel_count(const PanelDesc &pd, const int32_t *rp,
+                        const int32_t *col, int32_t *cnt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_panel_count, dim3(grid_for(pd.rows, kBlock, INT_MAX)),
+                       dim3(kBlock), 0, s, pd, rp, col, cnt);
+    check_launch("k_panel_count");
+}
+
+void launch_panel_scatter(lilac_dtype dt, const PanelDesc &pd, const int32_t *rp,
+                          const int32_t *col, const void *vals, const int32_t *ptr,
+                          void *pv, uint16_t *pc, hipStream_t s)
+{
+    dim3 g(grid_for(pd.rows, kBlock, INT_MAX)), b(kBlock);
+    if (dt == LILAC_F64)
+        hipLaunchKernelGGL(k_panel_scatter<double>, g, b, 0, s, pd, rp, col,
+                           (const double *)vals, ptr, (double *)pv, pc);
+    else
+        hipLaunchKernelGGL(k_panel_scatter<float>, g, b, 0, s, pd, rp, col,
+                           (const float *)vals, ptr, (float *)pv, pc);
+    check_launch("k_panel_scatter");
+}
+
+void launch_bfs_step(const Tile *tiles, int32_t ntiles, int32_t grid,
+                     const MatDesc &m, int32_t *level, int32_t depth,
+                     int32_t *changed, hipStream_t s)
+{
+    if (ntiles <= 0)
+        return;
+    hipLaunchKernelGGL(k_bfs_step, dim3(std::min(grid, ntiles)), dim3(kBlock), 0, s,
+                       tiles, ntiles, m, level, depth, changed);
+    check_launch("k_bfs_step");
+}
+
+void launch_spmv_jds(int32_t rows, int32_t max_len, int32_t nnz,
+                     const int32_t *iperm, const int32_t *nzcnt,
+                     const int32_t *jd_ptr, const int32_t *jd_col,
+                     const double *jd_val, const double *x, double *y,
+                     hipStream_t s)
+{
+    if (rows <= 0)
+        return;
+    hipLaunchKernelGGL(k_spmv_jds, dim3(grid_for(rows, kBlock, INT_MAX)), dim3(kBlock),
+                       0, s, rows, max_len, nnz, iperm, nzcnt, jd_ptr, jd_col, jd_val,
+                       x, y);
+    check_launch("k_spmv_jds");
+}
+
+void launch_invert_perm(int32_t rows, const int32_t *perm, int32_t *iperm,
+                        hipStream_t s)
+{
+    if (rows <= 0)
+        return;
+    hipLaunchKernelGGL(k_invert_perm, dim3(grid_for(rows, kBlock, INT_MAX)), dim3(kBlock),
+                       0, s, rows, perm, iperm);
+    check_launch("k_invert_perm");
 }
 
 int32_t cg_seg_blocks(int64_t n) { return grid_for(n, kBlock, kBlock); }

@@ -50,6 +50,7 @@ struct MatDesc {
     const int32_t *c_k0;      // chunk table: first non-zero of each chunk
     const int32_t *c_k1;      //              one past the last
     const int32_t *s_first;   // per split row: first chunk (nsplit+1 entries)
+    const int32_t *c_row;     // chunk table: row of each chunk
     const void *x;
     void *y;
     const void *w;            // second operand of the fused dot (or null)
@@ -83,7 +84,30 @@ struct Plan {
     int32_t rpg[NCLASS];    // rows per lane group per tile
     int32_t chunk;          // non-zeros per split-row chunk
     int32_t grid_per_cu;    // persistent workgroups per compute unit
+    int32_t layout;         // LAYOUT_AUTO, LAYOUT_ROWS or LAYOUT_PANELS
 };
+
+// Device layouts of a matrix for the product: the row-class tiles over the
+// CSR arrays, or column panels (x staged in LDS one panel at a time).
+enum : int32_t { LAYOUT_AUTO = -1, LAYOUT_ROWS = 0, LAYOUT_PANELS = 1 };
+
+// Column-panel layout: the columns are cut into panels of 2^log2w; the rows
+// into blocks of `rb`.  For row block b and panel p, the entries of the
+// block's rows that fall in the panel are stored together, row by row (each
+// row's entries in their CSR order), with 16-bit column offsets inside the
+// panel; ptr[(b*np + p)*(rb+1) + r] is where row r of the block starts.
+struct PanelDesc {
+    const void *vals;
+    const uint16_t *col;
+    const int32_t *ptr;
+    int32_t rows, cols;
+    int32_t log2w, np, rb, nblk;
+};
+constexpr int kPanelThreads = 512;   // 8 wave64 per workgroup
+constexpr int kPanelLanes = 16;      // lanes per row inside a panel
+constexpr int kPanelRpg = 16;        // rows per lane group (at most)
+constexpr int kPanelMaxRb = (kPanelThreads / kPanelLanes) * kPanelRpg;
+constexpr int kPanelBytes = 65536;   // LDS for one panel of x
 
 Plan default_plan();
 
@@ -107,6 +131,12 @@ struct CsrHandle {
     double *d_chunk_part = nullptr;
     Tile *d_tiles = nullptr;
     double *d_dot_part = nullptr;   // one per persistent workgroup + finaliser
+    // column-panel layout (when use_panels)
+    bool use_panels = false;
+    PanelDesc pan{};
+    void *d_pv = nullptr;
+    uint16_t *d_pc = nullptr;
+    int32_t *d_pptr = nullptr;
     std::vector<int32_t> bin_off;   // NCLASS+1
     int64_t nchunks = 0;
     int32_t nsplit = 0;
@@ -167,6 +197,16 @@ void launch_spmv_tiles(lilac_dtype dt, const Tile *tiles, int32_t ntiles,
                        int32_t grid, const MatDesc &single,
                        const MatDesc *mats, const Epi &epi, double *dot_part,
                        hipStream_t s);
+// Column-panel product (see PanelDesc); dot_part (or null) receives one
+// partial of sum w[i]*y[i] per workgroup.
+void launch_spmv_panels(lilac_dtype dt, const PanelDesc &pd, const void *x,
+                        void *y, const Epi &epi, const void *w, double *dot_part,
+                        hipStream_t s);
+void launch_panel_count(const PanelDesc &pd, const int32_t *rp,
+                        const int32_t *col, int32_t *cnt, hipStream_t s);
+void launch_panel_scatter(lilac_dtype dt, const PanelDesc &pd, const int32_t *rp,
+                          const int32_t *col, const void *vals, const int32_t *ptr,
+                          void *pv, uint16_t *pc, hipStream_t s);
 // Finaliser for split rows: single matrix (items == null, n = nsplit) or a
 // list of (matrix, split row) items for grouped launches.
 void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,
@@ -201,6 +241,23 @@ void launch_cgb_xpay(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_
 
 void launch_dot_parts(int64_t n, const double *a, const double *b,
                       double *part, int32_t nparts, hipStream_t s);
+
+// One level of a breadth-first search as a Boolean product over the tiles:
+// every row v with level[v] == -1 that has a column u with level[u] == depth
+// gets level depth+1; *changed is set to 1 if any row did.
+void launch_bfs_step(const Tile *tiles, int32_t ntiles, int32_t grid,
+                     const MatDesc &m, int32_t *level, int32_t depth,
+                     int32_t *changed, hipStream_t s);
+
+// Jagged Diagonal Storage product, every sum in diagonal order without
+// contraction (bitwise equal to the sequential definition).
+void launch_spmv_jds(int32_t rows, int32_t max_len, int32_t nnz,
+                     const int32_t *iperm, const int32_t *nzcnt,
+                     const int32_t *jd_ptr, const int32_t *jd_col,
+                     const double *jd_val, const double *x, double *y,
+                     hipStream_t s);
+void launch_invert_perm(int32_t rows, const int32_t *perm, int32_t *iperm,
+                        hipStream_t s);
 void launch_sum_parts(const double *part, int32_t nparts, double *out,
                       hipStream_t s);
 void launch_copy_f64(int64_t n, const double *src, double *dst, hipStream_t s);

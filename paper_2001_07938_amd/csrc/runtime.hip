@@ -231,6 +231,7 @@ Plan default_plan()
     }
     p.chunk = 4096;
     p.grid_per_cu = 8;
+    p.layout = LAYOUT_AUTO;
     return p;
 }
 
@@ -250,6 +251,8 @@ static void check_plan(const Plan &p)
         fail(LILAC_ERR_ARG, "chunk must be in [256, 2^24]");
     if (p.grid_per_cu < 1 || p.grid_per_cu > 32)
         fail(LILAC_ERR_ARG, "grid_per_cu must be in [1, 32]");
+    if (p.layout < LAYOUT_AUTO || p.layout > LAYOUT_PANELS)
+        fail(LILAC_ERR_ARG, "unknown layout");
 }
 
 static const int kLanes[NCLASS] = {1, 2, 4, 8, 16, 32, 64, kBlock, kBlock};
@@ -269,6 +272,11 @@ static void free_analysis(CsrHandle &h)
     dev_free_reset(h.d_chunk_part);
     dev_free_reset(h.d_tiles);
     dev_free_reset(h.d_dot_part);
+    dev_free_reset(h.d_pv);
+    dev_free_reset(h.d_pc);
+    dev_free_reset(h.d_pptr);
+    h.use_panels = false;
+    h.pan = PanelDesc{};
     h.ntiles = 0;
     h.nchunks = 0;
     h.nsplit = 0;
@@ -278,9 +286,81 @@ static void free_analysis(CsrHandle &h)
 
 static int64_t analysis_bytes(const CsrHandle &h)
 {
-    return (int64_t)h.rows * 4 + h.nchunks * (3 * 4 + 8) +
-           (int64_t)(h.nsplit + 1) * 4 + (int64_t)h.ntiles * sizeof(Tile) +
-           (int64_t)(h.grid + h.fin_blocks) * 8;
+    int64_t b = (int64_t)h.rows * 4 + h.nchunks * (3 * 4 + 8) +
+                (int64_t)(h.nsplit + 1) * 4 + (int64_t)h.ntiles * sizeof(Tile) +
+                (int64_t)(h.grid + h.fin_blocks) * 8;
+    if (h.use_panels)
+        b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 2) +
+             (int64_t)h.pan.nblk * h.pan.np * (h.pan.rb + 1) * 4;
+    return b;
+}
+
+// Panels of x that fit the LDS budget: 2^log2w columns of the value type.
+static int32_t panel_log2w(lilac_dtype dt) { return dt == LILAC_F32 ? 14 : 13; }
+
+// Whether the column-panel layout suits the matrix: at least 8 entries per
+// row and panel on average, few panels, and no row too long for one lane
+// group (rows in the wavefront class at most).
+static bool panels_eligible(const CsrHandle &h)
+{
+    if (h.rows == 0 || h.nnz == 0)
+        return false;
+    const int64_t np = ((int64_t)h.cols + (1 << panel_log2w(h.dt)) - 1) >> panel_log2w(h.dt);
+    if (np < 1 || np > 64)
+        return false;
+    if (h.bin_off[NCLASS] - h.bin_off[C_W64 + 1] > 0)
+        return false;  // rows longer than the wavefront class bound
+    const double mean = (double)h.nnz / h.rows;
+    return mean / (double)np >= 8.0;
+}
+
+static int64_t scan_total(int32_t *a, int64_t n, hipStream_t s);
+
+// Builds the column-panel copy of the matrix (see PanelDesc).
+static void build_panels(CsrHandle &h, hipStream_t s)
+{
+    Context &c = ctx();
+    PanelDesc pd{};
+    pd.rows = h.rows;
+    pd.cols = h.cols;
+    pd.log2w = panel_log2w(h.dt);
+    pd.np = (int32_t)(((int64_t)h.cols + (1 << pd.log2w) - 1) >> pd.log2w);
+    // two resident workgroups per CU, at most kPanelMaxRb rows each
+    int64_t nblk = std::max<int64_t>(2 * c.cu, (h.rows + kPanelMaxRb - 1) / kPanelMaxRb);
+    nblk = std::min<int64_t>(nblk, h.rows);
+    pd.rb = (int32_t)((h.rows + nblk - 1) / nblk);
+    pd.nblk = (int32_t)((h.rows + pd.rb - 1) / pd.rb);
+    const int64_t nptr = (int64_t)pd.nblk * pd.np * (pd.rb + 1);
+    h.d_pptr = (int32_t *)dev_alloc((size_t)nptr * 4);
+    launch_fill_i32(h.d_pptr, nptr, 0, s);
+    launch_panel_count(pd, h.d_row_ptr, h.d_col, h.d_pptr, s);
+    const int64_t total = scan_total(h.d_pptr, nptr, s);
+    if (total != h.nnz)
+        fail(LILAC_ERR_DEVICE, "panel layout lost entries");
+    const size_t vs = dtype_size(h.dt);
+    h.d_pv = dev_alloc((size_t)(h.nnz + kPad) * vs);
+    h.d_pc = (uint16_t *)dev_alloc((size_t)(h.nnz + kPad) * 2);
+    launch_fill_bytes_zero((char *)h.d_pv + h.nnz * vs, kPad * vs, s);
+    launch_fill_bytes_zero((char *)h.d_pc + h.nnz * 2, kPad * 2, s);
+    launch_panel_scatter(h.dt, pd, h.d_row_ptr, h.d_col, h.d_vals, h.d_pptr,
+                         h.d_pv, h.d_pc, s);
+    pd.vals = h.d_pv;
+    pd.col = h.d_pc;
+    pd.ptr = h.d_pptr;
+    h.pan = pd;
+    h.use_panels = true;
+    HIPC(hipStreamSynchronize(s));
+}
+
+// Exclusive scan of a[0..n) in place; returns the total.
+static int64_t scan_total(int32_t *a, int64_t n, hipStream_t s)
+{
+    Context &c = ctx();
+    launch_scan_excl(a, n, c.total, s);
+    int32_t total = 0;
+    HIPC(hipMemcpyAsync(&total, c.total, 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return total;
 }
 
 // Row-length analysis: class of every row, class-ordered row list, chunk
@@ -374,7 +454,18 @@ static void analyse(CsrHandle &h, hipStream_t s)
         h.grid = std::min<int32_t>(h.ntiles, c.cu * occ);
     }
     h.fin_blocks = (h.nsplit + kBlock - 1) / kBlock;
-    h.d_dot_part = (double *)dev_alloc((size_t)(h.grid + h.fin_blocks + 1) * 8);
+    // a forced panel layout only needs a bounded number of panels; the
+    // automatic choice also needs the matrix to suit it
+    const int64_t np_req = h.cols > 0 ? (((int64_t)h.cols - 1) >> panel_log2w(h.dt)) + 1 : 0;
+    const bool want_panels =
+        (h.plan.layout == LAYOUT_PANELS && np_req <= 1024) ||
+        (h.plan.layout == LAYOUT_AUTO && panels_eligible(h));
+    if (want_panels && h.rows > 0 && h.nnz > 0) {
+        build_panels(h, s);
+        h.grid = h.pan.nblk;   // one fused-dot partial per row block
+        h.fin_blocks = 0;
+    }
+    h.d_dot_part = (double *)dev_alloc((size_t)(std::max(h.grid, 1) + h.fin_blocks + 1) * 8);
     HIPC(hipStreamSynchronize(s));
     g_extra[&h].tiles = std::move(tiles);
 }
@@ -577,6 +668,7 @@ MatDesc make_desc(const CsrHandle &h, const void *x, void *y,
     d.c_k0 = h.d_c_k0;
     d.c_k1 = h.d_c_k1;
     d.s_first = h.d_s_first;
+    d.c_row = h.d_c_row;
     d.x = x;
     d.y = y;
     d.w = w;
@@ -595,6 +687,10 @@ void spmv_enqueue(const CsrHandle &h, const void *x, void *y,
 {
     if (h.rows == 0)
         return;
+    if (h.use_panels) {
+        launch_spmv_panels(h.dt, h.pan, x, y, epi, w, dot ? h.d_dot_part : nullptr, s);
+        return;
+    }
     const MatDesc d = make_desc(h, x, y, w, h.d_chunk_part);
     launch_spmv_tiles(h.dt, h.d_tiles, h.ntiles, h.grid, d, nullptr, epi,
                       dot ? h.d_dot_part : nullptr, s);
@@ -1061,6 +1157,8 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
             const CsrHandle *h = g->hs[j];
             descs[j] = make_desc(*h, xs[j], ys[j], nullptr,
                                  g->d_chunk ? g->d_chunk + chunk_off[j] : nullptr);
+            if (h->use_panels)
+                continue;  // launched on its own layout
             for (int32_t k = 0; k < h->nsplit; ++k) {
                 items.push_back(j);
                 items.push_back(k);
@@ -1070,6 +1168,7 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
         for (int cls = C_SPLIT; cls >= C_W1; --cls)
             for (int j = 0; j < count; ++j)
                 for (const Tile &t : g_extra[g->hs[j]].tiles)
+                    if (!g->hs[j]->use_panels)
                     if ((t.cls & kTileClassMask) == cls) {
                         Tile u = t;
                         u.mat = j;
@@ -1147,6 +1246,13 @@ static void run_batched(int count, const lilac_csr_t *hs, const void *const *xs,
     if (hit->nitems)
         launch_split_finalize(hit->dt, hit->d_items, hit->nitems, none,
                               hit->d_mats, epi_none(), nullptr, s);
+    // matrices kept in the column-panel layout run their own kernel, so each
+    // result is the same as its single call
+    for (int j = 0; j < count; ++j) {
+        const CsrHandle *h = hit->hs[j];
+        if (h->use_panels)
+            spmv_enqueue(*h, xs[j], ys[j], epi_none(), nullptr, false, s);
+    }
 }
 
 // ================================================================ tuning
@@ -1184,7 +1290,8 @@ static std::string plan_to_json(const Plan &p)
     o << "],\"rpg\":[";
     for (int c = 0; c < NCLASS; ++c)
         o << (c ? "," : "") << p.rpg[c];
-    o << "],\"chunk\":" << p.chunk << ",\"grid_per_cu\":" << p.grid_per_cu << "}";
+    o << "],\"chunk\":" << p.chunk << ",\"grid_per_cu\":" << p.grid_per_cu
+      << ",\"layout\":" << p.layout << "}";
     return o.str();
 }
 
@@ -1218,7 +1325,7 @@ void tune_cache_load()
                 ++i;
             }
         }
-        if (nums.size() != (size_t)(NCLASS - 1 + NCLASS + 2))
+        if (nums.size() != (size_t)(NCLASS - 1 + NCLASS + 3))
             continue;
         Plan p = default_plan();
         size_t k = 0;
@@ -1228,6 +1335,7 @@ void tune_cache_load()
             p.rpg[c] = (int32_t)nums[k++];
         p.chunk = (int32_t)nums[k++];
         p.grid_per_cu = (int32_t)nums[k++];
+        p.layout = (int32_t)nums[k++];
         try {
             check_plan(p);
             g_tune[key] = p;
@@ -1344,6 +1452,13 @@ static double tune_handle(CsrHandle &h)
         for (int gp : {2, 4, 8, 16}) {
             Plan p = best;
             p.grid_per_cu = gp;
+            trial(p);
+        }
+        for (int lay : {LAYOUT_ROWS, LAYOUT_PANELS}) {
+            Plan p = best;
+            p.layout = lay;
+            if (lay == LAYOUT_PANELS && !panels_eligible(h))
+                continue;
             trial(p);
         }
     } catch (...) {
@@ -1533,6 +1648,8 @@ int lilac_csr_info(lilac_csr_t hh, lilac_csr_info_t *out)
         out->chunk = h->plan.chunk;
         out->nchunks = h->nchunks;
         out->ntiles = h->ntiles;
+        out->layout = h->use_panels ? LAYOUT_PANELS : LAYOUT_ROWS;
+        out->npanels = h->use_panels ? h->pan.np : 0;
     });
 }
 
@@ -1583,6 +1700,24 @@ int lilac_csr_set_plan(lilac_csr_t hh, const int *upper, const int *rpg, int chu
         forget_handle_in_groups(h);
         h->plan = p;
         h->dev_bytes -= analysis_bytes(*h);
+        analyse(*h, s);
+        h->dev_bytes += analysis_bytes(*h);
+    });
+}
+
+int lilac_csr_set_layout(lilac_csr_t hh, int layout)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        Plan p = h->plan;
+        p.layout = layout;
+        check_plan(p);
+        hipStream_t s = ctx().stream;
+        refresh(*h, s);
+        h->dev_bytes -= analysis_bytes(*h);
+        h->plan = p;
         analyse(*h, s);
         h->dev_bytes += analysis_bytes(*h);
     });
@@ -1672,6 +1807,120 @@ int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
                        void *const *ys, void *stream)
 {
     return guard([&] { run_batched(count, hs, xs, ys, pick_stream(stream)); });
+}
+
+int lilac_bfs(lilac_csr_t hh, int source, int *level, int *nlevels, void *stream)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h || !level)
+            fail(LILAC_ERR_ARG, "NULL argument");
+        if (h->cols > h->rows)
+            fail(LILAC_ERR_ARG, "BFS needs cols <= rows (a graph's adjacency)");
+        if (source < 0 || source >= h->rows)
+            fail(LILAC_ERR_ARG, "source out of range");
+        if (!is_device_ptr(level))
+            fail(LILAC_ERR_ARG, "level must be a device array");
+        hipStream_t s = pick_stream(stream);
+        refresh(*h, s);
+        Context &c = ctx();
+        launch_fill_i32(level, h->rows, -1, s);
+        launch_fill_i32(level + source, 1, 0, s);
+        const MatDesc m = make_desc(*h, nullptr, nullptr, nullptr, nullptr);
+        const int32_t grid = h->use_panels ? tile_grid(h->dt) : h->grid;
+        int32_t depth = 0;
+        for (;; ++depth) {
+            launch_fill_i32(c.status, 1, 0, s);
+            launch_bfs_step(h->d_tiles, h->ntiles, grid, m, level, depth, c.status, s);
+            int32_t changed = 0;
+            HIPC(hipMemcpyAsync(&changed, c.status, 4, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            if (!changed)
+                break;
+        }
+        if (nlevels)
+            *nlevels = depth + 1;
+    });
+}
+
+int lilac_spmv_jds(int rows, int max_len, const int *perm, const int *nzcnt,
+                   const int *jd_ptr, const int *jd_col, const double *jd_val,
+                   const double *x, double *y)
+{
+    return guard([&] {
+        if (rows < 0 || max_len < 0)
+            fail(LILAC_ERR_ARG, "negative size");
+        if (rows == 0)
+            return;
+        if (!perm || !nzcnt || !jd_ptr || !y || (max_len > 0 && (!jd_col || !jd_val || !x)))
+            fail(LILAC_ERR_ARG, "NULL argument");
+        Context &c = ctx();
+        hipStream_t s = c.stream;
+        const bool any_dev = is_device_ptr(perm) || is_device_ptr(nzcnt) ||
+                             is_device_ptr(jd_ptr) || is_device_ptr(jd_col) ||
+                             is_device_ptr(jd_val) || is_device_ptr(x) || is_device_ptr(y);
+        if (any_dev)
+            HIPC(hipDeviceSynchronize());
+        // jd_ptr[max_len] is the number of entries
+        int32_t nnz = 0;
+        if (is_device_ptr(jd_ptr)) {
+            HIPC(hipMemcpyAsync(&nnz, jd_ptr + max_len, 4, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+        } else {
+            nnz = jd_ptr[max_len];
+        }
+        if (nnz < 0)
+            fail(LILAC_ERR_ARG, "jd_ptr[max_len] < 0");
+        // device copies of host arrays for this call (JDS is not cached)
+        std::vector<void *> tmp;
+        auto dev = [&](const void *p, size_t bytes) -> const void * {
+            if (!p || is_device_ptr(p))
+                return p;
+            void *d = dev_alloc(bytes);
+            tmp.push_back(d);
+            HIPC(hipMemcpyAsync(d, p, bytes, hipMemcpyHostToDevice, s));
+            return d;
+        };
+        int32_t cols = 0;
+        try {
+            const int32_t *d_perm = (const int32_t *)dev(perm, (size_t)rows * 4);
+            const int32_t *d_nz = (const int32_t *)dev(nzcnt, (size_t)rows * 4);
+            const int32_t *d_ptr = (const int32_t *)dev(jd_ptr, (size_t)(max_len + 1) * 4);
+            const int32_t *d_col = (const int32_t *)dev(jd_col, (size_t)std::max(nnz, 1) * 4);
+            const double *d_val = (const double *)dev(jd_val, (size_t)std::max(nnz, 1) * 8);
+            // the columns bound the x that must be present
+            launch_fill_i32(c.status + 1, 1, -1, s);
+            launch_fill_i32(c.status, 1, 0, s);
+            launch_validate(0, c.total, nnz, d_col, -1, c.status, s);
+            int32_t st[2];
+            HIPC(hipMemcpyAsync(st, c.status, 8, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            if (st[0] & 8)
+                fail(LILAC_ERR_CSR, "negative column index in JDS");
+            cols = st[1] + 1;
+            const double *d_x = (const double *)dev(x, (size_t)std::max(cols, 1) * 8);
+            int32_t *iperm = (int32_t *)dev_alloc((size_t)rows * 4);
+            tmp.push_back(iperm);
+            const bool y_dev = is_device_ptr(y);
+            double *d_y = y_dev ? y : (double *)dev_alloc((size_t)rows * 8);
+            if (!y_dev)
+                tmp.push_back(d_y);
+            launch_fill_i32(iperm, rows, -1, s);
+            launch_invert_perm(rows, d_perm, iperm, s);
+            launch_spmv_jds(rows, max_len, nnz, iperm, d_nz, d_ptr, d_col, d_val, d_x,
+                            d_y, s);
+            if (!y_dev)
+                HIPC(hipMemcpyAsync(y, d_y, (size_t)rows * 8, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            for (void *d : tmp)
+                dev_free(d);
+            throw;
+        }
+        for (void *d : tmp)
+            dev_free(d);
+    });
 }
 
 int lilac_csr_tune(lilac_csr_t hh, double *best_us)

@@ -396,6 +396,7 @@ void run_tick(Server *S)
     std::vector<int32_t> prefix(1, 0);
     std::vector<int32_t> items;
     std::vector<CgSeg> init, step;
+    std::vector<Req *> own;
     int32_t init_blocks = 0, step_blocks = 0;
     for (Req *r : S->active) {
         SMatrix &m = S->mats[r->mid];
@@ -403,10 +404,15 @@ void run_tick(Server *S)
         const int j = (int)descs.size();
         const double *in = r->in ? r->in : m.vin;
         double *out = r->out ? r->out : m.vout;
-        if (r->kind == LILAC_REQ_SPMV) {
+        if (m.h->use_panels) {
+            // column-panel matrices run their own product kernel
+            own.push_back(r);
+        } else if (r->kind == LILAC_REQ_SPMV) {
             descs.push_back(make_desc(*m.h, in, out, nullptr, sl.chunk));
         } else {
             descs.push_back(make_desc(*m.h, sl.p, sl.q, nullptr, sl.chunk));
+        }
+        if (r->kind == LILAC_REQ_CG) {
             CgSeg sg;
             sg.b = in;
             sg.x = out;
@@ -429,6 +435,8 @@ void run_tick(Server *S)
             step_blocks += sg.nb;
             step.push_back(sg);
         }
+        if (m.h->use_panels)
+            continue;
         prefix.push_back(prefix.back() + m.h->ntiles);
         for (int32_t k = 0; k < m.h->nsplit; ++k) {
             items.push_back(j);
@@ -461,6 +469,16 @@ void run_tick(Server *S)
     launch_spmv_segments(LILAC_F64, d_desc, (const int32_t *)(tk.dev + o_pre),
                          (int32_t)descs.size(), prefix.back(), tile_grid(LILAC_F64),
                          S->stream);
+    for (Req *r : own) {
+        SMatrix &m = S->mats[r->mid];
+        Slot &sl = S->slots[r->slot];
+        if (r->kind == LILAC_REQ_SPMV)
+            spmv_enqueue(*m.h, r->in ? r->in : m.vin, r->out ? r->out : m.vout,
+                         Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, S->stream);
+        else
+            spmv_enqueue(*m.h, sl.p, sl.q, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr,
+                         false, S->stream);
+    }
     if (!items.empty()) {
         MatDesc none{};
         launch_split_finalize(LILAC_F64, (const int32_t *)(tk.dev + o_items),

@@ -83,3 +83,22 @@ def test_tuner_keeps_results_in_tolerance():
     torch.cuda.synchronize()
     check_spmv(A, x, y.cpu().numpy(), TOL_F64)
     h.destroy()
+
+
+def test_batched_with_panel_matrices_bitwise():
+    mats = [gen.spd_random(20000, 60, seed=21), gen.stencil(12, 7),
+            gen.uniform_rows(4096, 16), gen.random_rows(8000, 5, 60, seed=22)]
+    hs = [L.Csr.from_gen(A) for A in mats]
+    assert hs[0].info().layout == L.LAYOUT_PANELS
+    assert hs[1].info().layout == L.LAYOUT_ROWS
+    xs = [_dev(gen.vector(A.cols, 30 + i)) for i, A in enumerate(mats)]
+    ys = [torch.empty(A.rows, dtype=torch.float64, device=DEV) for A in mats]
+    ys1 = [torch.empty_like(y) for y in ys]
+    for h, x, y in zip(hs, xs, ys1):
+        h.spmv(x, y)
+    L.lilac_spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for y, y1 in zip(ys, ys1):
+        assert torch.equal(y, y1)
+    for h in hs:
+        h.destroy()

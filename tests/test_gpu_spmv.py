@@ -246,3 +246,76 @@ def test_dot_raw_and_device():
             L.lilac_dot_dev(n, ad, bd, out)
             assert _host(out)[0] == L.lilac_dot(n, ad, bd)
     assert L.lilac_dot(1 << 20, np.ones(1 << 20), np.ones(1 << 20)) == float(1 << 20)
+
+
+PANEL_MATS = {
+    "spd20k": lambda: gen.spd_random(20000, 60, seed=6),
+    "uniform16": lambda: gen.uniform_rows(4096, 16),
+    "ragged_dense_rows": lambda: gen.ragged(3000, 9000, seed=8, max_len=1000,
+                                            empty_frac=0.05, sort_cols=False),
+    "wide_tail_panel": lambda: gen.random_rows(5000, 150, 300, seed=9, cols=20000),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PANEL_MATS))
+def test_panel_layout_parity(name):
+    A = PANEL_MATS[name]()
+    x = gen.vector(A.cols, 60)
+    h = L.Csr.from_gen(A, cols=A.cols)
+    xd = _dev(x)
+    ys = {}
+    for lay in (L.LAYOUT_PANELS, L.LAYOUT_ROWS):
+        h.set_layout(lay)
+        inf = h.info()
+        assert inf.layout == lay, (name, lay)
+        yd = torch.full((A.rows,), np.nan, dtype=torch.float64, device=DEV)
+        h.spmv(xd, yd)
+        ys[lay] = _host(yd)
+        check_spmv(A, x, ys[lay], TOL_F64)
+    # integer data: both layouts exact
+    A.vals = gen.int_vector(A.nnz, 61)
+    xi = gen.int_vector(A.cols, 62)
+    h2 = L.Csr.from_gen(A, cols=A.cols)
+    h2.set_layout(L.LAYOUT_PANELS)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h2.spmv(_dev(xi), yd)
+    assert np.array_equal(_host(yd), oracle.spmv_csr(A.row_ptr, A.col_idx, A.vals, xi))
+    h.destroy()
+    h2.destroy()
+
+
+def test_panel_layout_f32_and_fused_dot():
+    A = gen.spd_random(20000, 60, seed=6)
+    h = L.Csr.from_gen(A)
+    assert h.info().layout == L.LAYOUT_PANELS  # chosen automatically
+    x = gen.vector(A.cols, 63)
+    w = gen.vector(A.rows, 64)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    out = torch.empty(1, dtype=torch.float64, device=DEV)
+    h.spmv_dot(_dev(x), yd, _dev(w), out)
+    y = _host(yd)
+    check_spmv(A, x, y, TOL_F64)
+    assert abs(_host(out)[0] - oracle.dot(w, y)) <= TOL_F64 * oracle.dot_abs(w, y)
+    h.destroy()
+    B = A.astype(np.float32)
+    h = L.Csr.from_gen(B)
+    h.set_layout(L.LAYOUT_PANELS)
+    x32 = gen.vector(B.cols, 65, dtype=np.float32)
+    yd = torch.empty(B.rows, dtype=torch.float32, device=DEV)
+    h.spmv(_dev(x32), yd)
+    check_spmv(B, x32, _host(yd), TOL_F32)
+    h.destroy()
+
+
+def test_panel_layout_unaligned_x():
+    """x starting 8 bytes past a 16-byte boundary takes the scalar staging
+    path of the panel kernel."""
+    A = gen.spd_random(20000, 60, seed=6)
+    h = L.Csr.from_gen(A)
+    x = gen.vector(A.cols, 66)
+    buf = torch.empty(A.cols + 1, dtype=torch.float64, device=DEV)
+    buf[1:] = torch.from_numpy(x).to(DEV)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(buf[1:], yd)
+    check_spmv(A, x, _host(yd), TOL_F64)
+    h.destroy()
