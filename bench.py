@@ -14,7 +14,7 @@ and the oracle's CPU time on the same input.
 Other workloads (--workload): spmv16 (single product, n = 4096, 16 per row),
 pagerank (R-MAT 2^22, 2^26 edge draws, float32, 20 steps), batched (512
 matrices in one grouped launch), serve (Poisson request stream over resident
-matrices).  --workload all adds every other workload's figures under
+matrices), marshal (cached versus per-call upload of the paper-shaped call).  --workload all adds every other workload's figures under
 "extras" of the same line.
 """
 from __future__ import annotations
@@ -270,13 +270,40 @@ def run_serve(args, torch, L, gen):
     return out
 
 
+def run_marshal(args, torch, L, gen):
+    """The paper's marshaling comparison on MI355X: the paper-shaped call
+    with host arrays, the matrix cached on the device after the first call
+    (only x up and y down per call) against re-uploading and re-analysing it
+    on every call (LILAC_MARSHAL=naive)."""
+    A = gen.spd_random()
+    x = gen.vector(A.cols, 3)
+    y = np.empty(A.rows)
+    out = {"workload": "marshal_spd150k"}
+    for mode, reps in (("persistent", 20), ("naive", 3)):
+        if mode == "naive":
+            os.environ["LILAC_MARSHAL"] = "naive"
+        else:
+            os.environ.pop("LILAC_MARSHAL", None)
+        L.lilac_spmv_csr(A.rows, A.row_ptr, A.col_idx, A.vals, x, y)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            L.lilac_spmv_csr(A.rows, A.row_ptr, A.col_idx, A.vals, x, y)
+        out[f"ms_per_call_{mode}"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+        L.lilac_release_all()
+    os.environ.pop("LILAC_MARSHAL", None)
+    out["naive_over_persistent"] = round(out["ms_per_call_naive"] /
+                                         out["ms_per_call_persistent"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cg",
-                    choices=["cg", "spmv16", "pagerank", "batched", "serve", "all"])
+                    choices=["cg", "spmv16", "pagerank", "batched", "serve",
+                             "marshal", "all"])
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -294,14 +321,16 @@ def main():
         res = run_cg(args, torch, L, gen)
     else:
         fn = {"spmv16": run_spmv16, "pagerank": run_pagerank,
-              "batched": run_batched, "serve": run_serve}[args.workload]
+              "batched": run_batched, "serve": run_serve,
+              "marshal": run_marshal}[args.workload]
         extra = fn(args, torch, L, gen)
         res = run_cg(args, torch, L, gen, extras_only=True)
         res["extras"] = {args.workload: extra}
     if args.workload == "all":
         res["extras"] = {}
         for name, fn in (("spmv16", run_spmv16), ("pagerank", run_pagerank),
-                         ("batched", run_batched), ("serve", run_serve)):
+                         ("batched", run_batched), ("marshal", run_marshal),
+                         ("serve", run_serve)):
             log(f"[{name}] ...")
             res["extras"][name] = fn(args, torch, L, gen)
     out = {

@@ -997,10 +997,22 @@ __global__ __launch_bounds__(kBlock) void k_copy(int64_t n,
         dst[i] = src[i];
 }
 
-// CG: x = 0, r = b, p = b, partial sums of b.b
+// Sum of part[0..n) by one 256-thread workgroup in a fixed order (the same
+// value in every workgroup that computes it).
+__device__ __forceinline__ double sum_parts_256(const double *__restrict__ part,
+                                                int32_t n, double *lds)
+{
+    double acc = 0.0;
+    for (int32_t i = threadIdx.x; i < n; i += kBlock)
+        acc += part[i];
+    return block_sum<kWaves>(acc, lds);
+}
+
+// CG start: x = 0, r = b, p = b, partial sums of b.b into rr (parity 0).
 __global__ __launch_bounds__(kBlock) void k_cg_init(
     int64_t n, const double *__restrict__ b, double *__restrict__ x,
-    double *__restrict__ r, double *__restrict__ p, double *__restrict__ part)
+    double *__restrict__ r, double *__restrict__ p, double *__restrict__ rr,
+    CgScalars *__restrict__ sc)
 {
     __shared__ double lds[kWaves];
     double acc = 0.0;
@@ -1013,53 +1025,43 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(
         acc = fma(bi, bi, acc);
     }
     const double t = block_sum<kWaves>(acc, lds);
-    if (threadIdx.x == 0)
-        part[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(1024) void k_cg_start(
-    const double *__restrict__ part, int32_t n, CgScalars *__restrict__ sc)
-{
-    __shared__ double lds[16];
-    const double rho = sum_parts_1024(part, n, lds);
     if (threadIdx.x == 0) {
-        sc->rho = rho;
-        sc->pq = 0.0;
-        sc->alpha = 0.0;
-        sc->beta = 0.0;
-        sc->done = 0;
-        sc->iters = 0;
+        rr[blockIdx.x] = t;
+        if (blockIdx.x == 0) {
+            sc->rho = 0.0;
+            sc->pq = 0.0;
+            sc->alpha = 0.0;
+            sc->beta = 0.0;
+            sc->done = 0;
+            sc->iters = 0;
+        }
     }
 }
 
-// alpha = rho / (p.q); a zero rho or p.q ends the solve (x is kept).
-__global__ __launch_bounds__(1024) void k_cg_alpha(
-    const double *__restrict__ part, int32_t n, CgScalars *__restrict__ sc)
-{
-    __shared__ double lds[16];
-    if (sc->done)
-        return;
-    const double pq = sum_parts_1024(part, n, lds);
-    if (threadIdx.x == 0) {
-        const double rho = sc->rho;
-        sc->pq = pq;
-        if (rho == 0.0 || pq == 0.0)
-            sc->done = 1;
-        else
-            sc->alpha = rho / pq;
-    }
-}
-
-// x += alpha p; r -= alpha q; partial sums of r.r
+// Iteration k, after q = A p (with p.q partials in dot_part):
+//   rho = sum rr[k&1], pq = sum dot_part; stop (x kept) if either is 0;
+//   alpha = rho/pq; x += alpha p; r -= alpha q; partials of r.r into rr[~k&1].
+// Every workgroup forms rho, pq and alpha itself, in the same order.
 __global__ __launch_bounds__(kBlock) void k_cg_update(
-    int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ p,
+    int64_t n, CgScalars *__restrict__ sc, const double *__restrict__ p,
     const double *__restrict__ q, double *__restrict__ x,
-    double *__restrict__ r, double *__restrict__ part)
+    double *__restrict__ r, const double *__restrict__ dot_part, int32_t ndot,
+    double *__restrict__ rr, int32_t nparts, int32_t par)
 {
     __shared__ double lds[kWaves];
     if (sc->done)
         return;
-    const double alpha = sc->alpha;
+    const double rho = sum_parts_256(rr + par * kDotParts, nparts, lds);
+    const double pq = sum_parts_256(dot_part, ndot, lds);
+    if (rho == 0.0 || pq == 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->done = 1;
+            sc->rho = rho;
+            sc->pq = pq;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
@@ -1069,36 +1071,35 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
         acc = fma(ri, ri, acc);
     }
     const double t = block_sum<kWaves>(acc, lds);
-    if (threadIdx.x == 0)
-        part[blockIdx.x] = t;
-}
-
-// beta = rho' / rho; rho = rho'
-__global__ __launch_bounds__(1024) void k_cg_beta(
-    const double *__restrict__ part, int32_t n, CgScalars *__restrict__ sc)
-{
-    __shared__ double lds[16];
-    if (sc->done)
-        return;
-    const double rho_new = sum_parts_1024(part, n, lds);
     if (threadIdx.x == 0) {
-        sc->beta = rho_new / sc->rho;
-        sc->rho = rho_new;
-        sc->iters += 1;
+        rr[(par ^ 1) * kDotParts + blockIdx.x] = t;
+        if (blockIdx.x == 0) {
+            sc->pq = pq;
+            sc->alpha = alpha;
+        }
     }
 }
 
-// p = r + beta p
+// beta = rho'/rho (rho' = sum rr[~k&1]); p = r + beta p.
 __global__ __launch_bounds__(kBlock) void k_cg_xpay(
-    int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ r,
-    double *__restrict__ p)
+    int64_t n, CgScalars *__restrict__ sc, const double *__restrict__ r,
+    double *__restrict__ p, const double *__restrict__ rr, int32_t nparts,
+    int32_t par)
 {
+    __shared__ double lds[kWaves];
     if (sc->done)
         return;
-    const double beta = sc->beta;
+    const double rho = sum_parts_256(rr + par * kDotParts, nparts, lds);
+    const double rho_new = sum_parts_256(rr + (par ^ 1) * kDotParts, nparts, lds);
+    const double beta = rho_new / rho;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)
         p[i] = fma(beta, p[i], r[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho = rho_new;
+        sc->beta = beta;
+        sc->iters += 1;
+    }
 }
 
 inline int32_t grid_for(int64_t n, int32_t per_block, int32_t cap)
@@ -1431,48 +1432,29 @@ void launch_copy_f32(int64_t n, const float *src, float *dst, hipStream_t s)
 }
 
 void launch_cg_init(int64_t n, const double *b, double *x, double *r,
-                    double *p, double *part, int32_t nparts, hipStream_t s)
+                    double *p, double *rr, int32_t nparts, CgScalars *sc,
+                    hipStream_t s)
 {
     hipLaunchKernelGGL(k_cg_init, dim3(nparts), dim3(kBlock), 0, s, n, b, x, r,
-                       p, part);
+                       p, rr, sc);
     check_launch("k_cg_init");
 }
 
-void launch_cg_start(const double *part, int32_t nparts, CgScalars *sc,
-                     hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1024), 0, s, part, nparts, sc);
-    check_launch("k_cg_start");
-}
-
-void launch_cg_alpha(const double *part, int32_t nparts, CgScalars *sc,
-                     hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, part, nparts, sc);
-    check_launch("k_cg_alpha");
-}
-
-void launch_cg_update(int64_t n, const CgScalars *sc, const double *p,
-                      const double *q, double *x, double *r, double *part,
-                      int32_t nparts, hipStream_t s)
+void launch_cg_update(int64_t n, CgScalars *sc, const double *p,
+                      const double *q, double *x, double *r,
+                      const double *dot_part, int32_t ndot, double *rr,
+                      int32_t nparts, int32_t par, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cg_update, dim3(nparts), dim3(kBlock), 0, s, n, sc, p,
-                       q, x, r, part);
+                       q, x, r, dot_part, ndot, rr, nparts, par);
     check_launch("k_cg_update");
 }
 
-void launch_cg_beta(const double *part, int32_t nparts, CgScalars *sc,
-                    hipStream_t s)
+void launch_cg_xpay(int64_t n, CgScalars *sc, const double *r, double *p,
+                    const double *rr, int32_t nparts, int32_t par, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, part, nparts, sc);
-    check_launch("k_cg_beta");
-}
-
-void launch_cg_xpay(int64_t n, const CgScalars *sc, const double *r,
-                    double *p, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cg_xpay, dim3(blas1_parts(n)), dim3(kBlock), 0, s, n,
-                       sc, r, p);
+    hipLaunchKernelGGL(k_cg_xpay, dim3(nparts), dim3(kBlock), 0, s, n, sc, r, p,
+                       rr, nparts, par);
     check_launch("k_cg_xpay");
 }
 

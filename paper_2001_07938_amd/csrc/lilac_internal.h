@@ -269,19 +269,19 @@ struct CgScalars {
     int32_t done, iters;
     int32_t pad[2];
 };
+// CG iteration k is three launches: the product q = A p with fused p.q
+// partials, then these two; rr holds r.r partials for two parities
+// (kDotParts each), so no scalar is written by one workgroup while others
+// read it.
 void launch_cg_init(int64_t n, const double *b, double *x, double *r,
-                    double *p, double *part, int32_t nparts, hipStream_t s);
-void launch_cg_start(const double *part, int32_t nparts, CgScalars *sc,
-                     hipStream_t s);
-void launch_cg_alpha(const double *part, int32_t nparts, CgScalars *sc,
-                     hipStream_t s);
-void launch_cg_update(int64_t n, const CgScalars *sc, const double *p,
-                      const double *q, double *x, double *r, double *part,
-                      int32_t nparts, hipStream_t s);
-void launch_cg_beta(const double *part, int32_t nparts, CgScalars *sc,
+                    double *p, double *rr, int32_t nparts, CgScalars *sc,
                     hipStream_t s);
-void launch_cg_xpay(int64_t n, const CgScalars *sc, const double *r,
-                    double *p, hipStream_t s);
+void launch_cg_update(int64_t n, CgScalars *sc, const double *p,
+                      const double *q, double *x, double *r,
+                      const double *dot_part, int32_t ndot, double *rr,
+                      int32_t nparts, int32_t par, hipStream_t s);
+void launch_cg_xpay(int64_t n, CgScalars *sc, const double *r, double *p,
+                    const double *rr, int32_t nparts, int32_t par, hipStream_t s);
 int32_t blas1_parts(int64_t n);
 // Workgroups of the tile kernel resident per compute unit.
 int occupancy_tiles(lilac_dtype dt);

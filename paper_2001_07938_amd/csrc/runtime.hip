@@ -298,12 +298,14 @@ static int64_t analysis_bytes(const CsrHandle &h)
 // Panels of x that fit the LDS budget: 2^log2w columns of the value type.
 static int32_t panel_log2w(lilac_dtype dt) { return dt == LILAC_F32 ? 14 : 13; }
 
-// Whether the column-panel layout suits the matrix: at least 8 entries per
-// row and panel on average, few panels, and no row too long for one lane
-// group (rows in the wavefront class at most).
+// Whether the column-panel layout suits the matrix: enough rows to fill the
+// GPU with row blocks, at least 8 entries per row and panel on average, few
+// panels, and no row too long for one lane group (rows in the wavefront
+// class at most).  Smaller matrices stay on the row-class tiles, which also
+// lets grouped launches take them in one kernel.
 static bool panels_eligible(const CsrHandle &h)
 {
-    if (h.rows == 0 || h.nnz == 0)
+    if (h.rows < 32768 || h.nnz == 0)
         return false;
     const int64_t np = ((int64_t)h.cols + (1 << panel_log2w(h.dt)) - 1) >> panel_log2w(h.dt);
     if (np < 1 || np > 64)
@@ -916,7 +918,7 @@ static void cg_prepare(CsrHandle &h)
         st->r = (double *)dev_alloc((size_t)h.rows * 8);
         st->p = (double *)dev_alloc((size_t)h.rows * 8);
         st->q = (double *)dev_alloc((size_t)h.rows * 8);
-        st->part = (double *)dev_alloc((size_t)kDotParts * 8);
+        st->part = (double *)dev_alloc((size_t)2 * kDotParts * 8);
         st->sc = (CgScalars *)dev_alloc(sizeof(CgScalars));
     } catch (...) {
         dev_free(st->r);
@@ -929,9 +931,9 @@ static void cg_prepare(CsrHandle &h)
     h.cg = st;
 }
 
-// One whole solve: initialisation, then `iters` iterations of five kernels
-// (product with fused p.q partials, alpha, x/r update with r.r partials,
-// beta, direction update).  Scalars never leave the device.
+// One whole solve: initialisation, then `iters` iterations of three kernels
+// (product with fused p.q partials; alpha and the x/r update with r.r
+// partials; beta and the direction update).  Scalars never leave the device.
 static void cg_enqueue(const CsrHandle &h, const double *b, double *x,
                        int iters, hipStream_t s)
 {
@@ -939,14 +941,12 @@ static void cg_enqueue(const CsrHandle &h, const double *b, double *x,
     const int64_t n = h.rows;
     const int32_t np = blas1_parts(n);
     const int32_t ndot = h.grid + h.fin_blocks;
-    launch_cg_init(n, b, x, st.r, st.p, st.part, np, s);
-    launch_cg_start(st.part, np, st.sc, s);
+    launch_cg_init(n, b, x, st.r, st.p, st.part, np, st.sc, s);
     for (int it = 0; it < iters; ++it) {
         spmv_enqueue(h, st.p, st.q, epi_none(), st.p, true, s);
-        launch_cg_alpha(h.d_dot_part, ndot, st.sc, s);
-        launch_cg_update(n, st.sc, st.p, st.q, x, st.r, st.part, np, s);
-        launch_cg_beta(st.part, np, st.sc, s);
-        launch_cg_xpay(n, st.sc, st.r, st.p, s);
+        launch_cg_update(n, st.sc, st.p, st.q, x, st.r, h.d_dot_part, ndot,
+                         st.part, np, it & 1, s);
+        launch_cg_xpay(n, st.sc, st.r, st.p, st.part, np, it & 1, s);
     }
 }
 

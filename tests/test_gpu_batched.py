@@ -86,7 +86,7 @@ def test_tuner_keeps_results_in_tolerance():
 
 
 def test_batched_with_panel_matrices_bitwise():
-    mats = [gen.spd_random(20000, 60, seed=21), gen.stencil(12, 7),
+    mats = [gen.spd_random(40000, 60, seed=21), gen.stencil(12, 7),
             gen.uniform_rows(4096, 16), gen.random_rows(8000, 5, 60, seed=22)]
     hs = [L.Csr.from_gen(A) for A in mats]
     assert hs[0].info().layout == L.LAYOUT_PANELS

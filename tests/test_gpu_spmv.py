@@ -285,7 +285,7 @@ def test_panel_layout_parity(name):
 
 
 def test_panel_layout_f32_and_fused_dot():
-    A = gen.spd_random(20000, 60, seed=6)
+    A = gen.spd_random(40000, 60, seed=6)
     h = L.Csr.from_gen(A)
     assert h.info().layout == L.LAYOUT_PANELS  # chosen automatically
     x = gen.vector(A.cols, 63)
@@ -310,7 +310,7 @@ def test_panel_layout_f32_and_fused_dot():
 def test_panel_layout_unaligned_x():
     """x starting 8 bytes past a 16-byte boundary takes the scalar staging
     path of the panel kernel."""
-    A = gen.spd_random(20000, 60, seed=6)
+    A = gen.spd_random(40000, 60, seed=6)
     h = L.Csr.from_gen(A)
     x = gen.vector(A.cols, 66)
     buf = torch.empty(A.cols + 1, dtype=torch.float64, device=DEV)
