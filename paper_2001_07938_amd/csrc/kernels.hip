@@ -626,6 +626,126 @@ __global__ __launch_bounds__(kBlock) void k_bfs_step(
     }
 }
 
+// --------------------------------------------------- graph relabelling
+
+__global__ __launch_bounds__(kBlock) void k_count_cols(int64_t nnz,
+                                                       const int32_t *__restrict__ col,
+                                                       int32_t *__restrict__ deg)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * kBlock)
+        atomicAdd(&deg[col[k]], 1);
+}
+
+// key 0 holds the largest degrees (2^31..), key 31 degree 1, key 32 degree 0
+__global__ __launch_bounds__(kBlock) void k_degree_keys(int32_t n,
+                                                        const int32_t *__restrict__ deg,
+                                                        int32_t *__restrict__ key)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const int32_t d = deg[i];
+        key[i] = (d <= 0) ? 32 : __clz(d);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_key_hist(int32_t n,
+                                                     const int32_t *__restrict__ key,
+                                                     int32_t *__restrict__ hist,
+                                                     int32_t nblk)
+{
+    __shared__ int32_t cnt[kDegKeys];
+    if (threadIdx.x < kDegKeys)
+        cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        atomicAdd(&cnt[key[i]], 1);
+    __syncthreads();
+    if (threadIdx.x < kDegKeys)
+        hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable placement by key (same scheme as the row-class scatter).
+__global__ __launch_bounds__(kBlock) void k_key_scatter(int32_t n,
+                                                        const int32_t *__restrict__ key,
+                                                        const int32_t *__restrict__ hist,
+                                                        int32_t nblk,
+                                                        int32_t *__restrict__ newid)
+{
+    __shared__ int32_t wcnt[kWaves][kDegKeys];
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t c = (i < n) ? key[i] : -1;
+    const unsigned long long below = (lane == 0) ? 0ull : ((1ull << lane) - 1ull);
+    int32_t rank = 0;
+    for (int b = 0; b < kDegKeys; ++b) {
+        const unsigned long long m = __ballot(c == b);
+        if (lane == 0)
+            wcnt[wave][b] = __popcll(m);
+        if (c == b)
+            rank = __popcll(m & below);
+    }
+    __syncthreads();
+    if (c >= 0) {
+        int32_t off = hist[c * nblk + blockIdx.x];
+        for (int w = 0; w < wave; ++w)
+            off += wcnt[w][c];
+        newid[i] = off + rank;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_perm_lengths(int32_t rows,
+                                                         const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ newid,
+                                                         int32_t *__restrict__ len2)
+{
+    const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v < rows)
+        len2[newid[v]] = rp[v + 1] - rp[v];
+    else if (v == rows)
+        len2[rows] = 0;
+}
+
+// One thread per entry: its row by binary search in row_ptr.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_perm_entries(
+    int32_t rows, int64_t nnz, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const V *__restrict__ vals,
+    const int32_t *__restrict__ newid, const int32_t *__restrict__ rp2,
+    int32_t *__restrict__ col2, V *__restrict__ vals2)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * kBlock) {
+        int32_t lo = 0, hi = rows;  // rp[lo] <= k < rp[hi]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (rp[mid] <= k)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t dst = (int64_t)rp2[newid[lo]] + (k - rp[lo]);
+        col2[dst] = newid[col[k]];
+        vals2[dst] = vals[k];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_permute_f32(int32_t n,
+                                                        const int32_t *__restrict__ newid,
+                                                        const float *__restrict__ in,
+                                                        float *__restrict__ out, int to)
+{
+    const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v < n) {
+        if (to)
+            out[newid[v]] = in[v];
+        else
+            out[v] = in[newid[v]];
+    }
+}
+
 // ------------------------------------------------------------------ JDS
 
 // Thread p handles the row at JDS position p: diagonal j holds its j-th
@@ -1361,6 +1481,71 @@ void launch_invert_perm(int32_t rows, const int32_t *perm, int32_t *iperm,
     hipLaunchKernelGGL(k_invert_perm, dim3(grid_for(rows, kBlock, INT_MAX)), dim3(kBlock),
                        0, s, rows, perm, iperm);
     check_launch("k_invert_perm");
+}
+
+void launch_count_cols(int64_t nnz, const int32_t *col, int32_t *deg, hipStream_t s)
+{
+    if (nnz <= 0)
+        return;
+    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, kBlock * 8, 8192)), dim3(kBlock),
+                       0, s, nnz, col, deg);
+    check_launch("k_count_cols");
+}
+
+void launch_degree_keys(int32_t n, const int32_t *deg, int32_t *key, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n, kBlock, INT_MAX)), dim3(kBlock),
+                       0, s, n, deg, key);
+    check_launch("k_degree_keys");
+}
+
+void launch_key_hist(int32_t n, const int32_t *key, int32_t *hist, int32_t nblk,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_key_hist, dim3(nblk), dim3(kBlock), 0, s, n, key, hist, nblk);
+    check_launch("k_key_hist");
+}
+
+void launch_key_scatter(int32_t n, const int32_t *key, const int32_t *hist,
+                        int32_t nblk, int32_t *newid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_key_scatter, dim3(nblk), dim3(kBlock), 0, s, n, key, hist,
+                       nblk, newid);
+    check_launch("k_key_scatter");
+}
+
+void launch_perm_lengths(int32_t rows, const int32_t *rp, const int32_t *newid,
+                         int32_t *len2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_perm_lengths, dim3(grid_for((int64_t)rows + 1, kBlock, INT_MAX)),
+                       dim3(kBlock), 0, s, rows, rp, newid, len2);
+    check_launch("k_perm_lengths");
+}
+
+void launch_perm_entries(lilac_dtype dt, int32_t rows, int64_t nnz, const int32_t *rp,
+                         const int32_t *col, const void *vals, const int32_t *newid,
+                         const int32_t *rp2, int32_t *col2, void *vals2, hipStream_t s)
+{
+    if (nnz <= 0)
+        return;
+    dim3 g(grid_for(nnz, kBlock, 65536)), b(kBlock);
+    if (dt == LILAC_F64)
+        hipLaunchKernelGGL(k_perm_entries<double>, g, b, 0, s, rows, nnz, rp, col,
+                           (const double *)vals, newid, rp2, col2, (double *)vals2);
+    else
+        hipLaunchKernelGGL(k_perm_entries<float>, g, b, 0, s, rows, nnz, rp, col,
+                           (const float *)vals, newid, rp2, col2, (float *)vals2);
+    check_launch("k_perm_entries");
+}
+
+void launch_permute_f32(int32_t n, const int32_t *newid, const float *in, float *out,
+                        bool to, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_permute_f32, dim3(grid_for(n, kBlock, INT_MAX)), dim3(kBlock), 0,
+                       s, n, newid, in, out, to ? 1 : 0);
+    check_launch("k_permute_f32");
 }
 
 int32_t cg_seg_blocks(int64_t n) { return grid_for(n, kBlock, kBlock); }

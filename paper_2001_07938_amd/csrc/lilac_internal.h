@@ -249,6 +249,27 @@ void launch_bfs_step(const Tile *tiles, int32_t ntiles, int32_t grid,
                      const MatDesc &m, int32_t *level, int32_t depth,
                      int32_t *changed, hipStream_t s);
 
+// Relabelling of a graph's vertices by decreasing out-degree (locality of the
+// gathered vector): deg[u] = entries in column u; key = bucket of deg
+// (powers of two, largest first); newid = stable position by key.
+void launch_count_cols(int64_t nnz, const int32_t *col, int32_t *deg, hipStream_t s);
+void launch_degree_keys(int32_t n, const int32_t *deg, int32_t *key, hipStream_t s);
+constexpr int kDegKeys = 33;
+void launch_key_hist(int32_t n, const int32_t *key, int32_t *hist, int32_t nblk,
+                     hipStream_t s);
+void launch_key_scatter(int32_t n, const int32_t *key, const int32_t *hist,
+                        int32_t nblk, int32_t *newid, hipStream_t s);
+// Permuted copy: row newid[v] of the output is row v of the input with its
+// columns renamed by newid (entries keep their order).
+void launch_perm_lengths(int32_t rows, const int32_t *rp, const int32_t *newid,
+                         int32_t *len2, hipStream_t s);
+void launch_perm_entries(lilac_dtype dt, int32_t rows, int64_t nnz, const int32_t *rp,
+                         const int32_t *col, const void *vals, const int32_t *newid,
+                         const int32_t *rp2, int32_t *col2, void *vals2, hipStream_t s);
+// out[newid[v]] = in[v] (to = true) or out[v] = in[newid[v]] (to = false)
+void launch_permute_f32(int32_t n, const int32_t *newid, const float *in, float *out,
+                        bool to, hipStream_t s);
+
 // Jagged Diagonal Storage product, every sum in diagonal order without
 // contraction (bitwise equal to the sequential definition).
 void launch_spmv_jds(int32_t rows, int32_t max_len, int32_t nnz,

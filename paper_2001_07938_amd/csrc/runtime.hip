@@ -584,6 +584,10 @@ struct CgState {
 
 struct PrState {
     float *tmp = nullptr;
+    // vertices relabelled by decreasing out-degree (large graphs)
+    CsrHandle *g = nullptr;
+    int32_t *newid = nullptr;
+    float *xp = nullptr;
     struct G {
         float *x;
         int iters;
@@ -596,6 +600,15 @@ struct PrState {
 
 static void drop_graphs(CsrHandle &h)
 {
+    if (h.pr && h.pr->g) {
+        // the relabelled copy follows the matrix: rebuild it on next use
+        destroy_handle(h.pr->g);
+        h.pr->g = nullptr;
+        dev_free(h.pr->newid);
+        dev_free(h.pr->xp);
+        h.pr->newid = nullptr;
+        h.pr->xp = nullptr;
+    }
     if (h.cg) {
         for (auto &g : h.cg->graphs) {
             (void)hipGraphExecDestroy(g.exec);
@@ -631,6 +644,10 @@ void destroy_handle(CsrHandle *h)
     }
     if (h->pr) {
         dev_free(h->pr->tmp);
+        dev_free(h->pr->newid);
+        dev_free(h->pr->xp);
+        if (h->pr->g)
+            destroy_handle(h->pr->g);
         delete h->pr;
     }
     free_analysis(*h);
@@ -1031,6 +1048,62 @@ void run_cg(CsrHandle &h, const double *b, double *x, int iters,
 
 // ================================================================ PageRank
 
+// Graphs with at least this many vertices are iterated on a copy relabelled
+// by out-degree.
+constexpr int32_t kRelabelRows = 65536;
+
+// Copy of a square graph matrix with its vertices renamed in decreasing
+// out-degree order (stable): the most gathered entries of x become
+// neighbours in memory and stay in cache.  (P A P^T)(P x) = P (A x).
+static void build_relabel(CsrHandle &h, PrState &st)
+{
+    Context &c = ctx();
+    hipStream_t s = c.stream;
+    const int32_t n = h.rows;
+    const int32_t nblk = (n + kBlock - 1) / kBlock;
+    int32_t *deg = nullptr, *key = nullptr, *hist = nullptr, *rp2 = nullptr,
+            *col2 = nullptr;
+    void *vals2 = nullptr;
+    try {
+        deg = (int32_t *)dev_alloc((size_t)n * 4);
+        key = (int32_t *)dev_alloc((size_t)n * 4);
+        hist = (int32_t *)dev_alloc((size_t)kDegKeys * nblk * 4);
+        st.newid = (int32_t *)dev_alloc((size_t)n * 4);
+        launch_fill_i32(deg, n, 0, s);
+        launch_count_cols(h.nnz, h.d_col, deg, s);
+        launch_degree_keys(n, deg, key, s);
+        launch_key_hist(n, key, hist, nblk, s);
+        launch_scan_excl(hist, (int64_t)kDegKeys * nblk, nullptr, s);
+        launch_key_scatter(n, key, hist, nblk, st.newid, s);
+        rp2 = (int32_t *)dev_alloc((size_t)(n + 1) * 4);
+        launch_perm_lengths(n, h.d_row_ptr, st.newid, rp2, s);
+        const int64_t total = scan_total(rp2, (int64_t)n + 1, s);
+        if (total != h.nnz)
+            fail(LILAC_ERR_DEVICE, "relabelled copy lost entries");
+        col2 = (int32_t *)dev_alloc((size_t)std::max<int64_t>(h.nnz, 1) * 4);
+        vals2 = dev_alloc((size_t)std::max<int64_t>(h.nnz, 1) * 4);
+        launch_perm_entries(h.dt, n, h.nnz, h.d_row_ptr, h.d_col, h.d_vals, st.newid,
+                            rp2, col2, vals2, s);
+        HIPC(hipStreamSynchronize(s));
+        st.g = create_handle(n, h.cols, h.nnz, rp2, col2, vals2, h.dt, 0);
+        st.xp = (float *)dev_alloc((size_t)n * 4);
+    } catch (...) {
+        dev_free(deg);
+        dev_free(key);
+        dev_free(hist);
+        dev_free(rp2);
+        dev_free(col2);
+        dev_free(vals2);
+        throw;
+    }
+    dev_free(deg);
+    dev_free(key);
+    dev_free(hist);
+    dev_free(rp2);
+    dev_free(col2);
+    dev_free(vals2);
+}
+
 static void run_pagerank(CsrHandle &h, float d, int iters, float *x,
                          hipStream_t s)
 {
@@ -1069,7 +1142,21 @@ static void run_pagerank(CsrHandle &h, float d, int iters, float *x,
         PrState::G g{x, iters, d, nullptr, nullptr};
         const Epi epi{EPI_PAGERANK, 0, (double)d,
                       (1.0 - (double)d) / (double)h.rows};
+        const bool relabel = h.rows >= kRelabelRows && h.rows == h.cols;
+        if (relabel && !st.g)
+            build_relabel(h, st);
         capture(g.graph, g.exec, [&](hipStream_t cs) {
+            if (relabel) {
+                // iterate on the relabelled copy: x' = P x, ..., x = P^T x'
+                launch_permute_f32(h.rows, st.newid, x, st.xp, true, cs);
+                float *cur = st.xp, *nxt = st.tmp;
+                for (int it = 0; it < iters; ++it) {
+                    spmv_enqueue(*st.g, cur, nxt, epi, nullptr, false, cs);
+                    std::swap(cur, nxt);
+                }
+                launch_permute_f32(h.rows, st.newid, cur, x, false, cs);
+                return;
+            }
             float *cur = x, *nxt = st.tmp;
             for (int it = 0; it < iters; ++it) {
                 spmv_enqueue(h, cur, nxt, epi, nullptr, false, cs);
