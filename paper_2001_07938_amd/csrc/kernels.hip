@@ -31,6 +31,54 @@ __device__ __forceinline__ double dpp_f64(double v)
                             __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
 }
 
+// DPP move with a row mask; lanes of masked rows (or with no source) get
+// `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int32_t dpp_i32(int32_t v, int32_t old)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64m(double v, double old)
+{
+    return __hiloint2double(
+        __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWS, 0xF, false),
+        __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWS, 0xF, false));
+}
+
+// One step of a segmented inclusive scan over a wavefront whose keys
+// ascend along the lanes: add the partial of the source lane when it has
+// the same key (monotone keys: the whole span between has that key).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(double &val, int32_t key)
+{
+    const double t = dpp_f64m<CTRL, ROWS>(val, 0.0);
+    const int32_t tk = dpp_i32<CTRL, ROWS>(key, -1);
+    if (tk == key)
+        val += t;
+}
+
+// Segmented inclusive scan by key over the 64 lanes (keys ascending): row
+// shifts by 1, 2, 4, 8 inside each row of 16, then the last lane of row 0
+// (and of row 2) into rows 1 (and 3), then lane 31 into rows 2 and 3.
+__device__ __forceinline__ double seg_scan64(double val, int32_t key)
+{
+    seg_step<0x111, 0xF>(val, key);  // row_shr:1
+    seg_step<0x112, 0xF>(val, key);  // row_shr:2
+    seg_step<0x114, 0xF>(val, key);  // row_shr:4
+    seg_step<0x118, 0xF>(val, key);  // row_shr:8
+    seg_step<0x142, 0xA>(val, key);  // row_bcast:15 into rows 1 and 3
+    seg_step<0x143, 0xC>(val, key);  // row_bcast:31 into rows 2 and 3
+    return val;
+}
+
+// Key of the next lane (wave_shl:1); the last lane gets -1.
+__device__ __forceinline__ int32_t next_lane_key(int32_t key)
+{
+    return __builtin_amdgcn_update_dpp(-1, key, 0x130, 0xF, 0xF, false);
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int lane)
 {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
@@ -409,97 +457,106 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
 
 // ------------------------------------------------------- column panels
 
-// Product over the column-panel layout.  Workgroup b owns row block b.  For
-// each panel it stages that slice of x in LDS (coalesced 16-byte loads), then
-// every group of 16 lanes walks the panel entries of its rows, gathering x
-// from LDS; each lane keeps one running sum per row across all panels, and
-// the 16 lane sums of a row are combined once at the end.  The order of the
-// additions depends only on the matrix and the layout.
+// Product over the column-panel layout.  Workgroup b owns row block b; for
+// each panel it stages that slice of x in LDS (the next slice is already on
+// its way in registers while the current one is used), and each wavefront
+// streams its own entries of the panel in coalesced 64-entry chunks: lane j
+// forms vals[k] * x[col] from LDS, a segmented scan over the 64 lanes (rows
+// ascend along the chunk) adds up each row's run, and the last lane of a run
+// adds it to the row's sum in LDS.  Rows belong to one wavefront, chunks
+// follow in order, panels follow in order: the additions are in a fixed order
+// given by the matrix and the layout.
 template <typename V, bool DOT>
-__global__ __launch_bounds__(kPanelThreads, 4) void k_spmv_panels(
+__global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
     PanelDesc pd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
     const V *__restrict__ w, double *__restrict__ dot_part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    V *xs = (V *)smem;
-    constexpr int G = kPanelThreads / kPanelLanes;  // lane groups
-    const int g = threadIdx.x / kPanelLanes;
-    const int l = threadIdx.x % kPanelLanes;
+    double *acc = (double *)smem;                                 // row sums
+    V *xs = (V *)(smem + kPanelMaxRb * sizeof(double));           // x panel
+    constexpr int VV = 16 / sizeof(V);
+    typedef V vec_t __attribute__((ext_vector_type(VV)));
+    constexpr int kStage = (panel_width(sizeof(V)) / VV + kPanelThreads - 1) / kPanelThreads;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int32_t b = blockIdx.x;
     const int32_t r0 = b * pd.rb;
     const int32_t nr = min(pd.rb, pd.rows - r0);
     const V *pv = (const V *)pd.vals;
-    const int32_t pw = 1 << pd.log2w;
-    double acc[kPanelRpg];
+    for (int i = threadIdx.x; i < kPanelMaxRb; i += kPanelThreads)
+        acc[i] = 0.0;
+    const bool aligned = (((uintptr_t)x) & 15) == 0;
+    vec_t stage[kStage];
+    auto load_stage = [&](int32_t p) {
+        const int32_t c0 = p * pd.pw;
+        const int32_t nvec = min(pd.pw, pd.cols - c0) / VV;
 #pragma unroll
-    for (int k = 0; k < kPanelRpg; ++k)
-        acc[k] = 0.0;
+        for (int j = 0; j < kStage; ++j) {
+            const int32_t i = threadIdx.x + j * kPanelThreads;
+            if (i < nvec)
+                stage[j] = *(const vec_t *)(x + c0 + i * VV);
+        }
+    };
+    if (aligned)
+        load_stage(0);
     for (int32_t p = 0; p < pd.np; ++p) {
-        // stage x[p*pw, p*pw + width) in LDS
-        const int32_t c0 = p * pw;
-        const int32_t width = min(pw, pd.cols - c0);
-        __syncthreads();
-        constexpr int VV = 16 / sizeof(V);
-        const bool aligned = (((uintptr_t)(x + c0)) & 15) == 0;
-        const int32_t nvec = aligned ? width / VV : 0;
-        for (int32_t i = threadIdx.x; i < nvec; i += kPanelThreads) {
-            typedef V vec_t __attribute__((ext_vector_type(VV)));
-            *(vec_t *)(xs + i * VV) = *(const vec_t *)(x + c0 + i * VV);
-        }
-        for (int32_t i = nvec * VV + threadIdx.x; i < width; i += kPanelThreads)
-            xs[i] = x[c0 + i];
-        __syncthreads();
-        const int32_t *ptr = pd.ptr + (int64_t)(b * pd.np + p) * (pd.rb + 1);
-        // lane l of the group fetches the bounds of the group's row l
-        const int32_t rl = g + l * G;
-        int32_t ps = 0, pe = 0;
-        if (l < kPanelRpg && rl < nr) {
-            ps = ptr[rl];
-            pe = ptr[rl + 1];
-        }
-        // rows in two halves of eight: the first entry of each row is
-        // loaded for all eight rows before any is used
+        const int32_t c0 = p * pd.pw;
+        const int32_t width = min(pd.pw, pd.cols - c0);
+        __syncthreads();  // the previous panel is no longer read
+        if (aligned) {
+            const int32_t nvec = width / VV;
 #pragma unroll
-        for (int h0 = 0; h0 < kPanelRpg; h0 += 8) {
-            int32_t s[8], e[8];
-            V v[8];
-            uint16_t c[8];
+            for (int j = 0; j < kStage; ++j) {
+                const int32_t i = threadIdx.x + j * kPanelThreads;
+                if (i < nvec)
+                    *(vec_t *)(xs + i * VV) = stage[j];
+            }
+            for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
+                xs[e] = x[c0 + e];
+            if (p + 1 < pd.np)
+                load_stage(p + 1);
+        } else {
+            for (int32_t e = threadIdx.x; e < width; e += kPanelThreads)
+                xs[e] = x[c0 + e];
+        }
+        __syncthreads();  // the panel is in LDS
+        const int32_t *wp = pd.wptr + ((int64_t)b * pd.np + p) * (kPanelWaves + 1);
+        const int32_t ks = wp[wave];
+        const int32_t ke = wp[wave + 1];
+        for (int32_t base = ks; base < ke; base += 64 * kPanelChunks) {
+            V v[kPanelChunks];
+            uint32_t rc[kPanelChunks];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                s[k] = __shfl(ps, h0 + k, kPanelLanes);
-                e[k] = __shfl(pe, h0 + k, kPanelLanes);
-                const int32_t j = s[k] + l;
-                const int32_t ja = (j < e[k]) ? j : s[k];
-                v[k] = ld_stream(pv + ja);
-                c[k] = ld_stream(pd.col + ja);
+            for (int u = 0; u < kPanelChunks; ++u) {
+                const int32_t k = base + u * 64 + lane;
+                const int32_t kk = (k < ke) ? k : ks;
+                v[u] = ld_stream(pv + kk);
+                rc[u] = ld_stream(pd.rc + kk);
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (s[k] + l < e[k])
-                    acc[h0 + k] = fma((double)v[k], (double)xs[c[k]], acc[h0 + k]);
-            // rows with more than 16 entries in this panel
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                for (int32_t j = s[k] + kPanelLanes + l; j < e[k]; j += kPanelLanes)
-                    acc[h0 + k] = fma((double)ld_stream(pv + j),
-                                      (double)xs[ld_stream(pd.col + j)], acc[h0 + k]);
+            for (int u = 0; u < kPanelChunks; ++u) {
+                if (base + u * 64 >= ke)
+                    break;  // uniform: nothing left for this wavefront
+                const bool valid = base + u * 64 + lane < ke;
+                const int32_t row = valid ? (int32_t)(rc[u] >> 16) : kPanelMaxRb;
+                double val = valid ? (double)v[u] * (double)xs[rc[u] & 0xFFFFu] : 0.0;
+                val = seg_scan64(val, row);
+                const int32_t next = next_lane_key(row);
+                if (next != row && row < kPanelMaxRb)
+                    acc[row] += val;
+            }
         }
     }
+    __syncthreads();
     double dacc = 0.0;
-#pragma unroll
-    for (int k = 0; k < kPanelRpg; ++k) {
-        const double sum = lane_group_sum<kPanelLanes>(acc[k]);
-        const int32_t rl = g + k * G;
-        if (l == 0 && rl < nr) {
-            const V out = epilogue<V>(sum, epi);
-            y[r0 + rl] = out;
-            if (DOT)
-                dacc = fma((double)w[r0 + rl], (double)out, dacc);
-        }
+    for (int32_t i = threadIdx.x; i < nr; i += kPanelThreads) {
+        const V out = epilogue<V>(acc[i], epi);
+        y[r0 + i] = out;
+        if (DOT)
+            dacc = fma((double)w[r0 + i], (double)out, dacc);
     }
     if (DOT) {
-        __syncthreads();  // the panel buffer is reused for the reduction
-        const double tot = block_sum<kPanelThreads / 64>(dacc, (double *)smem);
+        const double tot = block_sum<kPanelWaves>(dacc, (double *)xs);
         if (threadIdx.x == 0)
             dot_part[blockIdx.x] = tot;
     }
@@ -519,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_count(PanelDesc pd,
     for (int32_t p = 0; p < pd.np; ++p) {
         int32_t n = 0;
         for (int32_t k = a; k < e; ++k)
-            n += ((col[k] >> pd.log2w) == p) ? 1 : 0;
+            n += (col[k] / pd.pw == p) ? 1 : 0;
         cnt[(int64_t)(b * pd.np + p) * (pd.rb + 1) + rl] = n;
     }
 }
@@ -529,25 +586,38 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_panel_scatter(
     PanelDesc pd, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ vals, const int32_t *__restrict__ ptr,
-    V *__restrict__ pv, uint16_t *__restrict__ pc)
+    V *__restrict__ pv, uint32_t *__restrict__ prc)
 {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= pd.rows)
         return;
     const int32_t b = i / pd.rb, rl = i - b * pd.rb;
     const int32_t a = rp[i], e = rp[i + 1];
-    const int32_t mask = (1 << pd.log2w) - 1;
     for (int32_t p = 0; p < pd.np; ++p) {
         int32_t pos = ptr[(int64_t)(b * pd.np + p) * (pd.rb + 1) + rl];
         for (int32_t k = a; k < e; ++k) {
             const int32_t cc = col[k];
-            if ((cc >> pd.log2w) == p) {
+            if (cc / pd.pw == p) {
                 pv[pos] = vals[k];
-                pc[pos] = (uint16_t)(cc & mask);
+                prc[pos] = ((uint32_t)rl << 16) | (uint32_t)(cc - p * pd.pw);
                 ++pos;
             }
         }
     }
+}
+
+// Where each wavefront's rows start, for every (row block, panel).
+__global__ __launch_bounds__(kBlock) void k_panel_wptr(PanelDesc pd,
+                                                       const int32_t *__restrict__ ptr,
+                                                       int32_t *__restrict__ wptr)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nseg = (int64_t)pd.nblk * pd.np;
+    if (t >= nseg * (kPanelWaves + 1))
+        return;
+    const int64_t seg = t / (kPanelWaves + 1);
+    const int32_t wv = (int32_t)(t - seg * (kPanelWaves + 1));
+    wptr[t] = ptr[seg * (pd.rb + 1) + min(wv * pd.rw, pd.rb)];
 }
 
 // ------------------------------------------------------------------ BFS
@@ -1412,15 +1482,15 @@ void launch_spmv_panels(lilac_dtype dt, const PanelDesc &pd, const void *x,
     dim3 g(pd.nblk), b(kPanelThreads);
     if (dt == LILAC_F64) {
         if (dot_part)
-            hipLaunchKernelGGL((k_spmv_panels<double, true>), g, b, kPanelBytes, s, pd,
+            hipLaunchKernelGGL((k_spmv_panels<double, true>), g, b, kPanelLds, s, pd,
                                (const double *)x, (double *)y, epi, (const double *)w, dot_part);
         else
-            hipLaunchKernelGGL((k_spmv_panels<double, false>), g, b, kPanelBytes, s, pd,
+            hipLaunchKernelGGL((k_spmv_panels<double, false>), g, b, kPanelLds, s, pd,
                                (const double *)x, (double *)y, epi, (const double *)w, dot_part);
     } else {
         if (dot_part)
             fail(LILAC_ERR_UNSUPPORTED, "fused dot is only provided for float64");
-        hipLaunchKernelGGL((k_spmv_panels<float, false>), g, b, kPanelBytes, s, pd,
+        hipLaunchKernelGGL((k_spmv_panels<float, false>), g, b, kPanelLds, s, pd,
                            (const float *)x, (float *)y, epi, (const float *)w, dot_part);
     }
     check_launch("k_spmv_panels");
@@ -1436,16 +1506,25 @@ void launch_panel_count(const PanelDesc &pd, const int32_t *rp,
 
 void launch_panel_scatter(lilac_dtype dt, const PanelDesc &pd, const int32_t *rp,
                           const int32_t *col, const void *vals, const int32_t *ptr,
-                          void *pv, uint16_t *pc, hipStream_t s)
+                          void *pv, uint32_t *prc, hipStream_t s)
 {
     dim3 g(grid_for(pd.rows, kBlock, INT_MAX)), b(kBlock);
     if (dt == LILAC_F64)
         hipLaunchKernelGGL(k_panel_scatter<double>, g, b, 0, s, pd, rp, col,
-                           (const double *)vals, ptr, (double *)pv, pc);
+                           (const double *)vals, ptr, (double *)pv, prc);
     else
         hipLaunchKernelGGL(k_panel_scatter<float>, g, b, 0, s, pd, rp, col,
-                           (const float *)vals, ptr, (float *)pv, pc);
+                           (const float *)vals, ptr, (float *)pv, prc);
     check_launch("k_panel_scatter");
+}
+
+void launch_panel_wptr(const PanelDesc &pd, const int32_t *ptr, int32_t *wptr,
+                       hipStream_t s)
+{
+    const int64_t n = (int64_t)pd.nblk * pd.np * (kPanelWaves + 1);
+    hipLaunchKernelGGL(k_panel_wptr, dim3(grid_for(n, kBlock, INT_MAX)), dim3(kBlock),
+                       0, s, pd, ptr, wptr);
+    check_launch("k_panel_wptr");
 }
 
 void launch_bfs_step(const Tile *tiles, int32_t ntiles, int32_t grid,

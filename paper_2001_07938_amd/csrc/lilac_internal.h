@@ -91,23 +91,31 @@ struct Plan {
 // CSR arrays, or column panels (x staged in LDS one panel at a time).
 enum : int32_t { LAYOUT_AUTO = -1, LAYOUT_ROWS = 0, LAYOUT_PANELS = 1 };
 
-// Column-panel layout: the columns are cut into panels of 2^log2w; the rows
-// into blocks of `rb`.  For row block b and panel p, the entries of the
-// block's rows that fall in the panel are stored together, row by row (each
-// row's entries in their CSR order), with 16-bit column offsets inside the
-// panel; ptr[(b*np + p)*(rb+1) + r] is where row r of the block starts.
+// Column-panel layout: the columns are cut into panels of `pw` (a panel of
+// x fits the LDS), the rows into blocks of `rb`.  Within row block b and
+// panel p the entries are stored row by row (each row's entries in their
+// CSR order), with the row inside the block and the column inside the panel
+// packed into 32 bits, (row << 16) | col.  Each of the eight wavefronts of a
+// workgroup owns `rw` consecutive rows of the block; wptr[(b*np + p)*9 + w]
+// is where wavefront w's entries of panel p start (entry 8: the end).
 struct PanelDesc {
     const void *vals;
-    const uint16_t *col;
-    const int32_t *ptr;
+    const uint32_t *rc;
+    const int32_t *wptr;
     int32_t rows, cols;
-    int32_t log2w, np, rb, nblk;
+    int32_t pw, np, rb, nblk, rw;
+    int32_t pad;
 };
-constexpr int kPanelThreads = 512;   // 8 wave64 per workgroup
-constexpr int kPanelLanes = 16;      // lanes per row inside a panel
-constexpr int kPanelRpg = 16;        // rows per lane group (at most)
-constexpr int kPanelMaxRb = (kPanelThreads / kPanelLanes) * kPanelRpg;
-constexpr int kPanelBytes = 65536;   // LDS for one panel of x
+constexpr int kPanelThreads = 512;             // 8 wave64 per workgroup
+constexpr int kPanelWaves = kPanelThreads / 64;
+constexpr int kPanelMaxRb = 512;               // rows per block (sums in LDS)
+constexpr int kPanelLds = 65536;               // LDS of one workgroup
+constexpr int kPanelChunks = 4;                // 64-entry chunks in flight
+// widest panel (elements) for a value size
+constexpr int panel_width(int vsize)
+{
+    return (kPanelLds - kPanelMaxRb * 8) / vsize;
+}
 
 Plan default_plan();
 
@@ -135,8 +143,8 @@ struct CsrHandle {
     bool use_panels = false;
     PanelDesc pan{};
     void *d_pv = nullptr;
-    uint16_t *d_pc = nullptr;
-    int32_t *d_pptr = nullptr;
+    uint32_t *d_prc = nullptr;
+    int32_t *d_pw = nullptr;
     std::vector<int32_t> bin_off;   // NCLASS+1
     int64_t nchunks = 0;
     int32_t nsplit = 0;
@@ -206,7 +214,9 @@ void launch_panel_count(const PanelDesc &pd, const int32_t *rp,
                         const int32_t *col, int32_t *cnt, hipStream_t s);
 void launch_panel_scatter(lilac_dtype dt, const PanelDesc &pd, const int32_t *rp,
                           const int32_t *col, const void *vals, const int32_t *ptr,
-                          void *pv, uint16_t *pc, hipStream_t s);
+                          void *pv, uint32_t *prc, hipStream_t s);
+void launch_panel_wptr(const PanelDesc &pd, const int32_t *ptr, int32_t *wptr,
+                       hipStream_t s);
 // Finaliser for split rows: single matrix (items == null, n = nsplit) or a
 // list of (matrix, split row) items for grouped launches.
 void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,

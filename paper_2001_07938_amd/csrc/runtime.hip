@@ -273,8 +273,8 @@ static void free_analysis(CsrHandle &h)
     dev_free_reset(h.d_tiles);
     dev_free_reset(h.d_dot_part);
     dev_free_reset(h.d_pv);
-    dev_free_reset(h.d_pc);
-    dev_free_reset(h.d_pptr);
+    dev_free_reset(h.d_prc);
+    dev_free_reset(h.d_pw);
     h.use_panels = false;
     h.pan = PanelDesc{};
     h.ntiles = 0;
@@ -290,13 +290,17 @@ static int64_t analysis_bytes(const CsrHandle &h)
                 (int64_t)(h.nsplit + 1) * 4 + (int64_t)h.ntiles * sizeof(Tile) +
                 (int64_t)(h.grid + h.fin_blocks) * 8;
     if (h.use_panels)
-        b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 2) +
-             (int64_t)h.pan.nblk * h.pan.np * (h.pan.rb + 1) * 4;
+        b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 4) +
+             (int64_t)h.pan.nblk * h.pan.np * (kPanelWaves + 1) * 4;
     return b;
 }
 
-// Panels of x that fit the LDS budget: 2^log2w columns of the value type.
-static int32_t panel_log2w(lilac_dtype dt) { return dt == LILAC_F32 ? 14 : 13; }
+// Columns per panel: a panel of x and the row sums fill the LDS.
+static int32_t panel_cols(lilac_dtype dt) { return panel_width((int)dtype_size(dt)); }
+static int64_t panel_count(const CsrHandle &h)
+{
+    return h.cols > 0 ? ((int64_t)h.cols + panel_cols(h.dt) - 1) / panel_cols(h.dt) : 0;
+}
 
 // Whether the column-panel layout suits the matrix: enough rows to fill the
 // GPU with row blocks, at least 8 entries per row and panel on average, few
@@ -307,7 +311,7 @@ static bool panels_eligible(const CsrHandle &h)
 {
     if (h.rows < 32768 || h.nnz == 0)
         return false;
-    const int64_t np = ((int64_t)h.cols + (1 << panel_log2w(h.dt)) - 1) >> panel_log2w(h.dt);
+    const int64_t np = panel_count(h);
     if (np < 1 || np > 64)
         return false;
     if (h.bin_off[NCLASS] - h.bin_off[C_W64 + 1] > 0)
@@ -325,33 +329,43 @@ static void build_panels(CsrHandle &h, hipStream_t s)
     PanelDesc pd{};
     pd.rows = h.rows;
     pd.cols = h.cols;
-    pd.log2w = panel_log2w(h.dt);
-    pd.np = (int32_t)(((int64_t)h.cols + (1 << pd.log2w) - 1) >> pd.log2w);
+    pd.pw = panel_cols(h.dt);
+    pd.np = (int32_t)panel_count(h);
     // two resident workgroups per CU, at most kPanelMaxRb rows each
     int64_t nblk = std::max<int64_t>(2 * c.cu, (h.rows + kPanelMaxRb - 1) / kPanelMaxRb);
     nblk = std::min<int64_t>(nblk, h.rows);
     pd.rb = (int32_t)((h.rows + nblk - 1) / nblk);
     pd.nblk = (int32_t)((h.rows + pd.rb - 1) / pd.rb);
+    pd.rw = (pd.rb + kPanelWaves - 1) / kPanelWaves;
     const int64_t nptr = (int64_t)pd.nblk * pd.np * (pd.rb + 1);
-    h.d_pptr = (int32_t *)dev_alloc((size_t)nptr * 4);
-    launch_fill_i32(h.d_pptr, nptr, 0, s);
-    launch_panel_count(pd, h.d_row_ptr, h.d_col, h.d_pptr, s);
-    const int64_t total = scan_total(h.d_pptr, nptr, s);
-    if (total != h.nnz)
-        fail(LILAC_ERR_DEVICE, "panel layout lost entries");
-    const size_t vs = dtype_size(h.dt);
-    h.d_pv = dev_alloc((size_t)(h.nnz + kPad) * vs);
-    h.d_pc = (uint16_t *)dev_alloc((size_t)(h.nnz + kPad) * 2);
-    launch_fill_bytes_zero((char *)h.d_pv + h.nnz * vs, kPad * vs, s);
-    launch_fill_bytes_zero((char *)h.d_pc + h.nnz * 2, kPad * 2, s);
-    launch_panel_scatter(h.dt, pd, h.d_row_ptr, h.d_col, h.d_vals, h.d_pptr,
-                         h.d_pv, h.d_pc, s);
+    int32_t *ptr = (int32_t *)dev_alloc((size_t)nptr * 4);
+    try {
+        launch_fill_i32(ptr, nptr, 0, s);
+        launch_panel_count(pd, h.d_row_ptr, h.d_col, ptr, s);
+        const int64_t total = scan_total(ptr, nptr, s);
+        if (total != h.nnz)
+            fail(LILAC_ERR_DEVICE, "panel layout lost entries");
+        const size_t vs = dtype_size(h.dt);
+        h.d_pv = dev_alloc((size_t)(h.nnz + kPad) * vs);
+        h.d_prc = (uint32_t *)dev_alloc((size_t)(h.nnz + kPad) * 4);
+        launch_fill_bytes_zero((char *)h.d_pv + h.nnz * vs, kPad * vs, s);
+        launch_fill_bytes_zero((char *)(h.d_prc + h.nnz), kPad * 4, s);
+        launch_panel_scatter(h.dt, pd, h.d_row_ptr, h.d_col, h.d_vals, ptr, h.d_pv,
+                             h.d_prc, s);
+        const int64_t nw = (int64_t)pd.nblk * pd.np * (kPanelWaves + 1);
+        h.d_pw = (int32_t *)dev_alloc((size_t)nw * 4);
+        launch_panel_wptr(pd, ptr, h.d_pw, s);
+        HIPC(hipStreamSynchronize(s));
+    } catch (...) {
+        dev_free(ptr);
+        throw;
+    }
+    dev_free(ptr);
     pd.vals = h.d_pv;
-    pd.col = h.d_pc;
-    pd.ptr = h.d_pptr;
+    pd.rc = h.d_prc;
+    pd.wptr = h.d_pw;
     h.pan = pd;
     h.use_panels = true;
-    HIPC(hipStreamSynchronize(s));
 }
 
 // Exclusive scan of a[0..n) in place; returns the total.
@@ -458,7 +472,7 @@ static void analyse(CsrHandle &h, hipStream_t s)
     h.fin_blocks = (h.nsplit + kBlock - 1) / kBlock;
     // a forced panel layout only needs a bounded number of panels; the
     // automatic choice also needs the matrix to suit it
-    const int64_t np_req = h.cols > 0 ? (((int64_t)h.cols - 1) >> panel_log2w(h.dt)) + 1 : 0;
+    const int64_t np_req = panel_count(h);
     const bool want_panels =
         (h.plan.layout == LAYOUT_PANELS && np_req <= 1024) ||
         (h.plan.layout == LAYOUT_AUTO && panels_eligible(h));
@@ -1142,7 +1156,7 @@ static void run_pagerank(CsrHandle &h, float d, int iters, float *x,
         PrState::G g{x, iters, d, nullptr, nullptr};
         const Epi epi{EPI_PAGERANK, 0, (double)d,
                       (1.0 - (double)d) / (double)h.rows};
-        const bool relabel = h.rows >= kRelabelRows && h.rows == h.cols;
+        const bool relabel = h.rows >= kRelabelRows && h.cols <= h.rows;
         if (relabel && !st.g)
             build_relabel(h, st);
         capture(g.graph, g.exec, [&](hipStream_t cs) {
