@@ -104,6 +104,9 @@ def run_cg(args, torch, L, gen, extras_only=False):
         h.spmv(p, q)
     ms = time_events(lambda: h.spmv(p, q), max(20, args.steps * 10), stream)
     achieved = kb / (ms * 1e-3) / 1e9
+    inf = h.info()
+    kernel_name = ("k_spmv_panels<double, false> (%d column panels)" % inf.npanels
+                   if inf.layout == L.LAYOUT_PANELS else "k_spmv_tiles<double, false, false>")
     # calibration for hardware byte counters: a plain copy of known size
     # (256 MiB read + 256 MiB written) run in the same process
     ca = torch.empty(32 << 20, dtype=torch.float64, device="cuda")
@@ -120,7 +123,7 @@ def run_cg(args, torch, L, gen, extras_only=False):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_spmv_tiles<double> (W64 rows)",
+                     "kernel": kernel_name,
                      "bytes_per_launch": kb, "avg_us": round(ms * 1e3, 2)},
         "config": {"workload": "cg_spd150k", "n": A.rows, "nnz": A.nnz,
                    "iters": iters, "graph": True, "dtype": "f64"},

@@ -513,8 +513,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
             }
             for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
                 xs[e] = x[c0 + e];
-            if (p + 1 < pd.np)
-                load_stage(p + 1);
         } else {
             for (int32_t e = threadIdx.x; e < width; e += kPanelThreads)
                 xs[e] = x[c0 + e];
@@ -523,29 +521,60 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
         const int32_t *wp = pd.wptr + ((int64_t)b * pd.np + p) * (kPanelWaves + 1);
         const int32_t ks = wp[wave];
         const int32_t ke = wp[wave + 1];
-        for (int32_t base = ks; base < ke; base += 64 * kPanelChunks) {
-            V v[kPanelChunks];
-            uint32_t rc[kPanelChunks];
+        // chunks of 128 entries from an even start: lane j holds the two
+        // consecutive entries base + 2j and base + 2j + 1 (one 16-byte value
+        // load, one 8-byte index load)
+        const int32_t kb = ks & ~1;
+        // the next panel of x is requested after this wavefront's first
+        // entry loads, so waiting for those does not wait for it (loads
+        // complete in issue order)
+        bool staged = !(aligned && p + 1 < pd.np);
+        for (int32_t base = kb; base < ke; base += 128 * kPanelChunks) {
+            typedef V pair_t __attribute__((ext_vector_type(2)));
+            typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
+            pair_t v[kPanelChunks];
+            upair_t rc[kPanelChunks];
 #pragma unroll
             for (int u = 0; u < kPanelChunks; ++u) {
-                const int32_t k = base + u * 64 + lane;
-                const int32_t kk = (k < ke) ? k : ks;
-                v[u] = ld_stream(pv + kk);
-                rc[u] = ld_stream(pd.rc + kk);
+                const int32_t e = base + u * 128 + 2 * lane;
+                const int32_t ea = (e < ke) ? e : kb;
+                v[u] = ld_stream((const pair_t *)(pv + ea));
+                rc[u] = ld_stream((const upair_t *)(pd.rc + ea));
+            }
+            if (!staged) {
+                load_stage(p + 1);
+                staged = true;
             }
 #pragma unroll
             for (int u = 0; u < kPanelChunks; ++u) {
-                if (base + u * 64 >= ke)
+                const int32_t e = base + u * 128 + 2 * lane;
+                if (base + u * 128 >= ke)
                     break;  // uniform: nothing left for this wavefront
-                const bool valid = base + u * 64 + lane < ke;
-                const int32_t row = valid ? (int32_t)(rc[u] >> 16) : kPanelMaxRb;
-                double val = valid ? (double)v[u] * (double)xs[rc[u] & 0xFFFFu] : 0.0;
-                val = seg_scan64(val, row);
-                const int32_t next = next_lane_key(row);
-                if (next != row && row < kPanelMaxRb)
-                    acc[row] += val;
+                // keys ascend along the wavefront: entries before ks belong to
+                // the previous wavefront (-1), entries past ke to nobody (max)
+                const int32_t k0 = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
+                const int32_t k1 = (e + 1 < ks) ? -1 : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16) : kPanelMaxRb;
+                const bool ok0 = e >= ks && e < ke, ok1 = e + 1 >= ks && e + 1 < ke;
+                const double p0 = ok0 ? (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu] : 0.0;
+                const double p1 = ok1 ? (double)v[u].y * (double)xs[rc[u].y & 0xFFFFu] : 0.0;
+                // this lane's part of the run of its last key, scanned over
+                // the lanes (a run that starts inside a lane breaks the scan
+                // because keys ascend)
+                const double part = (k0 == k1) ? p0 + p1 : p1;
+                const double incl = seg_scan64(part, k1);
+                const double prev_incl = dpp_f64m<0x138, 0xF>(incl, 0.0);  // wave_shr:1
+                const int32_t prev_k1 = dpp_i32<0x138, 0xF>(k1, -2);
+                const int32_t next_k0 = next_lane_key(k0);
+                // a run of k0 that ends on this lane's first entry
+                if (k0 != k1 && k0 >= 0 && k0 < kPanelMaxRb)
+                    acc[k0] += (prev_k1 == k0) ? prev_incl + p0 : p0;
+                // the run of k1 ends on this lane
+                if (next_k0 != k1 && k1 >= 0 && k1 < kPanelMaxRb)
+                    acc[k1] += incl;
             }
         }
+        if (!staged)
+            load_stage(p + 1);
     }
     __syncthreads();
     double dacc = 0.0;

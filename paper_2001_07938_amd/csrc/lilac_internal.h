@@ -110,7 +110,7 @@ constexpr int kPanelThreads = 512;             // 8 wave64 per workgroup
 constexpr int kPanelWaves = kPanelThreads / 64;
 constexpr int kPanelMaxRb = 512;               // rows per block (sums in LDS)
 constexpr int kPanelLds = 65536;               // LDS of one workgroup
-constexpr int kPanelChunks = 4;                // 64-entry chunks in flight
+constexpr int kPanelChunks = 2;                // 128-entry chunks in flight
 // widest panel (elements) for a value size
 constexpr int panel_width(int vsize)
 {
