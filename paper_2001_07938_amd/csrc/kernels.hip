@@ -457,15 +457,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
 
 // ------------------------------------------------------- column panels
 
-// Product over the column-panel layout.  Workgroup b owns row block b; for
-// each panel it stages that slice of x in LDS (the next slice is already on
-// its way in registers while the current one is used), and each wavefront
-// streams its own entries of the panel in coalesced 64-entry chunks: lane j
-// forms vals[k] * x[col] from LDS, a segmented scan over the 64 lanes (rows
-// ascend along the chunk) adds up each row's run, and the last lane of a run
-// adds it to the row's sum in LDS.  Rows belong to one wavefront, chunks
-// follow in order, panels follow in order: the additions are in a fixed order
-// given by the matrix and the layout.
+// Product over the column-panel layout.  Workgroup b (one per CU, 16
+// wavefronts) owns row block b; for each panel it copies that slice of x into
+// LDS, and each wavefront streams its own entries of the panel in coalesced
+// chunks: lane j forms vals[k] * x[col] from LDS for two consecutive
+// entries, a segmented scan over the lanes (rows ascend along the chunk) adds
+// up each row's run, and the last lane of a run adds it to the row's sum in
+// LDS.  Rows belong to one wavefront, chunks follow in order, panels follow
+// in order: the additions are in a fixed order given by the matrix and the
+// layout.
 template <typename V, bool DOT>
 __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
     PanelDesc pd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
@@ -476,7 +476,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
     V *xs = (V *)(smem + kPanelMaxRb * sizeof(double));           // x panel
     constexpr int VV = 16 / sizeof(V);
     typedef V vec_t __attribute__((ext_vector_type(VV)));
-    constexpr int kStage = (panel_width(sizeof(V)) / VV + kPanelThreads - 1) / kPanelThreads;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t b = blockIdx.x;
@@ -486,37 +485,15 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
     for (int i = threadIdx.x; i < kPanelMaxRb; i += kPanelThreads)
         acc[i] = 0.0;
     const bool aligned = (((uintptr_t)x) & 15) == 0;
-    vec_t stage[kStage];
-    auto load_stage = [&](int32_t p) {
-        const int32_t c0 = p * pd.pw;
-        const int32_t nvec = min(pd.pw, pd.cols - c0) / VV;
-#pragma unroll
-        for (int j = 0; j < kStage; ++j) {
-            const int32_t i = threadIdx.x + j * kPanelThreads;
-            if (i < nvec)
-                stage[j] = *(const vec_t *)(x + c0 + i * VV);
-        }
-    };
-    if (aligned)
-        load_stage(0);
     for (int32_t p = 0; p < pd.np; ++p) {
         const int32_t c0 = p * pd.pw;
         const int32_t width = min(pd.pw, pd.cols - c0);
         __syncthreads();  // the previous panel is no longer read
-        if (aligned) {
-            const int32_t nvec = width / VV;
-#pragma unroll
-            for (int j = 0; j < kStage; ++j) {
-                const int32_t i = threadIdx.x + j * kPanelThreads;
-                if (i < nvec)
-                    *(vec_t *)(xs + i * VV) = stage[j];
-            }
-            for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
-                xs[e] = x[c0 + e];
-        } else {
-            for (int32_t e = threadIdx.x; e < width; e += kPanelThreads)
-                xs[e] = x[c0 + e];
-        }
+        const int32_t nvec = aligned ? width / VV : 0;
+        for (int32_t i = threadIdx.x; i < nvec; i += kPanelThreads)
+            *(vec_t *)(xs + i * VV) = *(const vec_t *)(x + c0 + i * VV);
+        for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
+            xs[e] = x[c0 + e];
         __syncthreads();  // the panel is in LDS
         const int32_t *wp = pd.wptr + ((int64_t)b * pd.np + p) * (kPanelWaves + 1);
         const int32_t ks = wp[wave];
@@ -525,10 +502,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
         // consecutive entries base + 2j and base + 2j + 1 (one 16-byte value
         // load, one 8-byte index load)
         const int32_t kb = ks & ~1;
-        // the next panel of x is requested after this wavefront's first
-        // entry loads, so waiting for those does not wait for it (loads
-        // complete in issue order)
-        bool staged = !(aligned && p + 1 < pd.np);
         for (int32_t base = kb; base < ke; base += 128 * kPanelChunks) {
             typedef V pair_t __attribute__((ext_vector_type(2)));
             typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
@@ -540,10 +513,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
                 const int32_t ea = (e < ke) ? e : kb;
                 v[u] = ld_stream((const pair_t *)(pv + ea));
                 rc[u] = ld_stream((const upair_t *)(pd.rc + ea));
-            }
-            if (!staged) {
-                load_stage(p + 1);
-                staged = true;
             }
 #pragma unroll
             for (int u = 0; u < kPanelChunks; ++u) {
@@ -573,8 +542,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
                     acc[k1] += incl;
             }
         }
-        if (!staged)
-            load_stage(p + 1);
     }
     __syncthreads();
     double dacc = 0.0;
@@ -1523,6 +1490,20 @@ void launch_spmv_panels(lilac_dtype dt, const PanelDesc &pd, const void *x,
                            (const float *)x, (float *)y, epi, (const float *)w, dot_part);
     }
     check_launch("k_spmv_panels");
+}
+
+void panels_prepare()
+{
+    static bool done = false;
+    if (done)
+        return;
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_panels<double, true>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_panels<double, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_panels<float, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
+    done = true;
 }
 
 void launch_panel_count(const PanelDesc &pd, const int32_t *rp,

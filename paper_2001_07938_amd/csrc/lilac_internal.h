@@ -95,9 +95,9 @@ enum : int32_t { LAYOUT_AUTO = -1, LAYOUT_ROWS = 0, LAYOUT_PANELS = 1 };
 // x fits the LDS), the rows into blocks of `rb`.  Within row block b and
 // panel p the entries are stored row by row (each row's entries in their
 // CSR order), with the row inside the block and the column inside the panel
-// packed into 32 bits, (row << 16) | col.  Each of the eight wavefronts of a
-// workgroup owns `rw` consecutive rows of the block; wptr[(b*np + p)*9 + w]
-// is where wavefront w's entries of panel p start (entry 8: the end).
+// packed into 32 bits, (row << 16) | col.  Each of the sixteen wavefronts of
+// a workgroup owns `rw` consecutive rows of the block; wptr[(b*np + p)*17 + w]
+// is where wavefront w's entries of panel p start (entry 16: the end).
 struct PanelDesc {
     const void *vals;
     const uint32_t *rc;
@@ -106,10 +106,10 @@ struct PanelDesc {
     int32_t pw, np, rb, nblk, rw;
     int32_t pad;
 };
-constexpr int kPanelThreads = 512;             // 8 wave64 per workgroup
+constexpr int kPanelThreads = 1024;            // 16 wave64: one workgroup per CU
 constexpr int kPanelWaves = kPanelThreads / 64;
-constexpr int kPanelMaxRb = 512;               // rows per block (sums in LDS)
-constexpr int kPanelLds = 65536;               // LDS of one workgroup
+constexpr int kPanelMaxRb = 1024;              // rows per block (sums in LDS)
+constexpr int kPanelLds = 160 * 1024;          // LDS of one workgroup
 constexpr int kPanelChunks = 2;                // 128-entry chunks in flight
 // widest panel (elements) for a value size
 constexpr int panel_width(int vsize)
@@ -217,6 +217,8 @@ void launch_panel_scatter(lilac_dtype dt, const PanelDesc &pd, const int32_t *rp
                           void *pv, uint32_t *prc, hipStream_t s);
 void launch_panel_wptr(const PanelDesc &pd, const int32_t *ptr, int32_t *wptr,
                        hipStream_t s);
+// Lets the panel kernels use the whole LDS of a CU (once per process).
+void panels_prepare();
 // Finaliser for split rows: single matrix (items == null, n = nsplit) or a
 // list of (matrix, split row) items for grouped launches.
 void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,

@@ -331,8 +331,9 @@ static void build_panels(CsrHandle &h, hipStream_t s)
     pd.cols = h.cols;
     pd.pw = panel_cols(h.dt);
     pd.np = (int32_t)panel_count(h);
-    // two resident workgroups per CU, at most kPanelMaxRb rows each
-    int64_t nblk = std::max<int64_t>(2 * c.cu, (h.rows + kPanelMaxRb - 1) / kPanelMaxRb);
+    panels_prepare();
+    // one resident workgroup per CU, at most kPanelMaxRb rows each
+    int64_t nblk = std::max<int64_t>(c.cu, (h.rows + kPanelMaxRb - 1) / kPanelMaxRb);
     nblk = std::min<int64_t>(nblk, h.rows);
     pd.rb = (int32_t)((h.rows + nblk - 1) / nblk);
     pd.nblk = (int32_t)((h.rows + pd.rb - 1) / pd.rb);
