@@ -179,8 +179,9 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * at a time and gathers from there, with 16-bit column offsets.  It suits
  * matrices with many entries per row and panel (scattered columns); for
  * other matrices it is not built.  LILAC_LAYOUT_AUTO (the default) picks it
- * when the matrix has at least 8 entries per row and panel on average, at
- * most 64 panels and no row longer than 1024.  Re-runs the analysis.
+ * for matrices with at least 32768 rows, at most 64 panels, no row longer
+ * than 1024, and x small enough that copying it once per row block costs at
+ * most twice the matrix bytes.  Re-runs the analysis.
  */
 #define LILAC_LAYOUT_AUTO (-1)
 #define LILAC_LAYOUT_ROWS 0

@@ -514,32 +514,38 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
                 v[u] = ld_stream((const pair_t *)(pv + ea));
                 rc[u] = ld_stream((const upair_t *)(pd.rc + ea));
             }
+            // all chunks in lockstep (independent scans interleave); the sums
+            // reach the rows chunk by chunk, in order
+            int32_t k0[kPanelChunks], k1[kPanelChunks];
+            double p0[kPanelChunks], incl[kPanelChunks];
 #pragma unroll
             for (int u = 0; u < kPanelChunks; ++u) {
                 const int32_t e = base + u * 128 + 2 * lane;
-                if (base + u * 128 >= ke)
-                    break;  // uniform: nothing left for this wavefront
                 // keys ascend along the wavefront: entries before ks belong to
                 // the previous wavefront (-1), entries past ke to nobody (max)
-                const int32_t k0 = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
-                const int32_t k1 = (e + 1 < ks) ? -1 : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16) : kPanelMaxRb;
+                k0[u] = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
+                k1[u] = (e + 1 < ks) ? -1 : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16) : kPanelMaxRb;
                 const bool ok0 = e >= ks && e < ke, ok1 = e + 1 >= ks && e + 1 < ke;
-                const double p0 = ok0 ? (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu] : 0.0;
+                p0[u] = ok0 ? (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu] : 0.0;
                 const double p1 = ok1 ? (double)v[u].y * (double)xs[rc[u].y & 0xFFFFu] : 0.0;
-                // this lane's part of the run of its last key, scanned over
-                // the lanes (a run that starts inside a lane breaks the scan
-                // because keys ascend)
-                const double part = (k0 == k1) ? p0 + p1 : p1;
-                const double incl = seg_scan64(part, k1);
-                const double prev_incl = dpp_f64m<0x138, 0xF>(incl, 0.0);  // wave_shr:1
-                const int32_t prev_k1 = dpp_i32<0x138, 0xF>(k1, -2);
-                const int32_t next_k0 = next_lane_key(k0);
+                // this lane's part of the run of its last key (a run that
+                // starts inside a lane breaks the scan because keys ascend)
+                incl[u] = (k0[u] == k1[u]) ? p0[u] + p1 : p1;
+            }
+#pragma unroll
+            for (int u = 0; u < kPanelChunks; ++u)
+                incl[u] = seg_scan64(incl[u], k1[u]);
+#pragma unroll
+            for (int u = 0; u < kPanelChunks; ++u) {
+                const double prev_incl = dpp_f64m<0x138, 0xF>(incl[u], 0.0);  // wave_shr:1
+                const int32_t prev_k1 = dpp_i32<0x138, 0xF>(k1[u], -2);
+                const int32_t next_k0 = next_lane_key(k0[u]);
                 // a run of k0 that ends on this lane's first entry
-                if (k0 != k1 && k0 >= 0 && k0 < kPanelMaxRb)
-                    acc[k0] += (prev_k1 == k0) ? prev_incl + p0 : p0;
+                if (k0[u] != k1[u] && k0[u] >= 0 && k0[u] < kPanelMaxRb)
+                    acc[k0[u]] += (prev_k1 == k0[u]) ? prev_incl + p0[u] : p0[u];
                 // the run of k1 ends on this lane
-                if (next_k0 != k1 && k1 >= 0 && k1 < kPanelMaxRb)
-                    acc[k1] += incl;
+                if (next_k0 != k1[u] && k1[u] >= 0 && k1[u] < kPanelMaxRb)
+                    acc[k1[u]] += incl[u];
             }
         }
     }

@@ -302,11 +302,13 @@ static int64_t panel_count(const CsrHandle &h)
     return h.cols > 0 ? ((int64_t)h.cols + panel_cols(h.dt) - 1) / panel_cols(h.dt) : 0;
 }
 
-// Whether the column-panel layout suits the matrix: enough rows to fill the
-// GPU with row blocks, at least 8 entries per row and panel on average, few
-// panels, and no row too long for one lane group (rows in the wavefront
-// class at most).  Smaller matrices stay on the row-class tiles, which also
-// lets grouped launches take them in one kernel.
+// Whether the column-panel layout suits the matrix.  Every row block (one
+// per CU, at least) copies all of x into LDS once, so the layout pays off
+// when that copy traffic is small next to the matrix: at most twice the
+// matrix bytes.  Also: enough rows to give every CU a block, at most 64
+// panels, and no row longer than the wavefront class (1024).  Smaller or
+// sparser matrices stay on the row-class tiles, which also lets grouped
+// launches take them in one kernel.
 static bool panels_eligible(const CsrHandle &h)
 {
     if (h.rows < 32768 || h.nnz == 0)
@@ -316,8 +318,11 @@ static bool panels_eligible(const CsrHandle &h)
         return false;
     if (h.bin_off[NCLASS] - h.bin_off[C_W64 + 1] > 0)
         return false;  // rows longer than the wavefront class bound
-    const double mean = (double)h.nnz / h.rows;
-    return mean / (double)np >= 8.0;
+    const double vs = (double)dtype_size(h.dt);
+    const double nblk = std::max<double>(device_cu_count(),
+                                         std::ceil((double)h.rows / kPanelMaxRb));
+    const double stage = nblk * (double)h.cols * vs;
+    return stage <= 2.0 * (double)h.nnz * (vs + 4.0);
 }
 
 static int64_t scan_total(int32_t *a, int64_t n, hipStream_t s);
