@@ -52,6 +52,36 @@ def cg_iter_bytes(A) -> int:
     return spmv_bytes(A, 8) + 9 * A.rows * 8
 
 
+def kernel_source_digest() -> str:
+    """SHA-256 over the device sources (kernels and their shared header): a
+    stored counter reading is reported only while this still matches."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for rel in ("kernels.hip", "lilac_internal.h"):
+        with open(os.path.join(ROOT, "paper_2001_07938_amd", "csrc", rel), "rb") as f:
+            hsh.update(f.read())
+    return hsh.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the FETCH_SIZE and
+    WRITE_SIZE counter passes recorded under profiles/ (already scaled by
+    the copy-kernel calibration), or None when there is no record or the
+    device sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            recs = json.load(f)
+    except (OSError, ValueError):
+        return None
+    digest = kernel_source_digest()
+    for r in recs:
+        if r.get("kernel") == kernel and r.get("workload") == workload \
+                and r.get("source_sha256") == digest:
+            return int(r["read_bytes"]) + int(r["write_bytes"])
+    return None
+
+
 def time_events(fn, reps: int, stream) -> float:
     """Average milliseconds of fn() over reps launches, HIP events recorded
     on `stream` (the stream fn launches on)."""
@@ -105,8 +135,8 @@ def run_cg(args, torch, L, gen, extras_only=False):
     ms = time_events(lambda: h.spmv(p, q), max(20, args.steps * 10), stream)
     achieved = kb / (ms * 1e-3) / 1e9
     inf = h.info()
-    kernel_name = ("k_spmv_panels<double, false> (%d column panels)" % inf.npanels
-                   if inf.layout == L.LAYOUT_PANELS else "k_spmv_tiles<double, false, false>")
+    kernel_name = ("k_spmv_panels<double, false>" if inf.layout == L.LAYOUT_PANELS
+                   else "k_spmv_tiles<double, false, false>")
     # calibration for hardware byte counters: a plain copy of known size
     # (256 MiB read + 256 MiB written) run in the same process
     ca = torch.empty(32 << 20, dtype=torch.float64, device="cuda")
@@ -122,8 +152,9 @@ def run_cg(args, torch, L, gen, extras_only=False):
         "gflops": round(2.0 * A.nnz * iters / dt / 1e9, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": kernel_name,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(kernel_name, "cg_spd150k"),
+                     "kernel": kernel_name, "npanels": inf.npanels,
                      "bytes_per_launch": kb, "avg_us": round(ms * 1e3, 2)},
         "config": {"workload": "cg_spd150k", "n": A.rows, "nnz": A.nnz,
                    "iters": iters, "graph": True, "dtype": "f64"},
