@@ -145,7 +145,7 @@ typedef struct {
     int chunk;              /* non-zeros per chunk of a split row */
     int64_t nchunks;        /* entries of the chunk table */
     int ntiles;             /* work tiles of one product */
-    int layout;             /* LILAC_LAYOUT_ROWS or LILAC_LAYOUT_PANELS in use */
+    int layout;             /* LILAC_LAYOUT_ROWS, _PANELS or _HOT in use */
     int npanels;            /* column panels (panel layout), else 0 */
 } lilac_csr_info_t;
 int lilac_csr_info(lilac_csr_t h, lilac_csr_info_t *out);
@@ -181,11 +181,20 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * other matrices it is not built.  LILAC_LAYOUT_AUTO (the default) picks it
  * for matrices with at least 32768 rows, at most 64 panels, no row longer
  * than 1024, and x small enough that copying it once per row block costs at
- * most twice the matrix bytes.  Re-runs the analysis.
+ * most twice the matrix bytes.  LILAC_LAYOUT_HOT: a second copy for
+ * matrices whose most referenced columns have the lowest indices (a graph
+ * relabelled by decreasing out-degree, as lilac_pagerank does by itself for
+ * graphs of at least 65536 vertices): the first 32512 (float32) or 16256
+ * (float64) columns of x stay in LDS, the others are read from x in device
+ * memory; rows are cut into blocks of at most 2048 rows and about equal
+ * non-zeros.  Built only on request and only for matrices with non-zeros;
+ * otherwise the rows layout is used (lilac_csr_info reports which).  Every
+ * layout gives deterministic results.  Re-runs the analysis.
  */
 #define LILAC_LAYOUT_AUTO (-1)
 #define LILAC_LAYOUT_ROWS 0
 #define LILAC_LAYOUT_PANELS 1
+#define LILAC_LAYOUT_HOT 2
 int lilac_csr_set_layout(lilac_csr_t h, int layout);
 
 /*

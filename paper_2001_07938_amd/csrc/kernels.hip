@@ -622,6 +622,252 @@ __global__ __launch_bounds__(kBlock) void k_panel_wptr(PanelDesc pd,
     wptr[t] = ptr[seg * (pd.rb + 1) + min(wv * pd.rw, pd.rb)];
 }
 
+// ------------------------------------------------------- hot columns
+
+// One wavefront's share of a block part [s, e) of the hot-column layout.
+// The part is split evenly by entries, so a row can span wavefronts: the
+// run of the wavefront's first row goes to its carry slot (added after the
+// block, in slot order), every other run is added to the row sum in LDS by
+// the one wavefront where it ends.  HOT: the gather comes from the LDS copy
+// of the hot columns and the row is in the entry's word; otherwise from x
+// in global memory, the row from key[].  The entries of the next chunk are
+// requested before the gathers of the current one are used.
+template <typename V, bool HOT>
+__device__ __forceinline__ void hot_part(const V *__restrict__ pv,
+                                         const uint32_t *__restrict__ prc,
+                                         const uint16_t *__restrict__ pkey,
+                                         int32_t s, int32_t e, const V *xsrc,
+                                         double *acc, int32_t *ckey, double *csum,
+                                         int wave, int lane)
+{
+    typedef V pair_t __attribute__((ext_vector_type(2)));
+    typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
+    typedef uint16_t kpair_t __attribute__((ext_vector_type(2)));
+    const int64_t n = (int64_t)e - s;
+    const int32_t ks = s + (int32_t)(n * wave / kPanelWaves);
+    const int32_t ke = s + (int32_t)(n * (wave + 1) / kPanelWaves);
+    const int32_t kb = ks & ~1;
+    pair_t v;
+    upair_t rc;
+    kpair_t kk;
+    int32_t first = -1;
+    if (kb < ke) {
+        const int32_t en = kb + 2 * lane;
+        const int32_t ea = (en < ke) ? en : kb;
+        v = ld_stream((const pair_t *)(pv + ea));
+        rc = ld_stream((const upair_t *)(prc + ea));
+        if (!HOT)
+            kk = ld_stream((const kpair_t *)(pkey + ea));
+        // the share's first entry is entry 0 or 1 of lane 0
+        const int32_t f0 = HOT ? (int32_t)(rc.x >> 16) : (int32_t)kk.x;
+        const int32_t f1 = HOT ? (int32_t)(rc.y >> 16) : (int32_t)kk.y;
+        first = __builtin_amdgcn_readfirstlane((ks == kb) ? f0 : f1);
+    }
+    if (lane == 0) {
+        *ckey = first;
+        *csum = 0.0;
+    }
+    for (int32_t base = kb; base < ke; base += 128) {
+        const int32_t en = base + 2 * lane;
+        const bool ok0 = en >= ks && en < ke, ok1 = en + 1 >= ks && en + 1 < ke;
+        const int32_t r0 = HOT ? (int32_t)(rc.x >> 16) : (int32_t)kk.x;
+        const int32_t r1 = HOT ? (int32_t)(rc.y >> 16) : (int32_t)kk.y;
+        // keys ascend along the wavefront: entries before ks belong to the
+        // previous wavefront (-1), entries past ke to nobody (kHotRows)
+        const int32_t k0 = (en < ks) ? -1 : ok0 ? r0 : kHotRows;
+        const int32_t k1 = (en + 1 < ks) ? -1 : ok1 ? r1 : kHotRows;
+        // entries outside the share may belong to the other part (another
+        // packing): gather element 0 for them, which always exists
+        const uint32_t c0 = ok0 ? (HOT ? (rc.x & 0xFFFFu) : rc.x) : 0u;
+        const uint32_t c1 = ok1 ? (HOT ? (rc.y & 0xFFFFu) : rc.y) : 0u;
+        const V x0 = xsrc[c0], x1 = xsrc[c1];
+        const pair_t cv = v;
+        const int32_t nb = base + 128;
+        if (nb < ke) {
+            const int32_t nn = nb + 2 * lane;
+            const int32_t ea = (nn < ke) ? nn : kb;
+            v = ld_stream((const pair_t *)(pv + ea));
+            rc = ld_stream((const upair_t *)(prc + ea));
+            if (!HOT)
+                kk = ld_stream((const kpair_t *)(pkey + ea));
+        }
+        const double p0 = ok0 ? (double)cv.x * (double)x0 : 0.0;
+        const double p1 = ok1 ? (double)cv.y * (double)x1 : 0.0;
+        // this lane's part of the run of its last key (a run that starts
+        // inside a lane breaks the scan because keys ascend)
+        double incl = (k0 == k1) ? p0 + p1 : p1;
+        incl = seg_scan64(incl, k1);
+        const double prev_incl = dpp_f64m<0x138, 0xF>(incl, 0.0);  // wave_shr:1
+        const int32_t prev_k1 = dpp_i32<0x138, 0xF>(k1, -2);
+        const int32_t next_k0 = next_lane_key(k0);
+        if (k0 != k1 && k0 >= 0 && k0 < kHotRows) {
+            double *t = (k0 == first) ? csum : acc + k0;
+            *t += (prev_k1 == k0) ? prev_incl + p0 : p0;
+        }
+        if (next_k0 != k1 && k1 >= 0 && k1 < kHotRows) {
+            double *t = (k1 == first) ? csum : acc + k1;
+            *t += incl;
+        }
+    }
+}
+
+// Product over the hot-column layout.  Persistent: workgroup g copies the
+// hot columns of x into LDS once, then takes row blocks g, g + grid, ...
+// Each wavefront streams its share of the block's hot part and of its cold
+// part (odd wavefronts cold first, so LDS and global gathers overlap); the
+// two parts add into separate row sums, so no wavefront waits for another
+// between them.  The carries are then summed in slot order by one lane per
+// row, and each row's result is its hot sum plus its cold sum: every sum is
+// formed in an order fixed by the matrix and the layout.
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
+    HotDesc hd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
+    const V *__restrict__ w, double *__restrict__ dot_part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *acc_h = (double *)smem;                                    // hot row sums
+    double *acc_c = (double *)(smem + kHotRows * 8);                   // cold row sums
+    double *csum = (double *)(smem + 2 * kHotRows * 8);                // 32 carries
+    int32_t *ckey = (int32_t *)(smem + 2 * kHotRows * 8 + 32 * 8);     // their rows
+    V *xs = (V *)(smem + kHotLdsHead);                                 // hot columns
+    constexpr int VV = 16 / sizeof(V);
+    typedef V vec_t __attribute__((ext_vector_type(VV)));
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const V *pv = (const V *)hd.vals;
+    const int32_t width = hd.hot;
+    const bool aligned = (((uintptr_t)x) & 15) == 0;
+    const int32_t nvec = aligned ? width / VV : 0;
+    for (int32_t i = threadIdx.x; i < nvec; i += kPanelThreads)
+        *(vec_t *)(xs + i * VV) = *(const vec_t *)(x + i * VV);
+    for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
+        xs[e] = x[e];
+    for (int i = threadIdx.x; i < 2 * kHotRows; i += kPanelThreads)
+        acc_h[i] = 0.0;  // both sum arrays
+    double dacc = 0.0;
+    for (int32_t b = blockIdx.x; b < hd.nblk; b += gridDim.x) {
+        const int32_t r0 = hd.brow[b];
+        const int32_t nr = hd.brow[b + 1] - r0;
+        const int32_t e0 = hd.bent[b], es = hd.bsplit[b], e1 = hd.bent[b + 1];
+        __syncthreads();  // hot columns staged, sums of the last block cleared
+        if (wave & 1) {
+            hot_part<V, false>(pv, hd.rc, hd.key, es, e1, x, acc_c,
+                               ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
+                               wave, lane);
+            hot_part<V, true>(pv, hd.rc, hd.key, e0, es, xs, acc_h, ckey + wave,
+                              csum + wave, wave, lane);
+        } else {
+            hot_part<V, true>(pv, hd.rc, hd.key, e0, es, xs, acc_h, ckey + wave,
+                              csum + wave, wave, lane);
+            hot_part<V, false>(pv, hd.rc, hd.key, es, e1, x, acc_c,
+                               ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
+                               wave, lane);
+        }
+        __syncthreads();  // all runs are in
+        if (wave == 0) {
+            // lanes 0-15: hot slots, 16-31: cold slots.  A slot leads its
+            // row if no earlier slot of its part has it; the leader adds the
+            // row's carries of that part in slot order (distinct rows per part)
+            const int32_t k = (lane < 2 * kPanelWaves) ? ckey[lane] : -1;
+            const double c = (lane < 2 * kPanelWaves) ? csum[lane] : 0.0;
+            const bool cold = lane >= kPanelWaves;
+            bool lead = k >= 0;
+            double t = 0.0;
+            for (int j = 0; j < 2 * kPanelWaves; ++j) {
+                const int32_t kj = __builtin_amdgcn_readlane(k, j);
+                const double cj = readlane_f64(c, j);
+                if ((j >= kPanelWaves) == cold && kj == k) {
+                    if (j < lane)
+                        lead = false;
+                    else
+                        t += cj;
+                }
+            }
+            if (lead)
+                (cold ? acc_c : acc_h)[k] += t;
+        }
+        __syncthreads();  // carries are in
+        for (int32_t i = threadIdx.x; i < nr; i += kPanelThreads) {
+            const V out = epilogue<V>(acc_h[i] + acc_c[i], epi);
+            acc_h[i] = 0.0;  // the thread that reads a sum clears it
+            acc_c[i] = 0.0;
+            y[r0 + i] = out;
+            if (DOT)
+                dacc = fma((double)w[r0 + i], (double)out, dacc);
+        }
+    }
+    if (DOT) {
+        const double tot = block_sum<kPanelWaves>(dacc, csum);
+        if (threadIdx.x == 0)
+            dot_part[blockIdx.x] = tot;
+    }
+}
+
+// Hot entries of each row (one thread per row).
+__global__ __launch_bounds__(kBlock) void k_hot_count(HotDesc hd,
+                                                      const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col,
+                                                      int32_t *__restrict__ cnt)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= hd.rows)
+        return;
+    int32_t n = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        n += (col[k] < hd.hot) ? 1 : 0;
+    cnt[i] = n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hot_split(HotDesc hd,
+                                                      const int32_t *__restrict__ hx,
+                                                      int32_t *__restrict__ bsplit)
+{
+    const int32_t b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= hd.nblk)
+        return;
+    bsplit[b] = hd.bent[b] + (hx[hd.brow[b + 1]] - hx[hd.brow[b]]);
+}
+
+// Move each row's entries to the hot or cold part of its block (stable
+// inside a row).  hx: exclusive scan of the per-row hot counts.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_hot_scatter(
+    HotDesc hd, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ vals, const int32_t *__restrict__ hx,
+    V *__restrict__ hv, uint32_t *__restrict__ hrc, uint16_t *__restrict__ hkey)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= hd.rows)
+        return;
+    // block of row i: the last b with brow[b] <= i
+    int32_t lo = 0, hi = hd.nblk - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (hd.brow[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int32_t b = lo;
+    const uint32_t rl = (uint32_t)(i - hd.brow[b]);
+    const int32_t before = hx[i] - hx[hd.brow[b]];   // hot entries of earlier rows
+    int32_t hp = hd.bent[b] + before;
+    int32_t cp = hd.bsplit[b] + (rp[i] - hd.bent[b]) - before;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t c = col[k];
+        if (c < hd.hot) {
+            hv[hp] = vals[k];
+            hrc[hp] = (rl << 16) | (uint32_t)c;
+            ++hp;
+        } else {
+            hv[cp] = vals[k];
+            hrc[cp] = (uint32_t)c;
+            hkey[cp] = (uint16_t)rl;
+            ++cp;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ BFS
 
 // Rows of a tile, W lanes per row, Boolean (or, and) product against the
@@ -1095,6 +1341,57 @@ __global__ __launch_bounds__(1024) void k_scan_excl(int32_t *__restrict__ a,
         *total = carry;
 }
 
+// Exclusive scan of 8192-element tiles of a (8 consecutive per thread); the
+// tile totals go to aux[tile].
+__global__ __launch_bounds__(1024) void k_scan_tiles(int32_t *__restrict__ a,
+                                                     int64_t n,
+                                                     int32_t *__restrict__ aux)
+{
+    __shared__ int32_t ws[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * 8192 + (int64_t)threadIdx.x * 8;
+    int32_t v[8];
+    int32_t t = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        v[j] = (base + j < n) ? a[base + j] : 0;
+        t += v[j];
+    }
+    int32_t inc = t;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += u;
+    }
+    if (lane == 63)
+        ws[wave] = inc;
+    __syncthreads();
+    int32_t run = inc - t;
+    for (int i = 0; i < wave; ++i)
+        run += ws[i];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (base + j < n)
+            a[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 1023)
+        aux[blockIdx.x] = run;
+}
+
+// Adds the scanned tile totals to every element of the tile.
+__global__ __launch_bounds__(1024) void k_scan_add(int32_t *__restrict__ a,
+                                                   int64_t n,
+                                                   const int32_t *__restrict__ aux)
+{
+    const int32_t add = aux[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * 8192;
+    for (int j = threadIdx.x; j < 8192; j += 1024)
+        if (base + j < n)
+            a[base + j] += add;
+}
+
 __global__ __launch_bounds__(kBlock) void k_chunk_count(
     int32_t nsplit, const int32_t *__restrict__ split_rows,
     const int32_t *__restrict__ rp, int32_t chunk, int32_t *__restrict__ cnt)
@@ -1369,8 +1666,25 @@ void launch_bin_count(int32_t rows, const int32_t *rp, const Thresholds &th,
 
 void launch_scan_excl(int32_t *a, int64_t n, int32_t *total, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, a, n, total);
+    if (n <= 65536) {
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, a, n, total);
+        check_launch("k_scan_excl");
+        return;
+    }
+    // tiles of 8192, then the tile totals, then the offsets back into the tiles
+    const int64_t nt = (n + 8191) / 8192;
+    if (nt > INT32_MAX)
+        fail(LILAC_ERR_ARG, "scan too long");
+    int32_t *aux = (int32_t *)dev_alloc((size_t)nt * 4);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((uint32_t)nt), dim3(1024), 0, s, a, n, aux);
+    check_launch("k_scan_tiles");
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, aux, nt, total);
     check_launch("k_scan_excl");
+    hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)nt), dim3(1024), 0, s, a, n,
+                       (const int32_t *)aux);
+    check_launch("k_scan_add");
+    HIPC(hipStreamSynchronize(s));
+    dev_free(aux);
 }
 
 void launch_bin_scatter(int32_t rows, const int32_t *rp, const Thresholds &th,
@@ -1498,11 +1812,69 @@ void launch_spmv_panels(lilac_dtype dt, const PanelDesc &pd, const void *x,
     check_launch("k_spmv_panels");
 }
 
+void launch_spmv_hot(lilac_dtype dt, const HotDesc &hd, const void *x, void *y,
+                     const Epi &epi, const void *w, double *dot_part, hipStream_t s)
+{
+    if (hd.nblk <= 0 || hd.grid <= 0)
+        return;
+    dim3 g(hd.grid), b(kPanelThreads);
+    if (dt == LILAC_F64) {
+        if (dot_part)
+            hipLaunchKernelGGL((k_spmv_hot<double, true>), g, b, kPanelLds, s, hd,
+                               (const double *)x, (double *)y, epi, (const double *)w, dot_part);
+        else
+            hipLaunchKernelGGL((k_spmv_hot<double, false>), g, b, kPanelLds, s, hd,
+                               (const double *)x, (double *)y, epi, (const double *)w, dot_part);
+    } else {
+        if (dot_part)
+            fail(LILAC_ERR_UNSUPPORTED, "fused dot is only provided for float64");
+        hipLaunchKernelGGL((k_spmv_hot<float, false>), g, b, kPanelLds, s, hd,
+                           (const float *)x, (float *)y, epi, (const float *)w, dot_part);
+    }
+    check_launch("k_spmv_hot");
+}
+
+void launch_hot_count(const HotDesc &hd, const int32_t *rp, const int32_t *col,
+                      int32_t *cnt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hot_count, dim3(grid_for(hd.rows, kBlock, INT_MAX)),
+                       dim3(kBlock), 0, s, hd, rp, col, cnt);
+    check_launch("k_hot_count");
+}
+
+void launch_hot_split(const HotDesc &hd, const int32_t *hx, int32_t *bsplit,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hot_split, dim3(grid_for(hd.nblk, kBlock, INT_MAX)),
+                       dim3(kBlock), 0, s, hd, hx, bsplit);
+    check_launch("k_hot_split");
+}
+
+void launch_hot_scatter(lilac_dtype dt, const HotDesc &hd, const int32_t *rp,
+                        const int32_t *col, const void *vals, const int32_t *hx,
+                        void *hv, uint32_t *hrc, uint16_t *hkey, hipStream_t s)
+{
+    dim3 g(grid_for(hd.rows, kBlock, INT_MAX)), b(kBlock);
+    if (dt == LILAC_F64)
+        hipLaunchKernelGGL(k_hot_scatter<double>, g, b, 0, s, hd, rp, col,
+                           (const double *)vals, hx, (double *)hv, hrc, hkey);
+    else
+        hipLaunchKernelGGL(k_hot_scatter<float>, g, b, 0, s, hd, rp, col,
+                           (const float *)vals, hx, (float *)hv, hrc, hkey);
+    check_launch("k_hot_scatter");
+}
+
 void panels_prepare()
 {
     static bool done = false;
     if (done)
         return;
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_hot<double, true>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_hot<double, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_hot<float, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
     HIPC(hipFuncSetAttribute((const void *)k_spmv_panels<double, true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
     HIPC(hipFuncSetAttribute((const void *)k_spmv_panels<double, false>,

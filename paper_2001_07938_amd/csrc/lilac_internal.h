@@ -84,12 +84,12 @@ struct Plan {
     int32_t rpg[NCLASS];    // rows per lane group per tile
     int32_t chunk;          // non-zeros per split-row chunk
     int32_t grid_per_cu;    // persistent workgroups per compute unit
-    int32_t layout;         // LAYOUT_AUTO, LAYOUT_ROWS or LAYOUT_PANELS
+    int32_t layout;         // LAYOUT_AUTO, LAYOUT_ROWS, LAYOUT_PANELS or LAYOUT_HOT
 };
 
 // Device layouts of a matrix for the product: the row-class tiles over the
 // CSR arrays, or column panels (x staged in LDS one panel at a time).
-enum : int32_t { LAYOUT_AUTO = -1, LAYOUT_ROWS = 0, LAYOUT_PANELS = 1 };
+enum : int32_t { LAYOUT_AUTO = -1, LAYOUT_ROWS = 0, LAYOUT_PANELS = 1, LAYOUT_HOT = 2 };
 
 // Column-panel layout: the columns are cut into panels of `pw` (a panel of
 // x fits the LDS), the rows into blocks of `rb`.  Within row block b and
@@ -115,6 +115,32 @@ constexpr int kPanelChunks = 2;                // 128-entry chunks in flight
 constexpr int panel_width(int vsize)
 {
     return (kPanelLds - kPanelMaxRb * 8) / vsize;
+}
+
+// Hot-column layout, for matrices whose most referenced columns come first
+// (a graph relabelled by decreasing out-degree).  Columns [0, hot) are
+// copied into LDS once per workgroup; the others are read from x in global
+// memory.  Rows are cut into blocks of at most kHotRows rows and about the
+// same number of entries; block b holds rows [brow[b], brow[b+1]) and the
+// entries [bent[b], bent[b+1]), its hot entries first (up to bsplit[b]),
+// then its cold ones, each part row by row.  A hot entry's word packs the
+// row inside the block and the column, (row << 16) | col; a cold entry's
+// word is its column and key[] holds its row inside the block.
+struct HotDesc {
+    const void *vals;
+    const uint32_t *rc;
+    const uint16_t *key;
+    const int32_t *brow;     // [nblk + 1]
+    const int32_t *bent;     // [nblk + 1]
+    const int32_t *bsplit;   // [nblk]
+    int32_t rows, cols, nblk, hot, grid, pad;
+};
+constexpr int kHotRows = 2048;                        // rows per block
+constexpr int kHotLdsHead = 2 * kHotRows * 8 + 1024;  // hot and cold row sums + carries
+// hot columns (elements) for a value size
+constexpr int hot_width(int vsize)
+{
+    return ((kPanelLds - kHotLdsHead) / vsize) & ~63;
 }
 
 Plan default_plan();
@@ -145,6 +171,13 @@ struct CsrHandle {
     void *d_pv = nullptr;
     uint32_t *d_prc = nullptr;
     int32_t *d_pw = nullptr;
+    // hot-column layout (when use_hot)
+    bool use_hot = false;
+    HotDesc hot{};
+    void *d_hv = nullptr;
+    uint32_t *d_hrc = nullptr;
+    uint16_t *d_hkey = nullptr;
+    int32_t *d_hb = nullptr;        // brow | bent | bsplit
     std::vector<int32_t> bin_off;   // NCLASS+1
     int64_t nchunks = 0;
     int32_t nsplit = 0;
@@ -162,6 +195,10 @@ struct CsrHandle {
 };
 
 size_t dtype_size(lilac_dtype dt);
+
+// Whether the product runs on a layout of its own (column panels or hot
+// columns) rather than on the row-class tiles.
+inline bool own_layout(const CsrHandle &h) { return h.use_panels || h.use_hot; }
 
 // ---- errors ---------------------------------------------------------------
 struct Error {
@@ -185,6 +222,9 @@ void launch_validate(int32_t rows, const int32_t *rp, int64_t nnz,
                      hipStream_t s);
 void launch_bin_count(int32_t rows, const int32_t *rp, const Thresholds &th,
                       int32_t *hist, int32_t nblk, hipStream_t s);
+// Exclusive prefix sum of a[0..n) in place; *total (if non-null) receives
+// the sum.  Beyond 65536 elements it takes a temporary buffer and waits for
+// the stream: analysis only, never inside a captured graph.
 void launch_scan_excl(int32_t *a, int64_t n, int32_t *total, hipStream_t s);
 void launch_bin_scatter(int32_t rows, const int32_t *rp, const Thresholds &th,
                         const int32_t *hist, int32_t nblk, int32_t *bin_rows,
@@ -219,6 +259,19 @@ void launch_panel_wptr(const PanelDesc &pd, const int32_t *ptr, int32_t *wptr,
                        hipStream_t s);
 // Lets the panel kernels use the whole LDS of a CU (once per process).
 void panels_prepare();
+// Hot-column product (see HotDesc): hd.grid persistent workgroups take the
+// row blocks in turn; dot_part (or null) receives one partial per workgroup.
+void launch_spmv_hot(lilac_dtype dt, const HotDesc &hd, const void *x, void *y,
+                     const Epi &epi, const void *w, double *dot_part, hipStream_t s);
+// cnt[r] = entries of row r with a column below hd.hot.
+void launch_hot_count(const HotDesc &hd, const int32_t *rp, const int32_t *col,
+                      int32_t *cnt, hipStream_t s);
+// bsplit from the block bounds and the exclusive scan hx of the hot counts.
+void launch_hot_split(const HotDesc &hd, const int32_t *hx, int32_t *bsplit,
+                      hipStream_t s);
+void launch_hot_scatter(lilac_dtype dt, const HotDesc &hd, const int32_t *rp,
+                        const int32_t *col, const void *vals, const int32_t *hx,
+                        void *hv, uint32_t *hrc, uint16_t *hkey, hipStream_t s);
 // Finaliser for split rows: single matrix (items == null, n = nsplit) or a
 // list of (matrix, split row) items for grouped launches.
 void launch_split_finalize(lilac_dtype dt, const int32_t *items, int32_t n,

@@ -251,7 +251,7 @@ static void check_plan(const Plan &p)
         fail(LILAC_ERR_ARG, "chunk must be in [256, 2^24]");
     if (p.grid_per_cu < 1 || p.grid_per_cu > 32)
         fail(LILAC_ERR_ARG, "grid_per_cu must be in [1, 32]");
-    if (p.layout < LAYOUT_AUTO || p.layout > LAYOUT_PANELS)
+    if (p.layout < LAYOUT_AUTO || p.layout > LAYOUT_HOT)
         fail(LILAC_ERR_ARG, "unknown layout");
 }
 
@@ -275,8 +275,14 @@ static void free_analysis(CsrHandle &h)
     dev_free_reset(h.d_pv);
     dev_free_reset(h.d_prc);
     dev_free_reset(h.d_pw);
+    dev_free_reset(h.d_hv);
+    dev_free_reset(h.d_hrc);
+    dev_free_reset(h.d_hkey);
+    dev_free_reset(h.d_hb);
     h.use_panels = false;
     h.pan = PanelDesc{};
+    h.use_hot = false;
+    h.hot = HotDesc{};
     h.ntiles = 0;
     h.nchunks = 0;
     h.nsplit = 0;
@@ -292,6 +298,9 @@ static int64_t analysis_bytes(const CsrHandle &h)
     if (h.use_panels)
         b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 4) +
              (int64_t)h.pan.nblk * h.pan.np * (kPanelWaves + 1) * 4;
+    if (h.use_hot)
+        b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 6) +
+             (int64_t)(3 * h.hot.nblk + 2) * 4;
     return b;
 }
 
@@ -372,6 +381,78 @@ static void build_panels(CsrHandle &h, hipStream_t s)
     pd.wptr = h.d_pw;
     h.pan = pd;
     h.use_panels = true;
+}
+
+// Whether the hot-column layout can be built: it needs entries.
+static bool hot_possible(const CsrHandle &h)
+{
+    return h.rows > 0 && h.nnz > 0 && h.cols > 0;
+}
+
+// Builds the hot-column copy of the matrix (see HotDesc).  Block bounds are
+// chosen on the host from row_ptr: a new block starts when the current one
+// has kHotRows rows or at least `target` entries (about six blocks per
+// workgroup).
+static void build_hot(CsrHandle &h, hipStream_t s)
+{
+    Context &c = ctx();
+    HotDesc hd{};
+    hd.rows = h.rows;
+    hd.cols = h.cols;
+    hd.hot = std::min<int32_t>(h.cols, hot_width((int)dtype_size(h.dt)));
+    panels_prepare();
+    std::vector<int32_t> rp((size_t)h.rows + 1);
+    HIPC(hipMemcpyAsync(rp.data(), h.d_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    const int64_t target = std::max<int64_t>(8192, h.nnz / ((int64_t)c.cu * 6));
+    std::vector<int32_t> brow{0};
+    int32_t start = 0;
+    for (int32_t r = 1; r < h.rows; ++r)
+        if (r - start >= kHotRows || (int64_t)rp[r] - rp[start] >= target) {
+            brow.push_back(r);
+            start = r;
+        }
+    brow.push_back(h.rows);
+    hd.nblk = (int32_t)brow.size() - 1;
+    hd.grid = std::min<int32_t>(hd.nblk, c.cu);
+    std::vector<int32_t> hb((size_t)3 * hd.nblk + 2);
+    for (int32_t b = 0; b <= hd.nblk; ++b) {
+        hb[b] = brow[b];
+        hb[hd.nblk + 1 + b] = rp[brow[b]];
+    }
+    h.d_hb = (int32_t *)dev_alloc(hb.size() * 4);
+    HIPC(hipMemcpyAsync(h.d_hb, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, s));
+    hd.brow = h.d_hb;
+    hd.bent = h.d_hb + hd.nblk + 1;
+    int32_t *bsplit = h.d_hb + 2 * (hd.nblk + 1);
+    hd.bsplit = bsplit;
+    int32_t *hx = (int32_t *)dev_alloc((size_t)(h.rows + 1) * 4);
+    try {
+        launch_fill_i32(hx + h.rows, 1, 0, s);
+        launch_hot_count(hd, h.d_row_ptr, h.d_col, hx, s);
+        scan_total(hx, (int64_t)h.rows + 1, s);
+        launch_hot_split(hd, hx, bsplit, s);
+        const size_t vs = dtype_size(h.dt);
+        h.d_hv = dev_alloc((size_t)(h.nnz + kPad) * vs);
+        h.d_hrc = (uint32_t *)dev_alloc((size_t)(h.nnz + kPad) * 4);
+        h.d_hkey = (uint16_t *)dev_alloc((size_t)(h.nnz + kPad) * 2);
+        launch_fill_bytes_zero((char *)h.d_hv + h.nnz * vs, kPad * vs, s);
+        launch_fill_bytes_zero((char *)(h.d_hrc + h.nnz), kPad * 4, s);
+        // keys of hot entries are never used; keep every byte defined
+        launch_fill_bytes_zero(h.d_hkey, (h.nnz + kPad) * 2, s);
+        launch_hot_scatter(h.dt, hd, h.d_row_ptr, h.d_col, h.d_vals, hx, h.d_hv,
+                           h.d_hrc, h.d_hkey, s);
+        HIPC(hipStreamSynchronize(s));
+    } catch (...) {
+        dev_free(hx);
+        throw;
+    }
+    dev_free(hx);
+    hd.vals = h.d_hv;
+    hd.rc = h.d_hrc;
+    hd.key = h.d_hkey;
+    h.hot = hd;
+    h.use_hot = true;
 }
 
 // Exclusive scan of a[0..n) in place; returns the total.
@@ -482,7 +563,11 @@ static void analyse(CsrHandle &h, hipStream_t s)
     const bool want_panels =
         (h.plan.layout == LAYOUT_PANELS && np_req <= 1024) ||
         (h.plan.layout == LAYOUT_AUTO && panels_eligible(h));
-    if (want_panels && h.rows > 0 && h.nnz > 0) {
+    if (h.plan.layout == LAYOUT_HOT && hot_possible(h)) {
+        build_hot(h, s);
+        h.grid = h.hot.grid;   // one fused-dot partial per workgroup
+        h.fin_blocks = 0;
+    } else if (want_panels && h.rows > 0 && h.nnz > 0) {
         build_panels(h, s);
         h.grid = h.pan.nblk;   // one fused-dot partial per row block
         h.fin_blocks = 0;
@@ -728,6 +813,10 @@ void spmv_enqueue(const CsrHandle &h, const void *x, void *y,
         return;
     if (h.use_panels) {
         launch_spmv_panels(h.dt, h.pan, x, y, epi, w, dot ? h.d_dot_part : nullptr, s);
+        return;
+    }
+    if (h.use_hot) {
+        launch_spmv_hot(h.dt, h.hot, x, y, epi, w, dot ? h.d_dot_part : nullptr, s);
         return;
     }
     const MatDesc d = make_desc(h, x, y, w, h.d_chunk_part);
@@ -1073,8 +1162,8 @@ void run_cg(CsrHandle &h, const double *b, double *x, int iters,
 constexpr int32_t kRelabelRows = 65536;
 
 // Copy of a square graph matrix with its vertices renamed in decreasing
-// out-degree order (stable): the most gathered entries of x become
-// neighbours in memory and stay in cache.  (P A P^T)(P x) = P (A x).
+// out-degree order (stable): the most gathered entries of x come first,
+// where the hot-column layout keeps them in LDS.  (P A P^T)(P x) = P (A x).
 static void build_relabel(CsrHandle &h, PrState &st)
 {
     Context &c = ctx();
@@ -1106,6 +1195,15 @@ static void build_relabel(CsrHandle &h, PrState &st)
                             rp2, col2, vals2, s);
         HIPC(hipStreamSynchronize(s));
         st.g = create_handle(n, h.cols, h.nnz, rp2, col2, vals2, h.dt, 0);
+        if (hot_possible(*st.g)) {
+            // after relabelling the most gathered columns come first: keep
+            // them in LDS (hot-column layout)
+            CsrHandle &g = *st.g;
+            g.dev_bytes -= analysis_bytes(g);
+            g.plan.layout = LAYOUT_HOT;
+            analyse(g, s);
+            g.dev_bytes += analysis_bytes(g);
+        }
         st.xp = (float *)dev_alloc((size_t)n * 4);
     } catch (...) {
         dev_free(deg);
@@ -1264,7 +1362,7 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
             const CsrHandle *h = g->hs[j];
             descs[j] = make_desc(*h, xs[j], ys[j], nullptr,
                                  g->d_chunk ? g->d_chunk + chunk_off[j] : nullptr);
-            if (h->use_panels)
+            if (own_layout(*h))
                 continue;  // launched on its own layout
             for (int32_t k = 0; k < h->nsplit; ++k) {
                 items.push_back(j);
@@ -1275,7 +1373,7 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
         for (int cls = C_SPLIT; cls >= C_W1; --cls)
             for (int j = 0; j < count; ++j)
                 for (const Tile &t : g_extra[g->hs[j]].tiles)
-                    if (!g->hs[j]->use_panels)
+                    if (!own_layout(*g->hs[j]))
                     if ((t.cls & kTileClassMask) == cls) {
                         Tile u = t;
                         u.mat = j;
@@ -1353,11 +1451,11 @@ static void run_batched(int count, const lilac_csr_t *hs, const void *const *xs,
     if (hit->nitems)
         launch_split_finalize(hit->dt, hit->d_items, hit->nitems, none,
                               hit->d_mats, epi_none(), nullptr, s);
-    // matrices kept in the column-panel layout run their own kernel, so each
+    // matrices kept in a layout of their own run their own kernel, so each
     // result is the same as its single call
     for (int j = 0; j < count; ++j) {
         const CsrHandle *h = hit->hs[j];
-        if (h->use_panels)
+        if (own_layout(*h))
             spmv_enqueue(*h, xs[j], ys[j], epi_none(), nullptr, false, s);
     }
 }
@@ -1561,10 +1659,12 @@ static double tune_handle(CsrHandle &h)
             p.grid_per_cu = gp;
             trial(p);
         }
-        for (int lay : {LAYOUT_ROWS, LAYOUT_PANELS}) {
+        for (int lay : {LAYOUT_ROWS, LAYOUT_PANELS, LAYOUT_HOT}) {
             Plan p = best;
             p.layout = lay;
             if (lay == LAYOUT_PANELS && !panels_eligible(h))
+                continue;
+            if (lay == LAYOUT_HOT && (!hot_possible(h) || h.rows < 32768))
                 continue;
             trial(p);
         }
@@ -1755,7 +1855,7 @@ int lilac_csr_info(lilac_csr_t hh, lilac_csr_info_t *out)
         out->chunk = h->plan.chunk;
         out->nchunks = h->nchunks;
         out->ntiles = h->ntiles;
-        out->layout = h->use_panels ? LAYOUT_PANELS : LAYOUT_ROWS;
+        out->layout = h->use_panels ? LAYOUT_PANELS : h->use_hot ? LAYOUT_HOT : LAYOUT_ROWS;
         out->npanels = h->use_panels ? h->pan.np : 0;
     });
 }
@@ -1934,7 +2034,7 @@ int lilac_bfs(lilac_csr_t hh, int source, int *level, int *nlevels, void *stream
         launch_fill_i32(level, h->rows, -1, s);
         launch_fill_i32(level + source, 1, 0, s);
         const MatDesc m = make_desc(*h, nullptr, nullptr, nullptr, nullptr);
-        const int32_t grid = h->use_panels ? tile_grid(h->dt) : h->grid;
+        const int32_t grid = own_layout(*h) ? tile_grid(h->dt) : h->grid;
         int32_t depth = 0;
         for (;; ++depth) {
             launch_fill_i32(c.status, 1, 0, s);

@@ -404,8 +404,8 @@ void run_tick(Server *S)
         const int j = (int)descs.size();
         const double *in = r->in ? r->in : m.vin;
         double *out = r->out ? r->out : m.vout;
-        if (m.h->use_panels) {
-            // column-panel matrices run their own product kernel
+        if (own_layout(*m.h)) {
+            // matrices in a layout of their own run their own product kernel
             own.push_back(r);
         } else if (r->kind == LILAC_REQ_SPMV) {
             descs.push_back(make_desc(*m.h, in, out, nullptr, sl.chunk));
@@ -435,7 +435,7 @@ void run_tick(Server *S)
             step_blocks += sg.nb;
             step.push_back(sg);
         }
-        if (m.h->use_panels)
+        if (own_layout(*m.h))
             continue;
         prefix.push_back(prefix.back() + m.h->ntiles);
         for (int32_t k = 0; k < m.h->nsplit; ++k) {

@@ -319,3 +319,83 @@ def test_panel_layout_unaligned_x():
     h.spmv(buf[1:], yd)
     check_spmv(A, x, _host(yd), TOL_F64)
     h.destroy()
+
+
+HOT_MATS = {
+    "ragged_long_rows": lambda: gen.ragged(3000, 40000, seed=1, max_len=300,
+                                           long_rows=3, long_len=20000),
+    "mostly_empty_all_hot": lambda: gen.ragged(5000, 5000, seed=3, empty_frac=0.7),
+    "one_long_row": lambda: gen.ragged(1, 200000, seed=4, long_rows=1,
+                                       long_len=150000, empty_frac=0.0),
+    "rmat16": lambda: gen.rmat_pagerank(16, 1 << 20, seed=5).astype(np.float64),
+    "random5_60": lambda: gen.random_rows(30000, 5, 60, seed=7),
+    "stencil27": lambda: gen.stencil(12, 27),
+    "cols_2p22": lambda: gen.random_rows(5000, 1, 20, seed=10, cols=1 << 22),
+    "cols_one": lambda: gen.random_rows(3000, 1, 1, seed=11, cols=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(HOT_MATS))
+def test_hot_layout_parity(name):
+    """Hot-column layout (columns below the LDS width staged, the rest
+    gathered): float64 and float32 within tolerance, integer data exact,
+    repeated calls bitwise equal."""
+    A = HOT_MATS[name]()
+    x = gen.vector(A.cols, 70)
+    h = L.Csr.from_gen(A, cols=A.cols)
+    h.set_layout(L.LAYOUT_HOT)
+    assert h.info().layout == L.LAYOUT_HOT, name
+    xd = _dev(x)
+    yd = torch.full((A.rows,), np.nan, dtype=torch.float64, device=DEV)
+    h.spmv(xd, yd)
+    y = _host(yd)
+    check_spmv(A, x, y, TOL_F64)
+    h.spmv(xd, yd)
+    assert np.array_equal(_host(yd), y)
+    h.destroy()
+    B = A.astype(np.float32)
+    x32 = gen.vector(B.cols, 71, dtype=np.float32)
+    h = L.Csr.from_gen(B, cols=B.cols)
+    h.set_layout(L.LAYOUT_HOT)
+    yd = torch.empty(B.rows, dtype=torch.float32, device=DEV)
+    h.spmv(_dev(x32), yd)
+    check_spmv(B, x32, _host(yd), TOL_F32)
+    h.destroy()
+    A.vals = gen.int_vector(A.nnz, 72)
+    xi = gen.int_vector(A.cols, 73)
+    h = L.Csr.from_gen(A, cols=A.cols)
+    h.set_layout(L.LAYOUT_HOT)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(xi), yd)
+    assert np.array_equal(_host(yd), oracle.spmv_csr(A.row_ptr, A.col_idx, A.vals, xi))
+    h.destroy()
+
+
+def test_hot_layout_fused_dot_unaligned_x_and_fallback():
+    A = gen.ragged(20000, 60000, seed=12, max_len=200, long_rows=4, long_len=30000)
+    h = L.Csr.from_gen(A, cols=A.cols)
+    h.set_layout(L.LAYOUT_HOT)
+    x = gen.vector(A.cols, 74)
+    w = gen.vector(A.rows, 75)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    out = torch.empty(1, dtype=torch.float64, device=DEV)
+    h.spmv_dot(_dev(x), yd, _dev(w), out)
+    y = _host(yd)
+    check_spmv(A, x, y, TOL_F64)
+    assert abs(_host(out)[0] - oracle.dot(w, y)) <= TOL_F64 * oracle.dot_abs(w, y)
+    # x 8 bytes past a 16-byte boundary: scalar staging of the hot columns
+    buf = torch.empty(A.cols + 1, dtype=torch.float64, device=DEV)
+    buf[1:] = _dev(x)
+    yd2 = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(buf[1:], yd2)
+    assert np.array_equal(_host(yd2), y)
+    h.destroy()
+    # no entries: the layout is not built, the product still overwrites y
+    E = gen.empty_matrix(1000, 10)
+    he = L.Csr.from_gen(E, cols=E.cols)
+    he.set_layout(L.LAYOUT_HOT)
+    assert he.info().layout == L.LAYOUT_ROWS
+    yd = torch.full((1000,), np.nan, dtype=torch.float64, device=DEV)
+    he.spmv(_dev(np.ones(10)), yd)
+    assert np.array_equal(_host(yd), np.zeros(1000))
+    he.destroy()
