@@ -467,18 +467,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
 // in order: the additions are in a fixed order given by the matrix and the
 // layout.
 template <typename V, bool DOT>
-__global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
-    PanelDesc pd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
-    const V *__restrict__ w, double *__restrict__ dot_part)
+__device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
+                                            const V *__restrict__ x,
+                                            V *__restrict__ y, const Epi &epi,
+                                            const V *__restrict__ w,
+                                            double *__restrict__ dot_part,
+                                            unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     double *acc = (double *)smem;                                 // row sums
     V *xs = (V *)(smem + kPanelMaxRb * sizeof(double));           // x panel
     constexpr int VV = 16 / sizeof(V);
     typedef V vec_t __attribute__((ext_vector_type(VV)));
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int32_t b = blockIdx.x;
     const int32_t r0 = b * pd.rb;
     const int32_t nr = min(pd.rb, pd.rows - r0);
     const V *pv = (const V *)pd.vals;
@@ -560,7 +561,83 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
     if (DOT) {
         const double tot = block_sum<kPanelWaves>(dacc, (double *)xs);
         if (threadIdx.x == 0)
-            dot_part[blockIdx.x] = tot;
+            dot_part[b] = tot;
+    }
+}
+
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kPanelThreads) void k_spmv_panels(
+    PanelDesc pd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
+    const V *__restrict__ w, double *__restrict__ dot_part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    panel_block<V, DOT>(pd, blockIdx.x, x, y, epi, w, dot_part, smem);
+}
+
+// Column-panel products of many matrices in one launch: workgroup g takes
+// row block g - prefix[j] of matrix j (prefix[j] <= g < prefix[j + 1]).
+// Each block runs exactly as in the single-matrix kernel.
+template <typename V>
+__global__ __launch_bounds__(kPanelThreads) void k_spmv_panels_grouped(
+    const PanelDesc *__restrict__ descs, const PanelIO *__restrict__ io,
+    const int32_t *__restrict__ prefix, int32_t nmat)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t g = blockIdx.x;
+    int32_t lo = 0, hi = nmat - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const PanelDesc pd = descs[lo];
+    const Epi epi{EPI_NONE, 0, 0.0, 0.0};
+    panel_block<V, false>(pd, g - prefix[lo], (const V *)io[lo].x, (V *)io[lo].y,
+                          epi, nullptr, nullptr, smem);
+}
+
+// Distinct x cache lines among the non-zeros of sampled row groups (see
+// launch_line_reuse).  The count is a union of bits, so it does not depend
+// on the order of the atomic updates.
+__global__ __launch_bounds__(kBlock) void k_line_reuse(int32_t rows,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       int32_t ngroups, int32_t shift,
+                                                       int32_t *__restrict__ out)
+{
+    __shared__ uint32_t bits[512];
+    __shared__ int32_t red[kWaves];
+    for (int i = threadIdx.x; i < 512; i += kBlock)
+        bits[i] = 0u;
+    __syncthreads();
+    const int64_t groups = ((int64_t)rows + 63) / 64;
+    const int32_t grp = (int32_t)((int64_t)blockIdx.x * groups / ngroups);
+    const int32_t r0 = grp * 64;
+    const int32_t r1 = min(rows, r0 + 64);
+    const int32_t k0 = rp[r0];
+    const int32_t k1 = min(rp[r1], k0 + 8192);
+    for (int32_t k = k0 + threadIdx.x; k < k1; k += kBlock) {
+        const uint32_t line = (uint32_t)col[k] >> shift;
+        atomicOr(&bits[(line >> 5) & 511u], 1u << (line & 31u));
+    }
+    __syncthreads();
+    int32_t cnt = 0;
+    for (int i = threadIdx.x; i < 512; i += kBlock)
+        cnt += __popc(bits[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        cnt += __shfl_down(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int i = 0; i < kWaves; ++i)
+            t += red[i];
+        out[2 * blockIdx.x] = k1 - k0;
+        out[2 * blockIdx.x + 1] = t;
     }
 }
 
@@ -1812,6 +1889,32 @@ void launch_spmv_panels(lilac_dtype dt, const PanelDesc &pd, const void *x,
     check_launch("k_spmv_panels");
 }
 
+void launch_spmv_panels_grouped(lilac_dtype dt, const PanelDesc *descs,
+                                const PanelIO *io, const int32_t *prefix,
+                                int32_t nmat, int32_t nblocks, hipStream_t s)
+{
+    if (nmat <= 0 || nblocks <= 0)
+        return;
+    dim3 g(nblocks), b(kPanelThreads);
+    if (dt == LILAC_F64)
+        hipLaunchKernelGGL(k_spmv_panels_grouped<double>, g, b, kPanelLds, s, descs,
+                           io, prefix, nmat);
+    else
+        hipLaunchKernelGGL(k_spmv_panels_grouped<float>, g, b, kPanelLds, s, descs,
+                           io, prefix, nmat);
+    check_launch("k_spmv_panels_grouped");
+}
+
+void launch_line_reuse(int32_t rows, const int32_t *rp, const int32_t *col,
+                       int32_t ngroups, int32_t shift, int32_t *out, hipStream_t s)
+{
+    if (rows <= 0 || ngroups <= 0)
+        return;
+    hipLaunchKernelGGL(k_line_reuse, dim3(ngroups), dim3(kBlock), 0, s, rows, rp, col,
+                       ngroups, shift, out);
+    check_launch("k_line_reuse");
+}
+
 void launch_spmv_hot(lilac_dtype dt, const HotDesc &hd, const void *x, void *y,
                      const Epi &epi, const void *w, double *dot_part, hipStream_t s)
 {
@@ -1869,6 +1972,10 @@ void panels_prepare()
     static bool done = false;
     if (done)
         return;
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_panels_grouped<double>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
+    HIPC(hipFuncSetAttribute((const void *)k_spmv_panels_grouped<float>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
     HIPC(hipFuncSetAttribute((const void *)k_spmv_hot<double, true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, kPanelLds));
     HIPC(hipFuncSetAttribute((const void *)k_spmv_hot<double, false>,

@@ -106,6 +106,11 @@ struct PanelDesc {
     int32_t pw, np, rb, nblk, rw;
     int32_t pad;
 };
+// Vectors of one matrix in a grouped panel launch.
+struct PanelIO {
+    const void *x;
+    void *y;
+};
 constexpr int kPanelThreads = 1024;            // 16 wave64: one workgroup per CU
 constexpr int kPanelWaves = kPanelThreads / 64;
 constexpr int kPanelMaxRb = 1024;              // rows per block (sums in LDS)
@@ -165,6 +170,9 @@ struct CsrHandle {
     double *d_chunk_part = nullptr;
     Tile *d_tiles = nullptr;
     double *d_dot_part = nullptr;   // one per persistent workgroup + finaliser
+    // distinct 128-byte lines of x per non-zero in sampled groups of 64
+    // rows (near 1: scattered columns; -1: not measured)
+    double line_ratio = -1.0;
     // column-panel layout (when use_panels)
     bool use_panels = false;
     PanelDesc pan{};
@@ -257,6 +265,17 @@ void launch_panel_scatter(lilac_dtype dt, const PanelDesc &pd, const int32_t *rp
                           void *pv, uint32_t *prc, hipStream_t s);
 void launch_panel_wptr(const PanelDesc &pd, const int32_t *ptr, int32_t *wptr,
                        hipStream_t s);
+// Column-panel products of nmat matrices in one launch of nblocks
+// workgroups: matrix j owns workgroups [prefix[j], prefix[j+1]).  Each
+// result equals the single-matrix launch bit for bit.
+void launch_spmv_panels_grouped(lilac_dtype dt, const PanelDesc *descs,
+                                const PanelIO *io, const int32_t *prefix,
+                                int32_t nmat, int32_t nblocks, hipStream_t s);
+// For ngroups groups of 64 consecutive rows spread over the matrix:
+// out[2g] = non-zeros looked at (at most 8192), out[2g+1] = distinct
+// (col >> shift) among them, hashed into 16384 bins.
+void launch_line_reuse(int32_t rows, const int32_t *rp, const int32_t *col,
+                       int32_t ngroups, int32_t shift, int32_t *out, hipStream_t s);
 // Lets the panel kernels use the whole LDS of a CU (once per process).
 void panels_prepare();
 // Hot-column product (see HotDesc): hd.grid persistent workgroups take the

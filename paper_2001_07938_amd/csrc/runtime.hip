@@ -311,27 +311,71 @@ static int64_t panel_count(const CsrHandle &h)
     return h.cols > 0 ? ((int64_t)h.cols + panel_cols(h.dt) - 1) / panel_cols(h.dt) : 0;
 }
 
-// Whether the column-panel layout suits the matrix.  Every row block (one
-// per CU, at least) copies all of x into LDS once, so the layout pays off
-// when that copy traffic is small next to the matrix: at most twice the
-// matrix bytes.  Also: enough rows to give every CU a block, at most 64
-// panels, and no row longer than the wavefront class (1024).  Smaller or
-// sparser matrices stay on the row-class tiles, which also lets grouped
-// launches take them in one kernel.
+// Rows per block of the column-panel layout: enough blocks for every CU,
+// but at least as many rows as make up the bytes of one copy of x (each
+// block copies all of x into LDS once), and at most kPanelMaxRb.
+static int32_t panel_rows(const CsrHandle &h)
+{
+    if (h.rows == 0)
+        return 1;
+    const double vs = (double)dtype_size(h.dt);
+    const double row_bytes = std::max(1.0, (double)h.nnz / h.rows * (vs + 4.0));
+    const int64_t by_cu = ((int64_t)h.rows + device_cu_count() - 1) / device_cu_count();
+    const int64_t by_x = (int64_t)std::ceil((double)h.cols * vs / row_bytes);
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(kPanelMaxRb, std::max(by_cu, by_x)));
+}
+
+// A matrix is gather-heavy when its non-zeros touch nearly one distinct
+// cache line of x each (scattered columns): then the row-class tiles are
+// bound by the gathers, and copying x through LDS pays.
+constexpr double kGatherHeavy = 0.3;
+
+// Whether the column-panel layout suits the matrix: gather-heavy, at most
+// 64 panels, no row longer than the wavefront class (1024), and the copies
+// of x (one per row block, served from L2) at most four times the matrix
+// bytes.  Other matrices stay on the row-class tiles.
 static bool panels_eligible(const CsrHandle &h)
 {
-    if (h.rows < 32768 || h.nnz == 0)
+    if (h.rows == 0 || h.nnz == 0)
         return false;
     const int64_t np = panel_count(h);
     if (np < 1 || np > 64)
         return false;
     if (h.bin_off[NCLASS] - h.bin_off[C_W64 + 1] > 0)
         return false;  // rows longer than the wavefront class bound
+    if (h.line_ratio < kGatherHeavy)
+        return false;
     const double vs = (double)dtype_size(h.dt);
-    const double nblk = std::max<double>(device_cu_count(),
-                                         std::ceil((double)h.rows / kPanelMaxRb));
+    const int32_t rb = panel_rows(h);
+    const double nblk = std::ceil((double)h.rows / rb);
     const double stage = nblk * (double)h.cols * vs;
-    return stage <= 2.0 * (double)h.nnz * (vs + 4.0);
+    return stage <= 4.0 * (double)h.nnz * (vs + 4.0);
+}
+
+// Distinct x lines per non-zero over up to 256 sampled groups of 64 rows.
+static double measure_line_ratio(const CsrHandle &h, hipStream_t s)
+{
+    if (h.rows == 0 || h.nnz == 0)
+        return 0.0;
+    const int32_t ngroups = (int32_t)std::min<int64_t>(256, ((int64_t)h.rows + 63) / 64);
+    int32_t *d = (int32_t *)dev_alloc((size_t)ngroups * 8);
+    std::vector<int32_t> out((size_t)ngroups * 2);
+    try {
+        launch_line_reuse(h.rows, h.d_row_ptr, h.d_col, ngroups,
+                          h.dt == LILAC_F64 ? 4 : 5, d, s);
+        HIPC(hipMemcpyAsync(out.data(), d, out.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    } catch (...) {
+        dev_free(d);
+        throw;
+    }
+    dev_free(d);
+    int64_t e = 0, l = 0;
+    for (int32_t g = 0; g < ngroups; ++g) {
+        e += out[2 * g];
+        l += out[2 * g + 1];
+    }
+    return e > 0 ? (double)l / (double)e : 0.0;
 }
 
 static int64_t scan_total(int32_t *a, int64_t n, hipStream_t s);
@@ -339,17 +383,13 @@ static int64_t scan_total(int32_t *a, int64_t n, hipStream_t s);
 // Builds the column-panel copy of the matrix (see PanelDesc).
 static void build_panels(CsrHandle &h, hipStream_t s)
 {
-    Context &c = ctx();
     PanelDesc pd{};
     pd.rows = h.rows;
     pd.cols = h.cols;
     pd.pw = panel_cols(h.dt);
     pd.np = (int32_t)panel_count(h);
     panels_prepare();
-    // one resident workgroup per CU, at most kPanelMaxRb rows each
-    int64_t nblk = std::max<int64_t>(c.cu, (h.rows + kPanelMaxRb - 1) / kPanelMaxRb);
-    nblk = std::min<int64_t>(nblk, h.rows);
-    pd.rb = (int32_t)((h.rows + nblk - 1) / nblk);
+    pd.rb = panel_rows(h);
     pd.nblk = (int32_t)((h.rows + pd.rb - 1) / pd.rb);
     pd.rw = (pd.rb + kPanelWaves - 1) / kPanelWaves;
     const int64_t nptr = (int64_t)pd.nblk * pd.np * (pd.rb + 1);
@@ -559,6 +599,8 @@ static void analyse(CsrHandle &h, hipStream_t s)
     h.fin_blocks = (h.nsplit + kBlock - 1) / kBlock;
     // a forced panel layout only needs a bounded number of panels; the
     // automatic choice also needs the matrix to suit it
+    if (h.line_ratio < 0.0)
+        h.line_ratio = measure_line_ratio(h, s);
     const int64_t np_req = panel_count(h);
     const bool want_panels =
         (h.plan.layout == LAYOUT_PANELS && np_req <= 1024) ||
@@ -621,6 +663,7 @@ static void construct(CsrHandle &h, int cols_given, const int32_t *rp,
         fail(LILAC_ERR_CSR, "invalid CSR:" + why);
     }
     h.cols = cols_given >= 0 ? cols_given : st[1] + 1;
+    h.line_ratio = -1.0;  // measured again for the new structure
     Plan tuned;
     if (tune_cache_lookup(h, tuned))
         h.plan = tuned;
@@ -763,6 +806,19 @@ void destroy_handle(CsrHandle *h)
     delete h;
 }
 
+// New values also feed the copies made from the CSR arrays (column panels,
+// hot columns, the relabelled PageRank graph): rebuild those.
+static void values_changed(CsrHandle &h, hipStream_t s)
+{
+    if (own_layout(h)) {
+        h.dev_bytes -= analysis_bytes(h);
+        analyse(h, s);
+        h.dev_bytes += analysis_bytes(h);
+    } else if (h.pr && h.pr->g) {
+        drop_graphs(h);
+    }
+}
+
 // Bring a handle up to date before use (ReadObject: re-construct after a
 // structural change, update after a value change).
 static void refresh(CsrHandle &h, hipStream_t s)
@@ -776,6 +832,7 @@ static void refresh(CsrHandle &h, hipStream_t s)
     } else if (h.dirty_vals) {
         upload_values(h, h.h_vals, s);
         h.dirty_vals = false;
+        values_changed(h, s);
     }
 }
 
@@ -1301,6 +1358,11 @@ struct GroupPlan {
     int32_t *d_items = nullptr;
     double *d_chunk = nullptr;
     int32_t ntiles = 0, grid = 0, nitems = 0;
+    // column-panel matrices of the group: one grouped launch
+    PanelDesc *d_pdesc = nullptr;
+    PanelIO *d_pio = nullptr;
+    int32_t *d_pprefix = nullptr;
+    int32_t npm = 0, pblocks = 0;
 };
 static std::vector<GroupPlan *> g_groups;
 
@@ -1310,6 +1372,9 @@ static void free_group(GroupPlan *g)
     dev_free(g->d_tiles);
     dev_free(g->d_items);
     dev_free(g->d_chunk);
+    dev_free(g->d_pdesc);
+    dev_free(g->d_pio);
+    dev_free(g->d_pprefix);
     delete g;
 }
 
@@ -1394,6 +1459,30 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
             HIPC(hipMemcpyAsync(g->d_items, items.data(), items.size() * 4,
                                 hipMemcpyHostToDevice, s));
         }
+        std::vector<PanelDesc> pdesc;
+        std::vector<PanelIO> pio;
+        std::vector<int32_t> pprefix(1, 0);
+        for (int j = 0; j < count; ++j) {
+            const CsrHandle *h = g->hs[j];
+            if (!h->use_panels || h->rows == 0)
+                continue;
+            pdesc.push_back(h->pan);
+            pio.push_back(PanelIO{xs[j], ys[j]});
+            pprefix.push_back(pprefix.back() + h->pan.nblk);
+        }
+        g->npm = (int32_t)pdesc.size();
+        g->pblocks = pprefix.back();
+        if (g->npm) {
+            g->d_pdesc = (PanelDesc *)dev_alloc(pdesc.size() * sizeof(PanelDesc));
+            g->d_pio = (PanelIO *)dev_alloc(pio.size() * sizeof(PanelIO));
+            g->d_pprefix = (int32_t *)dev_alloc(pprefix.size() * 4);
+            HIPC(hipMemcpyAsync(g->d_pdesc, pdesc.data(), pdesc.size() * sizeof(PanelDesc),
+                                hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(g->d_pio, pio.data(), pio.size() * sizeof(PanelIO),
+                                hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(g->d_pprefix, pprefix.data(), pprefix.size() * 4,
+                                hipMemcpyHostToDevice, s));
+        }
         HIPC(hipStreamSynchronize(s));
     } catch (...) {
         free_group(g);
@@ -1451,11 +1540,13 @@ static void run_batched(int count, const lilac_csr_t *hs, const void *const *xs,
     if (hit->nitems)
         launch_split_finalize(hit->dt, hit->d_items, hit->nitems, none,
                               hit->d_mats, epi_none(), nullptr, s);
-    // matrices kept in a layout of their own run their own kernel, so each
-    // result is the same as its single call
+    // column-panel matrices: one grouped launch whose blocks run exactly as
+    // in each matrix's single call; hot-column matrices: their own launch
+    launch_spmv_panels_grouped(hit->dt, hit->d_pdesc, hit->d_pio, hit->d_pprefix,
+                               hit->npm, hit->pblocks, s);
     for (int j = 0; j < count; ++j) {
         const CsrHandle *h = hit->hs[j];
-        if (own_layout(*h))
+        if (h->use_hot)
             spmv_enqueue(*h, xs[j], ys[j], epi_none(), nullptr, false, s);
     }
 }
@@ -1811,6 +1902,7 @@ int lilac_csr_update_values(lilac_csr_t hh, const void *vals)
         if (is_device_ptr(vals))
             HIPC(hipDeviceSynchronize());
         upload_values(*h, vals, ctx().stream);
+        values_changed(*h, ctx().stream);
         HIPC(hipStreamSynchronize(ctx().stream));
         if (h->flags & LILAC_KEEP_HOST)
             h->h_vals = vals;

@@ -443,12 +443,35 @@ void run_tick(Server *S)
             items.push_back(k);
         }
     }
+    // column-panel products of the tick: one grouped launch
+    std::vector<PanelDesc> pdesc;
+    std::vector<PanelIO> pio;
+    std::vector<int32_t> pprefix(1, 0);
+    std::vector<Req *> own_hot;
+    for (Req *r : own) {
+        SMatrix &m = S->mats[r->mid];
+        Slot &sl = S->slots[r->slot];
+        if (!m.h->use_panels) {
+            own_hot.push_back(r);
+            continue;
+        }
+        pdesc.push_back(m.h->pan);
+        if (r->kind == LILAC_REQ_SPMV)
+            pio.push_back(PanelIO{r->in ? r->in : m.vin, r->out ? r->out : m.vout});
+        else
+            pio.push_back(PanelIO{sl.p, sl.q});
+        pprefix.push_back(pprefix.back() + m.h->pan.nblk);
+    }
     const size_t b_desc = descs.size() * sizeof(MatDesc);
     const size_t b_pre = ((prefix.size() * 4 + 15) / 16) * 16;
     const size_t b_items = ((items.size() * 4 + 15) / 16) * 16;
     const size_t b_init = init.size() * sizeof(CgSeg);
     const size_t b_step = step.size() * sizeof(CgSeg);
-    tick_reserve(tk, b_desc + b_pre + b_items + b_init + b_step + 64);
+    const size_t b_pdesc = pdesc.size() * sizeof(PanelDesc);
+    const size_t b_pio = pio.size() * sizeof(PanelIO);
+    const size_t b_ppre = ((pprefix.size() * 4 + 15) / 16) * 16;
+    tick_reserve(tk, b_desc + b_pre + b_items + b_init + b_step + b_pdesc + b_pio +
+                         b_ppre + 64);
     size_t off = 0;
     auto put = [&](const void *src, size_t n, size_t padded) {
         std::memcpy(tk.host + off, src, n);
@@ -461,6 +484,9 @@ void run_tick(Server *S)
     const size_t o_items = put(items.data(), items.size() * 4, b_items);
     const size_t o_init = put(init.data(), b_init, b_init);
     const size_t o_step = put(step.data(), b_step, b_step);
+    const size_t o_pdesc = put(pdesc.data(), b_pdesc, b_pdesc);
+    const size_t o_pio = put(pio.data(), b_pio, b_pio);
+    const size_t o_ppre = put(pprefix.data(), pprefix.size() * 4, b_ppre);
     HIPC(hipMemcpyAsync(tk.dev, tk.host, off, hipMemcpyHostToDevice, S->stream));
     const MatDesc *d_desc = (const MatDesc *)(tk.dev + o_desc);
     if (!init.empty())
@@ -469,7 +495,11 @@ void run_tick(Server *S)
     launch_spmv_segments(LILAC_F64, d_desc, (const int32_t *)(tk.dev + o_pre),
                          (int32_t)descs.size(), prefix.back(), tile_grid(LILAC_F64),
                          S->stream);
-    for (Req *r : own) {
+    launch_spmv_panels_grouped(LILAC_F64, (const PanelDesc *)(tk.dev + o_pdesc),
+                               (const PanelIO *)(tk.dev + o_pio),
+                               (const int32_t *)(tk.dev + o_ppre), (int32_t)pdesc.size(),
+                               pprefix.back(), S->stream);
+    for (Req *r : own_hot) {
         SMatrix &m = S->mats[r->mid];
         Slot &sl = S->slots[r->slot];
         if (r->kind == LILAC_REQ_SPMV)

@@ -140,3 +140,21 @@ def test_pagerank_cycle_fixed_point():
     h.pagerank(0.85, 20, x)
     assert np.allclose(_host(x), 1e-3, rtol=1e-6, atol=0)
     h.destroy()
+
+
+def test_pagerank_after_value_update():
+    """The relabelled copy PageRank iterates on follows new values."""
+    A = gen.rmat_pagerank(16, 1 << 20, seed=21)
+    n = A.rows
+    d = float(np.float32(0.85))
+    x0 = np.full(n, 1.0 / n, dtype=np.float32)
+    h = L.Csr.from_gen(A)
+    xd = _dev(x0)
+    h.pagerank(d, 3, xd)
+    vals2 = (A.vals * np.float32(0.5)).astype(np.float32)
+    h.update_values(vals2)
+    xd = _dev(x0)
+    h.pagerank(d, 3, xd)
+    ref = oracle.pagerank(A.row_ptr, A.col_idx, vals2, x0.astype(np.float64), d, 3)
+    assert np.sum(np.abs(_host(xd) - ref)) <= 3 * TOL_F32 * np.sum(np.abs(ref))
+    h.destroy()

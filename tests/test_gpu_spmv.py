@@ -399,3 +399,31 @@ def test_hot_layout_fused_dot_unaligned_x_and_fallback():
     he.spmv(_dev(np.ones(10)), yd)
     assert np.array_equal(_host(yd), np.zeros(1000))
     he.destroy()
+
+
+def test_value_updates_reach_panel_and_hot_copies():
+    """The column-panel and hot-column copies hold the values too: new values
+    (update or invalidate) must reach them, and the CG graph built on the old
+    copy must not be replayed."""
+    A = gen.spd_random(40000, 60, seed=6)
+    x = gen.vector(A.cols, 80)
+    b = gen.vector(A.rows, 81)
+    bd = _dev(b)  # same right-hand side and solution arrays: same graph key
+    for lay in (L.LAYOUT_PANELS, L.LAYOUT_HOT):
+        h = L.Csr.from_gen(A)
+        h.set_layout(lay)
+        assert h.info().layout == lay
+        yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+        xd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+        h.spmv(_dev(x), yd)
+        check_spmv(A, x, _host(yd), TOL_F64)
+        h.cg(bd, xd, 20, graph=True)
+        B = gen.Csr(A.rows, A.cols, A.row_ptr, A.col_idx, A.vals * 0.5, "scaled")
+        h.update_values(B.vals)
+        assert h.info().layout == lay
+        h.spmv(_dev(x), yd)
+        check_spmv(B, x, _host(yd), TOL_F64)
+        h.cg(bd, xd, 20, graph=True)
+        x_or, _, _ = oracle.cg(B.row_ptr, B.col_idx, B.vals, b, 20)
+        assert np.max(np.abs(_host(xd) - x_or)) <= 1e-10 * np.max(np.abs(x_or))
+        h.destroy()
