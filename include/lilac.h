@@ -145,7 +145,7 @@ typedef struct {
     int chunk;              /* non-zeros per chunk of a split row */
     int64_t nchunks;        /* entries of the chunk table */
     int ntiles;             /* work tiles of one product */
-    int layout;             /* LILAC_LAYOUT_ROWS, _PANELS or _HOT in use */
+    int layout;             /* LILAC_LAYOUT_ROWS, _PANELS, _HOT or _BAND in use */
     int npanels;            /* column panels (panel layout), else 0 */
 } lilac_csr_info_t;
 int lilac_csr_info(lilac_csr_t h, lilac_csr_info_t *out);
@@ -176,12 +176,16 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * the row-class tiles above.  LILAC_LAYOUT_PANELS: a second, column-panel
  * copy of the matrix in which the columns are cut into panels that fit the
  * LDS and the rows into blocks; each workgroup stages one panel of x in LDS
- * at a time and gathers from there, with 16-bit column offsets.  It suits
- * matrices with many entries per row and panel (scattered columns); for
- * other matrices it is not built.  LILAC_LAYOUT_AUTO (the default) picks it
- * for matrices with at least 32768 rows, at most 64 panels, no row longer
- * than 1024, and x small enough that copying it once per row block costs at
- * most twice the matrix bytes.  LILAC_LAYOUT_HOT: a second copy for
+ * at a time and gathers from there, with 16-bit column offsets.  Row
+ * blocks hold at most 1024 rows, enough blocks for every CU but at least
+ * the rows that weigh as much as one copy of x.  It suits matrices whose
+ * non-zeros scatter over x; for others it is not built.  LILAC_LAYOUT_AUTO
+ * (the default) picks it for gather-heavy matrices (sampled distinct
+ * 128-byte x lines per non-zero at least 0.3, at least 16384 non-zeros)
+ * with at most 64 panels, no
+ * row longer than 1024, and copies of x at most four times the matrix
+ * bytes.  Batched calls run all column-panel matrices of a batch in one
+ * launch, with the same results.  LILAC_LAYOUT_HOT: a second copy for
  * matrices whose most referenced columns have the lowest indices (a graph
  * relabelled by decreasing out-degree, as lilac_pagerank does by itself for
  * graphs of at least 65536 vertices): the first 32512 (float32) or 16256
@@ -189,12 +193,21 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * memory; rows are cut into blocks of at most 2048 rows and about equal
  * non-zeros.  Built only on request and only for matrices with non-zeros;
  * otherwise the rows layout is used (lilac_csr_info reports which).  Every
- * layout gives deterministic results.  Re-runs the analysis.
+ * layout gives deterministic results.  LILAC_LAYOUT_BAND: the CSR order and
+ * values with one extra 32-bit word per non-zero packing the row inside a
+ * block of at most 2048 rows and the column offset from the block's first
+ * column; possible when no block has to span 65536 columns or more (banded
+ * and stencil matrices, small matrices).  The wavefronts stream the
+ * entries and add up each row's run with a segmented scan.  LILAC_LAYOUT_AUTO
+ * picks it for matrices with at least 16384 non-zeros whose columns are
+ * local (sampled distinct 128-byte x lines per non-zero below 0.3) when it
+ * is possible.  Re-runs the analysis.
  */
 #define LILAC_LAYOUT_AUTO (-1)
 #define LILAC_LAYOUT_ROWS 0
 #define LILAC_LAYOUT_PANELS 1
 #define LILAC_LAYOUT_HOT 2
+#define LILAC_LAYOUT_BAND 3
 int lilac_csr_set_layout(lilac_csr_t h, int layout);
 
 /*

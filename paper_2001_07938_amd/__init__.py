@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "liblilac.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "lilac.h")
 
 F64, F32 = 0, 1
-LAYOUT_AUTO, LAYOUT_ROWS, LAYOUT_PANELS, LAYOUT_HOT = -1, 0, 1, 2
+LAYOUT_AUTO, LAYOUT_ROWS, LAYOUT_PANELS, LAYOUT_HOT, LAYOUT_BAND = -1, 0, 1, 2, 3
 KEEP_HOST = 1
 CG_GRAPH = 1
 NCLASS = 9
@@ -291,7 +291,8 @@ class Csr:
         _check(lib().lilac_csr_set_plan(self.handle, _ptr(up), _ptr(rg), chunk))
 
     def set_layout(self, layout: int):
-        """LAYOUT_AUTO (-1), LAYOUT_ROWS (0), LAYOUT_PANELS (1) or LAYOUT_HOT (2)."""
+        """LAYOUT_AUTO (-1), LAYOUT_ROWS (0), LAYOUT_PANELS (1), LAYOUT_HOT (2) or
+        LAYOUT_BAND (3)."""
         _check(lib().lilac_csr_set_layout(self.handle, layout))
 
     def spmv(self, x, y, stream=None):

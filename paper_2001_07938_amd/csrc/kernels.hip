@@ -21,6 +21,37 @@ __device__ __forceinline__ T ld_stream(const T *p)
     return __builtin_nontemporal_load(p);
 }
 
+// A pointer read from a descriptor table is a generic address to the
+// compiler, which then emits flat memory instructions.  These point to
+// device memory: marking them global lets it emit global loads and stores.
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_assume(!__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void *)p));
+    __builtin_assume(!__builtin_amdgcn_is_private((const __attribute__((address_space(0))) void *)p));
+#endif
+    return p;
+}
+
+__device__ __forceinline__ MatDesc global_desc(MatDesc m)
+{
+    m.row_ptr = as_global(m.row_ptr);
+    m.col = as_global(m.col);
+    m.vals = as_global(m.vals);
+    m.bin_rows = as_global(m.bin_rows);
+    m.c_k0 = as_global(m.c_k0);
+    m.c_k1 = as_global(m.c_k1);
+    m.s_first = as_global(m.s_first);
+    m.c_row = as_global(m.c_row);
+    m.x = as_global(m.x);
+    m.y = as_global(m.y);
+    m.w = as_global(m.w);
+    m.chunk_part = as_global(m.chunk_part);
+    m.tiles = as_global(m.tiles);
+    return m;
+}
+
 // Cross-lane move of a double with a DPP pattern (two 32-bit halves).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
@@ -369,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
     double dacc = 0.0;
     for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
         const Tile t = tiles[ti];
-        const MatDesc m = GROUPED ? mats[t.mat] : single;
+        const MatDesc m = GROUPED ? global_desc(mats[t.mat]) : single;
         switch (t.cls & kTileClassMask) {
         case C_W1: rows_by_lanes<V, 1, DOT>(m, t, epi, dacc); break;
         case C_W2: rows_by_lanes<V, 2, DOT>(m, t, epi, dacc); break;
@@ -402,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_split_finalize(
     if (i < n) {
         const int32_t mi = GROUPED ? items[2 * i] : 0;
         const int32_t j = GROUPED ? items[2 * i + 1] : i;
-        const MatDesc m = GROUPED ? mats[mi] : single;
+        const MatDesc m = GROUPED ? global_desc(mats[mi]) : single;
         const int32_t row = m.bin_rows[m.split_begin + j];
         double s = 0.0;
         for (int32_t c = m.s_first[j]; c < m.s_first[j + 1]; ++c)
@@ -439,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
             else
                 hi = mid;
         }
-        const MatDesc m = mats[lo];
+        const MatDesc m = global_desc(mats[lo]);
         const Tile t = m.tiles[v - prefix[lo]];
         switch (t.cls & kTileClassMask) {
         case C_W1: rows_by_lanes<V, 1, false>(m, t, epi, dacc); break;
@@ -592,10 +623,13 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels_grouped(
         else
             hi = mid - 1;
     }
-    const PanelDesc pd = descs[lo];
+    PanelDesc pd = descs[lo];
+    pd.vals = as_global(pd.vals);
+    pd.rc = as_global(pd.rc);
+    pd.wptr = as_global(pd.wptr);
     const Epi epi{EPI_NONE, 0, 0.0, 0.0};
-    panel_block<V, false>(pd, g - prefix[lo], (const V *)io[lo].x, (V *)io[lo].y,
-                          epi, nullptr, nullptr, smem);
+    panel_block<V, false>(pd, g - prefix[lo], as_global((const V *)io[lo].x),
+                          as_global((V *)io[lo].y), epi, nullptr, nullptr, smem);
 }
 
 // Distinct x cache lines among the non-zeros of sampled row groups (see
@@ -701,15 +735,20 @@ __global__ __launch_bounds__(kBlock) void k_panel_wptr(PanelDesc pd,
 
 // ------------------------------------------------------- hot columns
 
+// Row keys inside a block are below 2^16; this one is past every row.
+constexpr int32_t kKeyEnd = 1 << 16;
+
 // One wavefront's share of a block part [s, e) of the hot-column layout.
 // The part is split evenly by entries, so a row can span wavefronts: the
 // run of the wavefront's first row goes to its carry slot (added after the
 // block, in slot order), every other run is added to the row sum in LDS by
-// the one wavefront where it ends.  HOT: the gather comes from the LDS copy
-// of the hot columns and the row is in the entry's word; otherwise from x
-// in global memory, the row from key[].  The entries of the next chunk are
-// requested before the gathers of the current one are used.
-template <typename V, bool HOT>
+// the one wavefront where it ends.  HOT: the entry's word packs (row << 16)
+// | column offset and the gather reads xsrc[offset] (the LDS copy of the
+// hot columns, or x from a block's first column in the band layout);
+// otherwise the word is the column of x and the row comes from key[].  The
+// entries of the next chunk are requested before the gathers of the
+// current one are used.  NW wavefronts share the part.
+template <typename V, bool HOT, int NW = kPanelWaves>
 __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
                                          const uint32_t *__restrict__ prc,
                                          const uint16_t *__restrict__ pkey,
@@ -721,8 +760,8 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
     typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
     typedef uint16_t kpair_t __attribute__((ext_vector_type(2)));
     const int64_t n = (int64_t)e - s;
-    const int32_t ks = s + (int32_t)(n * wave / kPanelWaves);
-    const int32_t ke = s + (int32_t)(n * (wave + 1) / kPanelWaves);
+    const int32_t ks = s + (int32_t)(n * wave / NW);
+    const int32_t ke = s + (int32_t)(n * (wave + 1) / NW);
     const int32_t kb = ks & ~1;
     pair_t v;
     upair_t rc;
@@ -750,9 +789,9 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
         const int32_t r0 = HOT ? (int32_t)(rc.x >> 16) : (int32_t)kk.x;
         const int32_t r1 = HOT ? (int32_t)(rc.y >> 16) : (int32_t)kk.y;
         // keys ascend along the wavefront: entries before ks belong to the
-        // previous wavefront (-1), entries past ke to nobody (kHotRows)
-        const int32_t k0 = (en < ks) ? -1 : ok0 ? r0 : kHotRows;
-        const int32_t k1 = (en + 1 < ks) ? -1 : ok1 ? r1 : kHotRows;
+        // previous wavefront (-1), entries past ke to nobody (kKeyEnd)
+        const int32_t k0 = (en < ks) ? -1 : ok0 ? r0 : kKeyEnd;
+        const int32_t k1 = (en + 1 < ks) ? -1 : ok1 ? r1 : kKeyEnd;
         // entries outside the share may belong to the other part (another
         // packing): gather element 0 for them, which always exists
         const uint32_t c0 = ok0 ? (HOT ? (rc.x & 0xFFFFu) : rc.x) : 0u;
@@ -777,11 +816,11 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
         const double prev_incl = dpp_f64m<0x138, 0xF>(incl, 0.0);  // wave_shr:1
         const int32_t prev_k1 = dpp_i32<0x138, 0xF>(k1, -2);
         const int32_t next_k0 = next_lane_key(k0);
-        if (k0 != k1 && k0 >= 0 && k0 < kHotRows) {
+        if (k0 != k1 && k0 >= 0 && k0 < kKeyEnd) {
             double *t = (k0 == first) ? csum : acc + k0;
             *t += (prev_k1 == k0) ? prev_incl + p0 : p0;
         }
-        if (next_k0 != k1 && k1 >= 0 && k1 < kHotRows) {
+        if (next_k0 != k1 && k1 >= 0 && k1 < kKeyEnd) {
             double *t = (k1 == first) ? csum : acc + k1;
             *t += incl;
         }
@@ -878,6 +917,146 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
         if (threadIdx.x == 0)
             dot_part[blockIdx.x] = tot;
     }
+}
+
+// ------------------------------------------------------------- band
+
+// Product over the band layout (see BandDesc): one workgroup per row block,
+// its wavefronts share the block's entries evenly (a row can span them),
+// gather from x starting at the block's first column, and the carries of
+// rows split between wavefronts are added in slot order by one lane each.
+template <typename V, bool DOT>
+__device__ __forceinline__ void band_block(const BandDesc &bd, int32_t b,
+                                           const V *__restrict__ x,
+                                           V *__restrict__ y, const Epi &epi,
+                                           const V *__restrict__ w,
+                                           double *__restrict__ dot_part,
+                                           unsigned char *smem)
+{
+    double *acc = (double *)smem;                                  // row sums
+    double *csum = (double *)(smem + kBandRows * 8);               // carries
+    int32_t *ckey = (int32_t *)(smem + kBandRows * 8 + kBandWaves * 8);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t r0 = bd.brow[b];
+    const int32_t nr = bd.brow[b + 1] - r0;
+    for (int32_t i = threadIdx.x; i < nr; i += kBandThreads)
+        acc[i] = 0.0;
+    __syncthreads();
+    hot_part<V, true, kBandWaves>((const V *)bd.vals, bd.rc, nullptr, bd.bent[b],
+                                  bd.bent[b + 1], x + bd.cbase[b], acc, ckey + wave,
+                                  csum + wave, wave, lane);
+    __syncthreads();
+    if (wave == 0) {
+        const int32_t k = (lane < kBandWaves) ? ckey[lane] : -1;
+        const double c = (lane < kBandWaves) ? csum[lane] : 0.0;
+        bool lead = k >= 0;
+        double t = 0.0;
+        for (int j = 0; j < kBandWaves; ++j) {
+            const int32_t kj = __builtin_amdgcn_readlane(k, j);
+            const double cj = readlane_f64(c, j);
+            if (kj == k) {
+                if (j < lane)
+                    lead = false;
+                else
+                    t += cj;
+            }
+        }
+        if (lead)
+            acc[k] += t;
+    }
+    __syncthreads();
+    double dacc = 0.0;
+    for (int32_t i = threadIdx.x; i < nr; i += kBandThreads) {
+        const V out = epilogue<V>(acc[i], epi);
+        y[r0 + i] = out;
+        if (DOT)
+            dacc = fma((double)w[r0 + i], (double)out, dacc);
+    }
+    if (DOT) {
+        const double tot = block_sum<kBandWaves>(dacc, csum);
+        if (threadIdx.x == 0)
+            dot_part[b] = tot;
+    }
+}
+
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kBandThreads) void k_spmv_band(
+    BandDesc bd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
+    const V *__restrict__ w, double *__restrict__ dot_part)
+{
+    __shared__ __align__(16) unsigned char smem[kBandLds];
+    band_block<V, DOT>(bd, blockIdx.x, x, y, epi, w, dot_part, smem);
+}
+
+// Band products of many matrices in one launch: workgroup g takes row
+// block g - prefix[j] of matrix j, exactly as its single launch does.
+template <typename V>
+__global__ __launch_bounds__(kBandThreads) void k_spmv_band_grouped(
+    const BandDesc *__restrict__ descs, const PanelIO *__restrict__ io,
+    const int32_t *__restrict__ prefix, int32_t nmat)
+{
+    __shared__ __align__(16) unsigned char smem[kBandLds];
+    const int32_t g = blockIdx.x;
+    int32_t lo = 0, hi = nmat - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    BandDesc bd = descs[lo];
+    bd.vals = as_global(bd.vals);
+    bd.rc = as_global(bd.rc);
+    bd.brow = as_global(bd.brow);
+    bd.bent = as_global(bd.bent);
+    bd.cbase = as_global(bd.cbase);
+    const Epi epi{EPI_NONE, 0, 0.0, 0.0};
+    band_block<V, false>(bd, g - prefix[lo], as_global((const V *)io[lo].x),
+                         as_global((V *)io[lo].y), epi, nullptr, nullptr, smem);
+}
+
+// Smallest and largest column of every row (INT_MAX / -1 for empty rows).
+__global__ __launch_bounds__(kBlock) void k_row_span(int32_t rows,
+                                                     const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     int32_t *__restrict__ lo,
+                                                     int32_t *__restrict__ hi)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= rows)
+        return;
+    int32_t a = INT_MAX, z = -1;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        a = min(a, col[k]);
+        z = max(z, col[k]);
+    }
+    lo[i] = a;
+    hi[i] = z;
+}
+
+// Band words of every entry: (row in block << 16) | (col - block's base).
+__global__ __launch_bounds__(kBlock) void k_band_pack(BandDesc bd,
+                                                      const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col,
+                                                      uint32_t *__restrict__ rc)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= bd.rows)
+        return;
+    int32_t lo = 0, hi = bd.nblk - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (bd.brow[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const uint32_t rl = (uint32_t)(i - bd.brow[lo]);
+    const int32_t base = bd.cbase[lo];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        rc[k] = (rl << 16) | (uint32_t)(col[k] - base);
 }
 
 // Hot entries of each row (one thread per row).
@@ -1903,6 +2082,60 @@ void launch_spmv_panels_grouped(lilac_dtype dt, const PanelDesc *descs,
         hipLaunchKernelGGL(k_spmv_panels_grouped<float>, g, b, kPanelLds, s, descs,
                            io, prefix, nmat);
     check_launch("k_spmv_panels_grouped");
+}
+
+void launch_spmv_band(lilac_dtype dt, const BandDesc &bd, const void *x, void *y,
+                      const Epi &epi, const void *w, double *dot_part, hipStream_t s)
+{
+    if (bd.nblk <= 0)
+        return;
+    dim3 g(bd.nblk), b(kBandThreads);
+    if (dt == LILAC_F64) {
+        if (dot_part)
+            hipLaunchKernelGGL((k_spmv_band<double, true>), g, b, 0, s, bd,
+                               (const double *)x, (double *)y, epi, (const double *)w, dot_part);
+        else
+            hipLaunchKernelGGL((k_spmv_band<double, false>), g, b, 0, s, bd,
+                               (const double *)x, (double *)y, epi, (const double *)w, dot_part);
+    } else {
+        if (dot_part)
+            fail(LILAC_ERR_UNSUPPORTED, "fused dot is only provided for float64");
+        hipLaunchKernelGGL((k_spmv_band<float, false>), g, b, 0, s, bd,
+                           (const float *)x, (float *)y, epi, (const float *)w, dot_part);
+    }
+    check_launch("k_spmv_band");
+}
+
+void launch_spmv_band_grouped(lilac_dtype dt, const BandDesc *descs, const PanelIO *io,
+                              const int32_t *prefix, int32_t nmat, int32_t nblocks,
+                              hipStream_t s)
+{
+    if (nmat <= 0 || nblocks <= 0)
+        return;
+    dim3 g(nblocks), b(kBandThreads);
+    if (dt == LILAC_F64)
+        hipLaunchKernelGGL(k_spmv_band_grouped<double>, g, b, 0, s, descs, io, prefix, nmat);
+    else
+        hipLaunchKernelGGL(k_spmv_band_grouped<float>, g, b, 0, s, descs, io, prefix, nmat);
+    check_launch("k_spmv_band_grouped");
+}
+
+void launch_row_span(int32_t rows, const int32_t *rp, const int32_t *col, int32_t *lo,
+                     int32_t *hi, hipStream_t s)
+{
+    if (rows <= 0)
+        return;
+    hipLaunchKernelGGL(k_row_span, dim3(grid_for(rows, kBlock, INT_MAX)), dim3(kBlock), 0,
+                       s, rows, rp, col, lo, hi);
+    check_launch("k_row_span");
+}
+
+void launch_band_pack(const BandDesc &bd, const int32_t *rp, const int32_t *col,
+                      uint32_t *rc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_band_pack, dim3(grid_for(bd.rows, kBlock, INT_MAX)), dim3(kBlock),
+                       0, s, bd, rp, col, rc);
+    check_launch("k_band_pack");
 }
 
 void launch_line_reuse(int32_t rows, const int32_t *rp, const int32_t *col,

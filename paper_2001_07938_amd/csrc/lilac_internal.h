@@ -84,12 +84,13 @@ struct Plan {
     int32_t rpg[NCLASS];    // rows per lane group per tile
     int32_t chunk;          // non-zeros per split-row chunk
     int32_t grid_per_cu;    // persistent workgroups per compute unit
-    int32_t layout;         // LAYOUT_AUTO, LAYOUT_ROWS, LAYOUT_PANELS or LAYOUT_HOT
+    int32_t layout;         // LAYOUT_AUTO, _ROWS, _PANELS, _HOT or _BAND
 };
 
 // Device layouts of a matrix for the product: the row-class tiles over the
 // CSR arrays, or column panels (x staged in LDS one panel at a time).
-enum : int32_t { LAYOUT_AUTO = -1, LAYOUT_ROWS = 0, LAYOUT_PANELS = 1, LAYOUT_HOT = 2 };
+enum : int32_t { LAYOUT_AUTO = -1, LAYOUT_ROWS = 0, LAYOUT_PANELS = 1, LAYOUT_HOT = 2,
+                 LAYOUT_BAND = 3 };
 
 // Column-panel layout: the columns are cut into panels of `pw` (a panel of
 // x fits the LDS), the rows into blocks of `rb`.  Within row block b and
@@ -148,6 +149,25 @@ constexpr int hot_width(int vsize)
     return ((kPanelLds - kHotLdsHead) / vsize) & ~63;
 }
 
+// Band layout, for matrices whose rows reach only nearby columns: the CSR
+// order and values are kept, and each entry gets a 32-bit word
+// (row inside its block << 16) | (column - cbase[b]).  Rows are cut into
+// blocks of at most kBandRows rows, about the same number of entries, and
+// a column span below 65536; block b holds rows [brow[b], brow[b+1]) and
+// the entries [bent[b], bent[b+1]).
+struct BandDesc {
+    const void *vals;        // the CSR values
+    const uint32_t *rc;      // [nnz + pad]
+    const int32_t *brow;     // [nblk + 1]
+    const int32_t *bent;     // [nblk + 1]
+    const int32_t *cbase;    // [nblk]
+    int32_t rows, cols, nblk, pad;
+};
+constexpr int kBandThreads = 256;
+constexpr int kBandWaves = kBandThreads / 64;
+constexpr int kBandRows = 2048;                            // rows per block
+constexpr int kBandLds = kBandRows * 8 + kBandWaves * 12 + 16;
+
 Plan default_plan();
 
 struct CgState;      // device buffers + graph cache of a CG solve
@@ -186,6 +206,11 @@ struct CsrHandle {
     uint32_t *d_hrc = nullptr;
     uint16_t *d_hkey = nullptr;
     int32_t *d_hb = nullptr;        // brow | bent | bsplit
+    // band layout (when use_band)
+    bool use_band = false;
+    BandDesc band{};
+    uint32_t *d_brc = nullptr;
+    int32_t *d_bb = nullptr;        // brow | bent | cbase
     std::vector<int32_t> bin_off;   // NCLASS+1
     int64_t nchunks = 0;
     int32_t nsplit = 0;
@@ -206,7 +231,10 @@ size_t dtype_size(lilac_dtype dt);
 
 // Whether the product runs on a layout of its own (column panels or hot
 // columns) rather than on the row-class tiles.
-inline bool own_layout(const CsrHandle &h) { return h.use_panels || h.use_hot; }
+inline bool own_layout(const CsrHandle &h)
+{
+    return h.use_panels || h.use_hot || h.use_band;
+}
 
 // ---- errors ---------------------------------------------------------------
 struct Error {
@@ -271,6 +299,19 @@ void launch_panel_wptr(const PanelDesc &pd, const int32_t *ptr, int32_t *wptr,
 void launch_spmv_panels_grouped(lilac_dtype dt, const PanelDesc *descs,
                                 const PanelIO *io, const int32_t *prefix,
                                 int32_t nmat, int32_t nblocks, hipStream_t s);
+// Band product (see BandDesc): one workgroup per row block; dot_part (or
+// null) receives one partial per block.
+void launch_spmv_band(lilac_dtype dt, const BandDesc &bd, const void *x, void *y,
+                      const Epi &epi, const void *w, double *dot_part, hipStream_t s);
+// Band products of nmat matrices in one launch (as for column panels).
+void launch_spmv_band_grouped(lilac_dtype dt, const BandDesc *descs, const PanelIO *io,
+                              const int32_t *prefix, int32_t nmat, int32_t nblocks,
+                              hipStream_t s);
+// lo[i], hi[i] = smallest and largest column of row i (INT_MAX, -1 if empty).
+void launch_row_span(int32_t rows, const int32_t *rp, const int32_t *col, int32_t *lo,
+                     int32_t *hi, hipStream_t s);
+void launch_band_pack(const BandDesc &bd, const int32_t *rp, const int32_t *col,
+                      uint32_t *rc, hipStream_t s);
 // For ngroups groups of 64 consecutive rows spread over the matrix:
 // out[2g] = non-zeros looked at (at most 8192), out[2g+1] = distinct
 // (col >> shift) among them, hashed into 16384 bins.

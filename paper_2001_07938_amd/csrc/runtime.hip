@@ -251,7 +251,7 @@ static void check_plan(const Plan &p)
         fail(LILAC_ERR_ARG, "chunk must be in [256, 2^24]");
     if (p.grid_per_cu < 1 || p.grid_per_cu > 32)
         fail(LILAC_ERR_ARG, "grid_per_cu must be in [1, 32]");
-    if (p.layout < LAYOUT_AUTO || p.layout > LAYOUT_HOT)
+    if (p.layout < LAYOUT_AUTO || p.layout > LAYOUT_BAND)
         fail(LILAC_ERR_ARG, "unknown layout");
 }
 
@@ -279,6 +279,10 @@ static void free_analysis(CsrHandle &h)
     dev_free_reset(h.d_hrc);
     dev_free_reset(h.d_hkey);
     dev_free_reset(h.d_hb);
+    dev_free_reset(h.d_brc);
+    dev_free_reset(h.d_bb);
+    h.use_band = false;
+    h.band = BandDesc{};
     h.use_panels = false;
     h.pan = PanelDesc{};
     h.use_hot = false;
@@ -301,6 +305,8 @@ static int64_t analysis_bytes(const CsrHandle &h)
     if (h.use_hot)
         b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 6) +
              (int64_t)(3 * h.hot.nblk + 2) * 4;
+    if (h.use_band)
+        b += (h.nnz + kPad) * 4 + (int64_t)(3 * h.band.nblk + 2) * 4;
     return b;
 }
 
@@ -329,6 +335,10 @@ static int32_t panel_rows(const CsrHandle &h)
 // cache line of x each (scattered columns): then the row-class tiles are
 // bound by the gathers, and copying x through LDS pays.
 constexpr double kGatherHeavy = 0.3;
+// Smallest matrix given the column-panel or band layout automatically;
+// smaller ones stay on the row-class tiles (one grouped launch takes them
+// all in a batch).
+constexpr int64_t kOwnLayoutMinNnz = 16384;
 
 // Whether the column-panel layout suits the matrix: gather-heavy, at most
 // 64 panels, no row longer than the wavefront class (1024), and the copies
@@ -336,7 +346,7 @@ constexpr double kGatherHeavy = 0.3;
 // bytes.  Other matrices stay on the row-class tiles.
 static bool panels_eligible(const CsrHandle &h)
 {
-    if (h.rows == 0 || h.nnz == 0)
+    if (h.rows == 0 || h.nnz < kOwnLayoutMinNnz)
         return false;
     const int64_t np = panel_count(h);
     if (np < 1 || np > 64)
@@ -495,6 +505,82 @@ static void build_hot(CsrHandle &h, hipStream_t s)
     h.use_hot = true;
 }
 
+// Builds the band copy of the matrix (see BandDesc) if every row spans
+// fewer than 65536 columns; returns whether it did.  Block bounds are chosen
+// on the host: a new block starts when the current one has kBandRows rows,
+// `target` entries or more, or would span 65536 columns or more.
+static bool build_band(CsrHandle &h, hipStream_t s)
+{
+    if (h.rows == 0 || h.nnz == 0)
+        return false;
+    std::vector<int32_t> lo((size_t)h.rows), hi((size_t)h.rows), rp((size_t)h.rows + 1);
+    int32_t *d = (int32_t *)dev_alloc((size_t)h.rows * 8);
+    try {
+        launch_row_span(h.rows, h.d_row_ptr, h.d_col, d, d + h.rows, s);
+        HIPC(hipMemcpyAsync(lo.data(), d, (size_t)h.rows * 4, hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(hi.data(), d + h.rows, (size_t)h.rows * 4,
+                            hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(rp.data(), h.d_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    } catch (...) {
+        dev_free(d);
+        throw;
+    }
+    dev_free(d);
+    // about eight blocks per CU (they run eight at a time on one), between
+    // 1024 entries (short chains for small matrices) and 16384
+    const int64_t target = std::min<int64_t>(
+        16384, std::max<int64_t>(1024, h.nnz / ((int64_t)ctx().cu * 8)));
+    std::vector<int32_t> brow{0}, cbase;
+    int32_t start = 0;
+    int64_t bmin = INT64_MAX, bmax = -1;
+    for (int32_t r = 0; r < h.rows; ++r) {
+        if (hi[r] >= 0 && (int64_t)hi[r] - lo[r] >= 65536)
+            return false;  // one row alone is too wide
+        const int64_t nmin = hi[r] >= 0 ? std::min<int64_t>(bmin, lo[r]) : bmin;
+        const int64_t nmax = hi[r] >= 0 ? std::max<int64_t>(bmax, hi[r]) : bmax;
+        const bool wide = nmax >= 0 && nmax - nmin >= 65536;
+        if (r > start && (r - start >= kBandRows || (int64_t)rp[r] - rp[start] >= target ||
+                          wide)) {
+            cbase.push_back(bmax >= 0 ? (int32_t)bmin : 0);
+            brow.push_back(r);
+            start = r;
+            bmin = hi[r] >= 0 ? lo[r] : INT64_MAX;
+            bmax = hi[r];
+        } else {
+            bmin = nmin;
+            bmax = nmax;
+        }
+    }
+    cbase.push_back(bmax >= 0 ? (int32_t)bmin : 0);
+    brow.push_back(h.rows);
+    BandDesc bd{};
+    bd.rows = h.rows;
+    bd.cols = h.cols;
+    bd.nblk = (int32_t)cbase.size();
+    std::vector<int32_t> hb((size_t)3 * bd.nblk + 2);
+    for (int32_t b = 0; b <= bd.nblk; ++b) {
+        hb[b] = brow[b];
+        hb[bd.nblk + 1 + b] = rp[brow[b]];
+    }
+    for (int32_t b = 0; b < bd.nblk; ++b)
+        hb[2 * (bd.nblk + 1) + b] = cbase[b];
+    h.d_bb = (int32_t *)dev_alloc(hb.size() * 4);
+    HIPC(hipMemcpyAsync(h.d_bb, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, s));
+    bd.brow = h.d_bb;
+    bd.bent = h.d_bb + bd.nblk + 1;
+    bd.cbase = h.d_bb + 2 * (bd.nblk + 1);
+    h.d_brc = (uint32_t *)dev_alloc((size_t)(h.nnz + kPad) * 4);
+    launch_fill_bytes_zero((char *)(h.d_brc + h.nnz), kPad * 4, s);
+    launch_band_pack(bd, h.d_row_ptr, h.d_col, h.d_brc, s);
+    HIPC(hipStreamSynchronize(s));
+    bd.vals = h.d_vals;
+    bd.rc = h.d_brc;
+    h.band = bd;
+    h.use_band = true;
+    return true;
+}
+
 // Exclusive scan of a[0..n) in place; returns the total.
 static int64_t scan_total(int32_t *a, int64_t n, hipStream_t s)
 {
@@ -605,6 +691,13 @@ static void analyse(CsrHandle &h, hipStream_t s)
     const bool want_panels =
         (h.plan.layout == LAYOUT_PANELS && np_req <= 1024) ||
         (h.plan.layout == LAYOUT_AUTO && panels_eligible(h));
+    // the band layout: on request, or automatically for matrices whose
+    // columns are local (not gather-heavy) and whose rows are not all short
+    // enough for one lane each
+    const bool want_band =
+        h.plan.layout == LAYOUT_BAND ||
+        (h.plan.layout == LAYOUT_AUTO && !want_panels && h.nnz >= kOwnLayoutMinNnz &&
+         h.line_ratio < kGatherHeavy);
     if (h.plan.layout == LAYOUT_HOT && hot_possible(h)) {
         build_hot(h, s);
         h.grid = h.hot.grid;   // one fused-dot partial per workgroup
@@ -612,6 +705,9 @@ static void analyse(CsrHandle &h, hipStream_t s)
     } else if (want_panels && h.rows > 0 && h.nnz > 0) {
         build_panels(h, s);
         h.grid = h.pan.nblk;   // one fused-dot partial per row block
+        h.fin_blocks = 0;
+    } else if (want_band && build_band(h, s)) {
+        h.grid = h.band.nblk;  // one fused-dot partial per row block
         h.fin_blocks = 0;
     }
     h.d_dot_part = (double *)dev_alloc((size_t)(std::max(h.grid, 1) + h.fin_blocks + 1) * 8);
@@ -810,7 +906,7 @@ void destroy_handle(CsrHandle *h)
 // hot columns, the relabelled PageRank graph): rebuild those.
 static void values_changed(CsrHandle &h, hipStream_t s)
 {
-    if (own_layout(h)) {
+    if (h.use_panels || h.use_hot) {  // the band layout reads the CSR values
         h.dev_bytes -= analysis_bytes(h);
         analyse(h, s);
         h.dev_bytes += analysis_bytes(h);
@@ -874,6 +970,10 @@ void spmv_enqueue(const CsrHandle &h, const void *x, void *y,
     }
     if (h.use_hot) {
         launch_spmv_hot(h.dt, h.hot, x, y, epi, w, dot ? h.d_dot_part : nullptr, s);
+        return;
+    }
+    if (h.use_band) {
+        launch_spmv_band(h.dt, h.band, x, y, epi, w, dot ? h.d_dot_part : nullptr, s);
         return;
     }
     const MatDesc d = make_desc(h, x, y, w, h.d_chunk_part);
@@ -1363,6 +1463,11 @@ struct GroupPlan {
     PanelIO *d_pio = nullptr;
     int32_t *d_pprefix = nullptr;
     int32_t npm = 0, pblocks = 0;
+    // band matrices of the group: one grouped launch
+    BandDesc *d_bdesc = nullptr;
+    PanelIO *d_bio = nullptr;
+    int32_t *d_bprefix = nullptr;
+    int32_t nbm = 0, bblocks = 0;
 };
 static std::vector<GroupPlan *> g_groups;
 
@@ -1375,6 +1480,9 @@ static void free_group(GroupPlan *g)
     dev_free(g->d_pdesc);
     dev_free(g->d_pio);
     dev_free(g->d_pprefix);
+    dev_free(g->d_bdesc);
+    dev_free(g->d_bio);
+    dev_free(g->d_bprefix);
     delete g;
 }
 
@@ -1470,6 +1578,30 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
             pio.push_back(PanelIO{xs[j], ys[j]});
             pprefix.push_back(pprefix.back() + h->pan.nblk);
         }
+        std::vector<BandDesc> bdesc;
+        std::vector<PanelIO> bio;
+        std::vector<int32_t> bprefix(1, 0);
+        for (int j = 0; j < count; ++j) {
+            const CsrHandle *h = g->hs[j];
+            if (!h->use_band || h->rows == 0)
+                continue;
+            bdesc.push_back(h->band);
+            bio.push_back(PanelIO{xs[j], ys[j]});
+            bprefix.push_back(bprefix.back() + h->band.nblk);
+        }
+        g->nbm = (int32_t)bdesc.size();
+        g->bblocks = bprefix.back();
+        if (g->nbm) {
+            g->d_bdesc = (BandDesc *)dev_alloc(bdesc.size() * sizeof(BandDesc));
+            g->d_bio = (PanelIO *)dev_alloc(bio.size() * sizeof(PanelIO));
+            g->d_bprefix = (int32_t *)dev_alloc(bprefix.size() * 4);
+            HIPC(hipMemcpyAsync(g->d_bdesc, bdesc.data(), bdesc.size() * sizeof(BandDesc),
+                                hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(g->d_bio, bio.data(), bio.size() * sizeof(PanelIO),
+                                hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(g->d_bprefix, bprefix.data(), bprefix.size() * 4,
+                                hipMemcpyHostToDevice, s));
+        }
         g->npm = (int32_t)pdesc.size();
         g->pblocks = pprefix.back();
         if (g->npm) {
@@ -1540,10 +1672,13 @@ static void run_batched(int count, const lilac_csr_t *hs, const void *const *xs,
     if (hit->nitems)
         launch_split_finalize(hit->dt, hit->d_items, hit->nitems, none,
                               hit->d_mats, epi_none(), nullptr, s);
-    // column-panel matrices: one grouped launch whose blocks run exactly as
-    // in each matrix's single call; hot-column matrices: their own launch
+    // column-panel and band matrices: one grouped launch each, whose blocks
+    // run exactly as in each matrix's single call; hot-column matrices: their
+    // own launch
     launch_spmv_panels_grouped(hit->dt, hit->d_pdesc, hit->d_pio, hit->d_pprefix,
                                hit->npm, hit->pblocks, s);
+    launch_spmv_band_grouped(hit->dt, hit->d_bdesc, hit->d_bio, hit->d_bprefix,
+                             hit->nbm, hit->bblocks, s);
     for (int j = 0; j < count; ++j) {
         const CsrHandle *h = hit->hs[j];
         if (h->use_hot)
@@ -1750,7 +1885,7 @@ static double tune_handle(CsrHandle &h)
             p.grid_per_cu = gp;
             trial(p);
         }
-        for (int lay : {LAYOUT_ROWS, LAYOUT_PANELS, LAYOUT_HOT}) {
+        for (int lay : {LAYOUT_ROWS, LAYOUT_PANELS, LAYOUT_HOT, LAYOUT_BAND}) {
             Plan p = best;
             p.layout = lay;
             if (lay == LAYOUT_PANELS && !panels_eligible(h))
@@ -1947,7 +2082,10 @@ int lilac_csr_info(lilac_csr_t hh, lilac_csr_info_t *out)
         out->chunk = h->plan.chunk;
         out->nchunks = h->nchunks;
         out->ntiles = h->ntiles;
-        out->layout = h->use_panels ? LAYOUT_PANELS : h->use_hot ? LAYOUT_HOT : LAYOUT_ROWS;
+        out->layout = h->use_panels ? LAYOUT_PANELS
+                      : h->use_hot  ? LAYOUT_HOT
+                      : h->use_band ? LAYOUT_BAND
+                                    : LAYOUT_ROWS;
         out->npanels = h->use_panels ? h->pan.np : 0;
     });
 }

@@ -447,20 +447,27 @@ void run_tick(Server *S)
     std::vector<PanelDesc> pdesc;
     std::vector<PanelIO> pio;
     std::vector<int32_t> pprefix(1, 0);
+    std::vector<BandDesc> bdesc;
+    std::vector<PanelIO> bio;
+    std::vector<int32_t> bprefix(1, 0);
     std::vector<Req *> own_hot;
     for (Req *r : own) {
         SMatrix &m = S->mats[r->mid];
         Slot &sl = S->slots[r->slot];
-        if (!m.h->use_panels) {
+        const PanelIO io = (r->kind == LILAC_REQ_SPMV)
+                               ? PanelIO{r->in ? r->in : m.vin, r->out ? r->out : m.vout}
+                               : PanelIO{sl.p, sl.q};
+        if (m.h->use_panels) {
+            pdesc.push_back(m.h->pan);
+            pio.push_back(io);
+            pprefix.push_back(pprefix.back() + m.h->pan.nblk);
+        } else if (m.h->use_band) {
+            bdesc.push_back(m.h->band);
+            bio.push_back(io);
+            bprefix.push_back(bprefix.back() + m.h->band.nblk);
+        } else {
             own_hot.push_back(r);
-            continue;
         }
-        pdesc.push_back(m.h->pan);
-        if (r->kind == LILAC_REQ_SPMV)
-            pio.push_back(PanelIO{r->in ? r->in : m.vin, r->out ? r->out : m.vout});
-        else
-            pio.push_back(PanelIO{sl.p, sl.q});
-        pprefix.push_back(pprefix.back() + m.h->pan.nblk);
     }
     const size_t b_desc = descs.size() * sizeof(MatDesc);
     const size_t b_pre = ((prefix.size() * 4 + 15) / 16) * 16;
@@ -470,8 +477,11 @@ void run_tick(Server *S)
     const size_t b_pdesc = pdesc.size() * sizeof(PanelDesc);
     const size_t b_pio = pio.size() * sizeof(PanelIO);
     const size_t b_ppre = ((pprefix.size() * 4 + 15) / 16) * 16;
+    const size_t b_bdesc = bdesc.size() * sizeof(BandDesc);
+    const size_t b_bio = bio.size() * sizeof(PanelIO);
+    const size_t b_bpre = ((bprefix.size() * 4 + 15) / 16) * 16;
     tick_reserve(tk, b_desc + b_pre + b_items + b_init + b_step + b_pdesc + b_pio +
-                         b_ppre + 64);
+                         b_ppre + b_bdesc + b_bio + b_bpre + 64);
     size_t off = 0;
     auto put = [&](const void *src, size_t n, size_t padded) {
         std::memcpy(tk.host + off, src, n);
@@ -487,6 +497,9 @@ void run_tick(Server *S)
     const size_t o_pdesc = put(pdesc.data(), b_pdesc, b_pdesc);
     const size_t o_pio = put(pio.data(), b_pio, b_pio);
     const size_t o_ppre = put(pprefix.data(), pprefix.size() * 4, b_ppre);
+    const size_t o_bdesc = put(bdesc.data(), b_bdesc, b_bdesc);
+    const size_t o_bio = put(bio.data(), b_bio, b_bio);
+    const size_t o_bpre = put(bprefix.data(), bprefix.size() * 4, b_bpre);
     HIPC(hipMemcpyAsync(tk.dev, tk.host, off, hipMemcpyHostToDevice, S->stream));
     const MatDesc *d_desc = (const MatDesc *)(tk.dev + o_desc);
     if (!init.empty())
@@ -499,6 +512,10 @@ void run_tick(Server *S)
                                (const PanelIO *)(tk.dev + o_pio),
                                (const int32_t *)(tk.dev + o_ppre), (int32_t)pdesc.size(),
                                pprefix.back(), S->stream);
+    launch_spmv_band_grouped(LILAC_F64, (const BandDesc *)(tk.dev + o_bdesc),
+                             (const PanelIO *)(tk.dev + o_bio),
+                             (const int32_t *)(tk.dev + o_bpre), (int32_t)bdesc.size(),
+                             bprefix.back(), S->stream);
     for (Req *r : own_hot) {
         SMatrix &m = S->mats[r->mid];
         Slot &sl = S->slots[r->slot];

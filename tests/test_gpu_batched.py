@@ -102,3 +102,28 @@ def test_batched_with_panel_matrices_bitwise():
         assert torch.equal(y, y1)
     for h in hs:
         h.destroy()
+
+
+def test_batched_mixed_layouts_bitwise():
+    """A batch holding column-panel, band, hot-column and rows matrices: one
+    grouped launch per layout, each result equal to its single call."""
+    mats = [gen.spd_random(40000, 60, seed=6), gen.stencil(30, 27),
+            gen.stencil(25, 7), gen.random_rows(2000, 1, 4, seed=3),
+            gen.rmat_pagerank(16, 1 << 20, seed=5).astype(np.float64)]
+    hs = [L.Csr.from_gen(A) for A in mats]
+    hs[-1].set_layout(L.LAYOUT_HOT)
+    lays = [h.info().layout for h in hs]
+    assert lays == [L.LAYOUT_PANELS, L.LAYOUT_BAND, L.LAYOUT_BAND, L.LAYOUT_ROWS,
+                    L.LAYOUT_HOT], lays
+    xs = [_dev(gen.vector(A.cols, 200 + i)) for i, A in enumerate(mats)]
+    ys = [torch.empty(A.rows, dtype=torch.float64, device=DEV) for A in mats]
+    ys1 = [torch.empty_like(y) for y in ys]
+    for h, x, y in zip(hs, xs, ys1):
+        h.spmv(x, y)
+    L.lilac_spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for A, x, y, y1 in zip(mats, xs, ys, ys1):
+        assert torch.equal(y, y1), A.name
+        check_spmv(A, x.cpu().numpy(), y.cpu().numpy(), TOL_F64)
+    for h in hs:
+        h.destroy()

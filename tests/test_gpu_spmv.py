@@ -427,3 +427,113 @@ def test_value_updates_reach_panel_and_hot_copies():
         x_or, _, _ = oracle.cg(B.row_ptr, B.col_idx, B.vals, b, 20)
         assert np.max(np.abs(_host(xd) - x_or)) <= 1e-10 * np.max(np.abs(x_or))
         h.destroy()
+
+
+def _band_edges(n, offset):
+    """Rows i with columns i and i + offset (clipped): every row spans
+    `offset` columns, so blocks are cut by span, not only by rows."""
+    rows = np.repeat(np.arange(n), 2)
+    cols = np.stack([np.arange(n), np.minimum(np.arange(n) + offset, n - 1)], 1).ravel()
+    cols = np.where(np.arange(2 * n) % 2 == 1, np.maximum(cols, rows), cols)
+    keep = np.ones(2 * n, dtype=bool)
+    keep[1::2] = cols[1::2] != cols[0::2]
+    rows, cols = rows[keep], cols[keep]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    vals = gen.vector(len(cols), 90)
+    return gen.Csr(n, n, rp, cols.astype(np.int32), vals, f"band{offset}")
+
+
+BAND_MATS = {
+    "stencil7": lambda: gen.stencil(20, 7),
+    "stencil27": lambda: gen.stencil(14, 27),
+    "uniform16": lambda: gen.uniform_rows(4096, 16),
+    "ragged_long_rows": lambda: gen.ragged(3000, 40000, seed=1, max_len=300,
+                                           long_rows=3, long_len=20000),
+    "mostly_empty": lambda: gen.ragged(5000, 5000, seed=3, empty_frac=0.7),
+    "span_30000": lambda: _band_edges(120000, 30000),
+    "span_65000": lambda: _band_edges(120000, 65000),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BAND_MATS))
+def test_band_layout_parity(name):
+    """Band layout (CSR order, packed row and column offset): float64 and
+    float32 within tolerance, integer data exact, repeated calls equal."""
+    A = BAND_MATS[name]()
+    x = gen.vector(A.cols, 91)
+    h = L.Csr.from_gen(A, cols=A.cols)
+    h.set_layout(L.LAYOUT_BAND)
+    assert h.info().layout == L.LAYOUT_BAND, name
+    xd = _dev(x)
+    yd = torch.full((A.rows,), np.nan, dtype=torch.float64, device=DEV)
+    h.spmv(xd, yd)
+    y = _host(yd)
+    check_spmv(A, x, y, TOL_F64)
+    h.spmv(xd, yd)
+    assert np.array_equal(_host(yd), y)
+    h.destroy()
+    B = A.astype(np.float32)
+    x32 = gen.vector(B.cols, 92, dtype=np.float32)
+    h = L.Csr.from_gen(B, cols=B.cols)
+    h.set_layout(L.LAYOUT_BAND)
+    yd = torch.empty(B.rows, dtype=torch.float32, device=DEV)
+    h.spmv(_dev(x32), yd)
+    check_spmv(B, x32, _host(yd), TOL_F32)
+    h.destroy()
+    A.vals = gen.int_vector(A.nnz, 93)
+    xi = gen.int_vector(A.cols, 94)
+    h = L.Csr.from_gen(A, cols=A.cols)
+    h.set_layout(L.LAYOUT_BAND)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(xi), yd)
+    assert np.array_equal(_host(yd), oracle.spmv_csr(A.row_ptr, A.col_idx, A.vals, xi))
+    h.destroy()
+
+
+def test_layout_choice_and_band_fallback():
+    """The automatic choice: scattered columns -> column panels, local
+    columns -> band, tiny -> rows; a row spanning 65536 columns or more
+    makes the band impossible (rows layout instead)."""
+    cases = [(gen.spd_random(40000, 60, seed=6), L.LAYOUT_PANELS),
+             (gen.stencil(30, 27), L.LAYOUT_BAND),
+             (gen.stencil(30, 7), L.LAYOUT_BAND),
+             (gen.random_rows(2000, 1, 4, seed=3), L.LAYOUT_ROWS)]
+    for A, want in cases:
+        h = L.Csr.from_gen(A)
+        assert h.info().layout == want, (A.name, h.info().layout)
+        x = gen.vector(A.cols, 95)
+        yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+        h.spmv(_dev(x), yd)
+        check_spmv(A, x, _host(yd), TOL_F64)
+        h.destroy()
+    W = _band_edges(100000, 70000)
+    h = L.Csr.from_gen(W)
+    h.set_layout(L.LAYOUT_BAND)
+    assert h.info().layout == L.LAYOUT_ROWS
+    x = gen.vector(W.cols, 96)
+    yd = torch.empty(W.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(x), yd)
+    check_spmv(W, x, _host(yd), TOL_F64)
+    h.destroy()
+
+
+def test_band_fused_dot_and_cg():
+    A = gen.stencil(40, 7)
+    h = L.Csr.from_gen(A)
+    assert h.info().layout == L.LAYOUT_BAND
+    x = gen.vector(A.cols, 97)
+    w = gen.vector(A.rows, 98)
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    out = torch.empty(1, dtype=torch.float64, device=DEV)
+    h.spmv_dot(_dev(x), yd, _dev(w), out)
+    y = _host(yd)
+    check_spmv(A, x, y, TOL_F64)
+    assert abs(_host(out)[0] - oracle.dot(w, y)) <= TOL_F64 * oracle.dot_abs(w, y)
+    b = gen.vector(A.rows, 99)
+    xd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.cg(_dev(b), xd, 40, graph=True)
+    x_or, _, _ = oracle.cg(A.row_ptr, A.col_idx, A.vals, b, 40)
+    assert np.max(np.abs(_host(xd) - x_or)) <= 1e-10 * np.max(np.abs(x_or))
+    h.destroy()
