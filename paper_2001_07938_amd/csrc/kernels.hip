@@ -21,37 +21,6 @@ __device__ __forceinline__ T ld_stream(const T *p)
     return __builtin_nontemporal_load(p);
 }
 
-// A pointer read from a descriptor table is a generic address to the
-// compiler, which then emits flat memory instructions.  These point to
-// device memory: marking them global lets it emit global loads and stores.
-template <typename T>
-__device__ __forceinline__ T *as_global(T *p)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_assume(!__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void *)p));
-    __builtin_assume(!__builtin_amdgcn_is_private((const __attribute__((address_space(0))) void *)p));
-#endif
-    return p;
-}
-
-__device__ __forceinline__ MatDesc global_desc(MatDesc m)
-{
-    m.row_ptr = as_global(m.row_ptr);
-    m.col = as_global(m.col);
-    m.vals = as_global(m.vals);
-    m.bin_rows = as_global(m.bin_rows);
-    m.c_k0 = as_global(m.c_k0);
-    m.c_k1 = as_global(m.c_k1);
-    m.s_first = as_global(m.s_first);
-    m.c_row = as_global(m.c_row);
-    m.x = as_global(m.x);
-    m.y = as_global(m.y);
-    m.w = as_global(m.w);
-    m.chunk_part = as_global(m.chunk_part);
-    m.tiles = as_global(m.tiles);
-    return m;
-}
-
 // Cross-lane move of a double with a DPP pattern (two 32-bit halves).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
@@ -400,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
     double dacc = 0.0;
     for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
         const Tile t = tiles[ti];
-        const MatDesc m = GROUPED ? global_desc(mats[t.mat]) : single;
+        const MatDesc m = GROUPED ? mats[t.mat] : single;
         switch (t.cls & kTileClassMask) {
         case C_W1: rows_by_lanes<V, 1, DOT>(m, t, epi, dacc); break;
         case C_W2: rows_by_lanes<V, 2, DOT>(m, t, epi, dacc); break;
@@ -433,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_split_finalize(
     if (i < n) {
         const int32_t mi = GROUPED ? items[2 * i] : 0;
         const int32_t j = GROUPED ? items[2 * i + 1] : i;
-        const MatDesc m = GROUPED ? global_desc(mats[mi]) : single;
+        const MatDesc m = GROUPED ? mats[mi] : single;
         const int32_t row = m.bin_rows[m.split_begin + j];
         double s = 0.0;
         for (int32_t c = m.s_first[j]; c < m.s_first[j + 1]; ++c)
@@ -470,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
             else
                 hi = mid;
         }
-        const MatDesc m = global_desc(mats[lo]);
+        const MatDesc m = mats[lo];
         const Tile t = m.tiles[v - prefix[lo]];
         switch (t.cls & kTileClassMask) {
         case C_W1: rows_by_lanes<V, 1, false>(m, t, epi, dacc); break;
@@ -623,13 +592,10 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels_grouped(
         else
             hi = mid - 1;
     }
-    PanelDesc pd = descs[lo];
-    pd.vals = as_global(pd.vals);
-    pd.rc = as_global(pd.rc);
-    pd.wptr = as_global(pd.wptr);
+    const PanelDesc pd = descs[lo];
     const Epi epi{EPI_NONE, 0, 0.0, 0.0};
-    panel_block<V, false>(pd, g - prefix[lo], as_global((const V *)io[lo].x),
-                          as_global((V *)io[lo].y), epi, nullptr, nullptr, smem);
+    panel_block<V, false>(pd, g - prefix[lo], (const V *)io[lo].x, (V *)io[lo].y,
+                          epi, nullptr, nullptr, smem);
 }
 
 // Distinct x cache lines among the non-zeros of sampled row groups (see
@@ -1006,15 +972,10 @@ __global__ __launch_bounds__(kBandThreads) void k_spmv_band_grouped(
         else
             hi = mid - 1;
     }
-    BandDesc bd = descs[lo];
-    bd.vals = as_global(bd.vals);
-    bd.rc = as_global(bd.rc);
-    bd.brow = as_global(bd.brow);
-    bd.bent = as_global(bd.bent);
-    bd.cbase = as_global(bd.cbase);
+    const BandDesc bd = descs[lo];
     const Epi epi{EPI_NONE, 0, 0.0, 0.0};
-    band_block<V, false>(bd, g - prefix[lo], as_global((const V *)io[lo].x),
-                         as_global((V *)io[lo].y), epi, nullptr, nullptr, smem);
+    band_block<V, false>(bd, g - prefix[lo], (const V *)io[lo].x, (V *)io[lo].y, epi,
+                         nullptr, nullptr, smem);
 }
 
 // Smallest and largest column of every row (INT_MAX / -1 for empty rows).
@@ -1783,21 +1744,58 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(
     }
 }
 
+// Sums of two values over the workgroup at once, each in the order of
+// block_sum (so each equals block_sum of that value).
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *lds)
+{
+    a = lane_group_sum<64>(a);
+    b = lane_group_sum<64>(b);
+    __syncthreads();  // earlier readers of lds are done
+    if ((threadIdx.x & 63) == 0) {
+        lds[threadIdx.x >> 6] = a;
+        lds[kWaves + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
+    double ta = lds[0], tb = lds[kWaves];
+#pragma unroll
+    for (int i = 1; i < kWaves; ++i) {
+        ta += lds[i];
+        tb += lds[kWaves + i];
+    }
+    a = ta;
+    b = tb;
+}
+
 // Iteration k, after q = A p (with p.q partials in dot_part):
 //   rho = sum rr[k&1], pq = sum dot_part; stop (x kept) if either is 0;
 //   alpha = rho/pq; x += alpha p; r -= alpha q; partials of r.r into rr[~k&1].
-// Every workgroup forms rho, pq and alpha itself, in the same order.
+// Every workgroup forms rho, pq and alpha itself, in the same order.  The
+// thread's first elements are read before the sums, so their loads overlap.
 __global__ __launch_bounds__(kBlock) void k_cg_update(
     int64_t n, CgScalars *__restrict__ sc, const double *__restrict__ p,
     const double *__restrict__ q, double *__restrict__ x,
     double *__restrict__ r, const double *__restrict__ dot_part, int32_t ndot,
     double *__restrict__ rr, int32_t nparts, int32_t par)
 {
-    __shared__ double lds[kWaves];
-    if (sc->done)
+    __shared__ double lds[2 * kWaves];
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    double p0 = 0.0, q0 = 0.0, x0 = 0.0, r0 = 0.0;
+    if (i0 < n) {
+        p0 = p[i0];
+        q0 = q[i0];
+        x0 = x[i0];
+        r0 = r[i0];
+    }
+    const int32_t done = sc->done;
+    double rho = 0.0, pq = 0.0;
+    for (int32_t i = threadIdx.x; i < nparts; i += kBlock)
+        rho += rr[par * kDotParts + i];
+    for (int32_t i = threadIdx.x; i < ndot; i += kBlock)
+        pq += dot_part[i];
+    if (done)
         return;
-    const double rho = sum_parts_256(rr + par * kDotParts, nparts, lds);
-    const double pq = sum_parts_256(dot_part, ndot, lds);
+    block_sum2(rho, pq, lds);
     if (rho == 0.0 || pq == 0.0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->done = 1;
@@ -1808,8 +1806,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
     }
     const double alpha = rho / pq;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    if (i0 < n) {
+        x[i0] = fma(alpha, p0, x0);
+        const double ri = fma(-alpha, q0, r0);
+        r[i0] = ri;
+        acc = ri * ri;
+    }
+    for (int64_t i = i0 + step; i < n; i += step) {
         x[i] = fma(alpha, p[i], x[i]);
         const double ri = fma(-alpha, q[i], r[i]);
         r[i] = ri;
@@ -1831,14 +1834,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_xpay(
     double *__restrict__ p, const double *__restrict__ rr, int32_t nparts,
     int32_t par)
 {
-    __shared__ double lds[kWaves];
-    if (sc->done)
+    __shared__ double lds[2 * kWaves];
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    double r0 = 0.0, p0 = 0.0;
+    if (i0 < n) {
+        r0 = r[i0];
+        p0 = p[i0];
+    }
+    const int32_t done = sc->done;
+    double rho = 0.0, rho_new = 0.0;
+    for (int32_t i = threadIdx.x; i < nparts; i += kBlock) {
+        rho += rr[par * kDotParts + i];
+        rho_new += rr[(par ^ 1) * kDotParts + i];
+    }
+    if (done)
         return;
-    const double rho = sum_parts_256(rr + par * kDotParts, nparts, lds);
-    const double rho_new = sum_parts_256(rr + (par ^ 1) * kDotParts, nparts, lds);
+    block_sum2(rho, rho_new, lds);
     const double beta = rho_new / rho;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
+    if (i0 < n)
+        p[i0] = fma(beta, p0, r0);
+    for (int64_t i = i0 + step; i < n; i += step)
         p[i] = fma(beta, p[i], r[i]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rho = rho_new;
