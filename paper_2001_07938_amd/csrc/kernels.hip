@@ -21,14 +21,23 @@ __device__ __forceinline__ T ld_stream(const T *p)
     return __builtin_nontemporal_load(p);
 }
 
-// Cross-lane move of a double with a DPP pattern (two 32-bit halves).
+// Cross-lane move of a double with a DPP pattern (two 32-bit halves); a
+// lane with no source lane gets 0 (bound_ctrl), so no old value has to be
+// set up first.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
     const int lo = __double2loint(v);
     const int hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
-                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, true),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, true));
+}
+
+// The same for a 32-bit integer.
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32z(int32_t v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 
 // DPP move with a row mask; lanes of masked rows (or with no source) get
@@ -50,11 +59,21 @@ __device__ __forceinline__ double dpp_f64m(double v, double old)
 // One step of a segmented inclusive scan over a wavefront whose keys
 // ascend along the lanes: add the partial of the source lane when it has
 // the same key (monotone keys: the whole span between has that key).
+// Shifts inside rows (all rows enabled) read 0 and key 0 where there is no
+// source lane: a false key match then adds 0.  Broadcasts into some rows
+// keep the lane's own key -1 / value 0 in the other rows.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ void seg_step(double &val, int32_t key)
 {
-    const double t = dpp_f64m<CTRL, ROWS>(val, 0.0);
-    const int32_t tk = dpp_i32<CTRL, ROWS>(key, -1);
+    double t;
+    int32_t tk;
+    if (ROWS == 0xF) {
+        t = dpp_f64<CTRL>(val);
+        tk = dpp_i32z<CTRL>(key);
+    } else {
+        t = dpp_f64m<CTRL, ROWS>(val, 0.0);
+        tk = dpp_i32<CTRL, ROWS>(key, -1);
+    }
     if (tk == key)
         val += t;
 }
@@ -538,8 +557,10 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                 incl[u] = seg_scan64(incl[u], k1[u]);
 #pragma unroll
             for (int u = 0; u < kPanelChunks; ++u) {
-                const double prev_incl = dpp_f64m<0x138, 0xF>(incl[u], 0.0);  // wave_shr:1
-                const int32_t prev_k1 = dpp_i32<0x138, 0xF>(k1[u], -2);
+                // the previous lane's scan value and key (wave_shr:1; lane 0 reads 0
+                // and key 0, which adds 0 if it matches)
+                const double prev_incl = dpp_f64<0x138>(incl[u]);
+                const int32_t prev_k1 = dpp_i32z<0x138>(k1[u]);
                 const int32_t next_k0 = next_lane_key(k0[u]);
                 // a run of k0 that ends on this lane's first entry
                 if (k0[u] != k1[u] && k0[u] >= 0 && k0[u] < kPanelMaxRb)
@@ -779,8 +800,9 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
         // inside a lane breaks the scan because keys ascend)
         double incl = (k0 == k1) ? p0 + p1 : p1;
         incl = seg_scan64(incl, k1);
-        const double prev_incl = dpp_f64m<0x138, 0xF>(incl, 0.0);  // wave_shr:1
-        const int32_t prev_k1 = dpp_i32<0x138, 0xF>(k1, -2);
+        // previous lane's scan value and key (wave_shr:1; lane 0 reads 0)
+        const double prev_incl = dpp_f64<0x138>(incl);
+        const int32_t prev_k1 = dpp_i32z<0x138>(k1);
         const int32_t next_k0 = next_lane_key(k0);
         if (k0 != k1 && k0 >= 0 && k0 < kKeyEnd) {
             double *t = (k0 == first) ? csum : acc + k0;
