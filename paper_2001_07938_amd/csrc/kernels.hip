@@ -18,7 +18,23 @@ namespace {
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p)
 {
-    return __builtin_nontemporal_load(p);
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T *)p);
+}
+
+// Loads and stores of device memory through a global (address space 1)
+// pointer.  Pointers read from a descriptor table (grouped launches) are
+// otherwise generic to the compiler, which then emits flat instructions;
+// those also count against the LDS wait counter and so stall LDS work.
+template <typename T>
+__device__ __forceinline__ T gld(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void gst(T *p, T v)
+{
+    *(__attribute__((address_space(1))) T *)p = v;
 }
 
 // Cross-lane move of a double with a DPP pattern (two 32-bit halves); a
@@ -248,7 +264,7 @@ __device__ __forceinline__ double row_partial(const int32_t *__restrict__ col,
         for (int j = 0; j < U; ++j)
 #pragma unroll
             for (int t = 0; t < VEC; ++t)
-                xv[j][t] = (double)x[d[j].c[t]];
+                xv[j][t] = (double)gld(x + d[j].c[t]);
 #pragma unroll
         for (int j = 0; j < U; ++j)
 #pragma unroll
@@ -282,7 +298,7 @@ __device__ __forceinline__ V epilogue(double s, const Epi &e)
 __device__ __forceinline__ int32_t tile_row(const MatDesc &m, const Tile &t,
                                             int32_t p)
 {
-    return (t.cls & kTileContig) ? t.first + p : m.bin_rows[t.first + p];
+    return (t.cls & kTileContig) ? t.first + p : gld(m.bin_rows + t.first + p);
 }
 
 // Rows of a tile, W lanes per row (W <= 64).  Group g of the workgroup takes
@@ -310,8 +326,8 @@ __device__ __forceinline__ void rows_by_lanes(const MatDesc &m, const Tile &t,
     int32_t pr = 0, pk0 = 0, pk1 = 0;
     if (jp < count) {
         pr = tile_row(m, t, jp);
-        pk0 = m.row_ptr[pr];
-        pk1 = m.row_ptr[pr + 1];
+        pk0 = gld(m.row_ptr + pr);
+        pk1 = gld(m.row_ptr + pr + 1);
     }
     const int32_t g0 = wave * GPW;
     const int32_t iters = (count > g0) ? (count - g0 + G - 1) / G : 0;
@@ -326,9 +342,9 @@ __device__ __forceinline__ void rows_by_lanes(const MatDesc &m, const Tile &t,
                                                                 k0, k1, lane));
             if (lane == 0) {
                 const V out = epilogue<V>(s, epi);
-                y[row] = out;
+                gst(y + row, out);
                 if (DOT)
-                    dacc = fma((double)((const V *)m.w)[row], (double)out, dacc);
+                    dacc = fma((double)gld((const V *)m.w + row), (double)out, dacc);
             }
         }
     }
@@ -345,17 +361,17 @@ __device__ __forceinline__ void rows_by_block(const MatDesc &m, const Tile &t,
     V *y = (V *)m.y;
     for (int j = 0; j < t.count; ++j) {
         const int32_t row = tile_row(m, t, j);
-        const int32_t k0 = m.row_ptr[row];
-        const int32_t k1 = m.row_ptr[row + 1];
+        const int32_t k0 = gld(m.row_ptr + row);
+        const int32_t k1 = gld(m.row_ptr + row + 1);
         const double s = block_sum<kWaves>(
             row_partial<V, kBlock, VecOf<V, kBlock>::value, kUnroll>(
                 m.col, vals, x, k0, k1, threadIdx.x),
             lds);
         if (threadIdx.x == 0) {
             const V out = epilogue<V>(s, epi);
-            y[row] = out;
+            gst(y + row, out);
             if (DOT)
-                dacc = fma((double)((const V *)m.w)[row], (double)out, dacc);
+                dacc = fma((double)gld((const V *)m.w + row), (double)out, dacc);
         }
     }
 }
@@ -366,14 +382,14 @@ __device__ __forceinline__ void split_chunk(const MatDesc &m, const Tile &t,
                                             double *lds)
 {
     const int32_t c = t.first;
-    const int32_t k0 = m.c_k0[c];
-    const int32_t k1 = m.c_k1[c];
+    const int32_t k0 = gld(m.c_k0 + c);
+    const int32_t k1 = gld(m.c_k1 + c);
     const double s = block_sum<kWaves>(
         row_partial<V, kBlock, VecOf<V, kBlock>::value, kUnroll>(
             m.col, (const V *)m.vals, (const V *)m.x, k0, k1, threadIdx.x),
         lds);
     if (threadIdx.x == 0)
-        m.chunk_part[c] = s;
+        gst(m.chunk_part + c, s);
 }
 
 // Persistent tile loop: workgroup b takes tiles b, b+grid, b+2*grid, ...
@@ -459,7 +475,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
                 hi = mid;
         }
         const MatDesc m = mats[lo];
-        const Tile t = m.tiles[v - prefix[lo]];
+        const i32x4 tv = gld((const i32x4 *)(m.tiles + (v - prefix[lo])));
+        const Tile t{tv.x, tv.y, tv.z, tv.w};
         switch (t.cls & kTileClassMask) {
         case C_W1: rows_by_lanes<V, 1, false>(m, t, epi, dacc); break;
         case C_W2: rows_by_lanes<V, 2, false>(m, t, epi, dacc); break;
@@ -511,13 +528,13 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
         __syncthreads();  // the previous panel is no longer read
         const int32_t nvec = aligned ? width / VV : 0;
         for (int32_t i = threadIdx.x; i < nvec; i += kPanelThreads)
-            *(vec_t *)(xs + i * VV) = *(const vec_t *)(x + c0 + i * VV);
+            *(vec_t *)(xs + i * VV) = gld((const vec_t *)(x + c0 + i * VV));
         for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
-            xs[e] = x[c0 + e];
+            xs[e] = gld(x + c0 + e);
         __syncthreads();  // the panel is in LDS
         const int32_t *wp = pd.wptr + ((int64_t)b * pd.np + p) * (kPanelWaves + 1);
-        const int32_t ks = wp[wave];
-        const int32_t ke = wp[wave + 1];
+        const int32_t ks = gld(wp + wave);
+        const int32_t ke = gld(wp + wave + 1);
         // chunks of 128 entries from an even start: lane j holds the two
         // consecutive entries base + 2j and base + 2j + 1 (one 16-byte value
         // load, one 8-byte index load)
@@ -575,9 +592,9 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
     double dacc = 0.0;
     for (int32_t i = threadIdx.x; i < nr; i += kPanelThreads) {
         const V out = epilogue<V>(acc[i], epi);
-        y[r0 + i] = out;
+        gst(y + r0 + i, out);
         if (DOT)
-            dacc = fma((double)w[r0 + i], (double)out, dacc);
+            dacc = fma((double)gld(w + r0 + i), (double)out, dacc);
     }
     if (DOT) {
         const double tot = block_sum<kPanelWaves>(dacc, (double *)xs);
@@ -734,8 +751,9 @@ constexpr int32_t kKeyEnd = 1 << 16;
 // hot columns, or x from a block's first column in the band layout);
 // otherwise the word is the column of x and the row comes from key[].  The
 // entries of the next chunk are requested before the gathers of the
-// current one are used.  NW wavefronts share the part.
-template <typename V, bool HOT, int NW = kPanelWaves>
+// current one are used.  NW wavefronts share the part; XG: xsrc is in
+// device memory (else in LDS).
+template <typename V, bool HOT, int NW = kPanelWaves, bool XG = !HOT>
 __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
                                          const uint32_t *__restrict__ prc,
                                          const uint16_t *__restrict__ pkey,
@@ -783,7 +801,8 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
         // packing): gather element 0 for them, which always exists
         const uint32_t c0 = ok0 ? (HOT ? (rc.x & 0xFFFFu) : rc.x) : 0u;
         const uint32_t c1 = ok1 ? (HOT ? (rc.y & 0xFFFFu) : rc.y) : 0u;
-        const V x0 = xsrc[c0], x1 = xsrc[c1];
+        const V x0 = XG ? gld(xsrc + c0) : xsrc[c0];
+        const V x1 = XG ? gld(xsrc + c1) : xsrc[c1];
         const pair_t cv = v;
         const int32_t nb = base + 128;
         if (nb < ke) {
@@ -843,16 +862,17 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
     const bool aligned = (((uintptr_t)x) & 15) == 0;
     const int32_t nvec = aligned ? width / VV : 0;
     for (int32_t i = threadIdx.x; i < nvec; i += kPanelThreads)
-        *(vec_t *)(xs + i * VV) = *(const vec_t *)(x + i * VV);
+        *(vec_t *)(xs + i * VV) = gld((const vec_t *)(x + i * VV));
     for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
-        xs[e] = x[e];
+        xs[e] = gld(x + e);
     for (int i = threadIdx.x; i < 2 * kHotRows; i += kPanelThreads)
         acc_h[i] = 0.0;  // both sum arrays
     double dacc = 0.0;
     for (int32_t b = blockIdx.x; b < hd.nblk; b += gridDim.x) {
-        const int32_t r0 = hd.brow[b];
-        const int32_t nr = hd.brow[b + 1] - r0;
-        const int32_t e0 = hd.bent[b], es = hd.bsplit[b], e1 = hd.bent[b + 1];
+        const int32_t r0 = gld(hd.brow + b);
+        const int32_t nr = gld(hd.brow + b + 1) - r0;
+        const int32_t e0 = gld(hd.bent + b), es = gld(hd.bsplit + b);
+        const int32_t e1 = gld(hd.bent + b + 1);
         __syncthreads();  // hot columns staged, sums of the last block cleared
         if (wave & 1) {
             hot_part<V, false>(pv, hd.rc, hd.key, es, e1, x, acc_c,
@@ -895,9 +915,9 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
             const V out = epilogue<V>(acc_h[i] + acc_c[i], epi);
             acc_h[i] = 0.0;  // the thread that reads a sum clears it
             acc_c[i] = 0.0;
-            y[r0 + i] = out;
+            gst(y + r0 + i, out);
             if (DOT)
-                dacc = fma((double)w[r0 + i], (double)out, dacc);
+                dacc = fma((double)gld(w + r0 + i), (double)out, dacc);
         }
     }
     if (DOT) {
@@ -926,13 +946,14 @@ __device__ __forceinline__ void band_block(const BandDesc &bd, int32_t b,
     int32_t *ckey = (int32_t *)(smem + kBandRows * 8 + kBandWaves * 8);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int32_t r0 = bd.brow[b];
-    const int32_t nr = bd.brow[b + 1] - r0;
+    const int32_t r0 = gld(bd.brow + b);
+    const int32_t nr = gld(bd.brow + b + 1) - r0;
     for (int32_t i = threadIdx.x; i < nr; i += kBandThreads)
         acc[i] = 0.0;
     __syncthreads();
-    hot_part<V, true, kBandWaves>((const V *)bd.vals, bd.rc, nullptr, bd.bent[b],
-                                  bd.bent[b + 1], x + bd.cbase[b], acc, ckey + wave,
+    hot_part<V, true, kBandWaves, true>((const V *)bd.vals, bd.rc, nullptr,
+                                  gld(bd.bent + b), gld(bd.bent + b + 1),
+                                  x + gld(bd.cbase + b), acc, ckey + wave,
                                   csum + wave, wave, lane);
     __syncthreads();
     if (wave == 0) {
@@ -957,9 +978,9 @@ __device__ __forceinline__ void band_block(const BandDesc &bd, int32_t b,
     double dacc = 0.0;
     for (int32_t i = threadIdx.x; i < nr; i += kBandThreads) {
         const V out = epilogue<V>(acc[i], epi);
-        y[r0 + i] = out;
+        gst(y + r0 + i, out);
         if (DOT)
-            dacc = fma((double)w[r0 + i], (double)out, dacc);
+            dacc = fma((double)gld(w + r0 + i), (double)out, dacc);
     }
     if (DOT) {
         const double tot = block_sum<kBandWaves>(dacc, csum);
