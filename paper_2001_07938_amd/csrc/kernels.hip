@@ -533,8 +533,9 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
             xs[e] = gld(x + c0 + e);
         __syncthreads();  // the panel is in LDS
         const int32_t *wp = pd.wptr + ((int64_t)b * pd.np + p) * (kPanelWaves + 1);
-        const int32_t ks = gld(wp + wave);
-        const int32_t ke = gld(wp + wave + 1);
+        // uniform over the wavefront: scalar registers, scalar branches
+        const int32_t ks = __builtin_amdgcn_readfirstlane(gld(wp + wave));
+        const int32_t ke = __builtin_amdgcn_readfirstlane(gld(wp + wave + 1));
         // chunks of 128 entries from an even start: lane j holds the two
         // consecutive entries base + 2j and base + 2j + 1 (one 16-byte value
         // load, one 8-byte index load)
@@ -552,7 +553,9 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                 rc[u] = ld_stream((const upair_t *)(pd.rc + ea));
             }
             // all chunks in lockstep (independent scans interleave); the sums
-            // reach the rows chunk by chunk, in order
+            // reach the rows chunk by chunk, in order.  Chunks wholly inside
+            // [ks, ke) (most of them) skip the bound checks.
+            const bool full = base >= ks && base + 128 * kPanelChunks <= ke;
             int32_t k0[kPanelChunks], k1[kPanelChunks];
             double p0[kPanelChunks], incl[kPanelChunks];
 #pragma unroll
@@ -560,11 +563,21 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                 const int32_t e = base + u * 128 + 2 * lane;
                 // keys ascend along the wavefront: entries before ks belong to
                 // the previous wavefront (-1), entries past ke to nobody (max)
-                k0[u] = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
-                k1[u] = (e + 1 < ks) ? -1 : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16) : kPanelMaxRb;
-                const bool ok0 = e >= ks && e < ke, ok1 = e + 1 >= ks && e + 1 < ke;
-                p0[u] = ok0 ? (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu] : 0.0;
-                const double p1 = ok1 ? (double)v[u].y * (double)xs[rc[u].y & 0xFFFFu] : 0.0;
+                double p1;
+                if (full) {
+                    k0[u] = (int32_t)(rc[u].x >> 16);
+                    k1[u] = (int32_t)(rc[u].y >> 16);
+                    p0[u] = (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu];
+                    p1 = (double)v[u].y * (double)xs[rc[u].y & 0xFFFFu];
+                } else {
+                    k0[u] = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
+                    k1[u] = (e + 1 < ks) ? -1
+                            : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16)
+                                           : kPanelMaxRb;
+                    const bool ok0 = e >= ks && e < ke, ok1 = e + 1 >= ks && e + 1 < ke;
+                    p0[u] = ok0 ? (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu] : 0.0;
+                    p1 = ok1 ? (double)v[u].y * (double)xs[rc[u].y & 0xFFFFu] : 0.0;
+                }
                 // this lane's part of the run of its last key (a run that
                 // starts inside a lane breaks the scan because keys ascend)
                 incl[u] = (k0[u] == k1[u]) ? p0[u] + p1 : p1;
@@ -765,8 +778,8 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
     typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
     typedef uint16_t kpair_t __attribute__((ext_vector_type(2)));
     const int64_t n = (int64_t)e - s;
-    const int32_t ks = s + (int32_t)(n * wave / NW);
-    const int32_t ke = s + (int32_t)(n * (wave + 1) / NW);
+    const int32_t ks = __builtin_amdgcn_readfirstlane(s + (int32_t)(n * wave / NW));
+    const int32_t ke = __builtin_amdgcn_readfirstlane(s + (int32_t)(n * (wave + 1) / NW));
     const int32_t kb = ks & ~1;
     pair_t v;
     upair_t rc;
@@ -790,13 +803,16 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
     }
     for (int32_t base = kb; base < ke; base += 128) {
         const int32_t en = base + 2 * lane;
-        const bool ok0 = en >= ks && en < ke, ok1 = en + 1 >= ks && en + 1 < ke;
+        // chunks wholly inside [ks, ke) (most of them) need no bound checks
+        const bool full = base >= ks && base + 128 <= ke;
+        const bool ok0 = full || (en >= ks && en < ke);
+        const bool ok1 = full || (en + 1 >= ks && en + 1 < ke);
         const int32_t r0 = HOT ? (int32_t)(rc.x >> 16) : (int32_t)kk.x;
         const int32_t r1 = HOT ? (int32_t)(rc.y >> 16) : (int32_t)kk.y;
         // keys ascend along the wavefront: entries before ks belong to the
         // previous wavefront (-1), entries past ke to nobody (kKeyEnd)
-        const int32_t k0 = (en < ks) ? -1 : ok0 ? r0 : kKeyEnd;
-        const int32_t k1 = (en + 1 < ks) ? -1 : ok1 ? r1 : kKeyEnd;
+        const int32_t k0 = full ? r0 : (en < ks) ? -1 : ok0 ? r0 : kKeyEnd;
+        const int32_t k1 = full ? r1 : (en + 1 < ks) ? -1 : ok1 ? r1 : kKeyEnd;
         // entries outside the share may belong to the other part (another
         // packing): gather element 0 for them, which always exists
         const uint32_t c0 = ok0 ? (HOT ? (rc.x & 0xFFFFu) : rc.x) : 0u;
