@@ -10,6 +10,7 @@ C file, built with ``gcc -O2 -ffp-contract=off`` (see ``build``).
 Parity status of each function (what pins it, see ``tests/test_oracle_*.py``):
   spmv_csr / spmv_csr_f32 / spmv_abs : pinned (paper's 5x5 example, dense
       matvec, exact rational arithmetic, identity/permutation, scipy CSR)
+  spmv_csr_par                       : pinned (bitwise equal to spmv_csr)
   dot / dot_abs                      : pinned (closed forms, fsum, Fraction)
   cg                                 : pinned (direct solve, k-eigenvalue
       finite termination, zero right-hand side, A-norm monotonicity)
@@ -33,7 +34,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
-          "-shared"]
+          "-shared", "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -71,9 +72,11 @@ def _declare(L):
     L.oracle_csr_cols.argtypes = [I64, P]
     L.oracle_csr_cols.restype = I32
     for nm in ("oracle_spmv_csr_f64", "oracle_spmv_csr_f32",
-               "oracle_spmv_abs_f64", "oracle_spmv_abs_f32"):
+               "oracle_spmv_abs_f64", "oracle_spmv_abs_f32", "oracle_spmv_csr_f64_par"):
         getattr(L, nm).argtypes = [I32, P, P, P, P, P]
         getattr(L, nm).restype = None
+    L.oracle_threads.argtypes = []
+    L.oracle_threads.restype = ctypes.c_int
     L.oracle_dot.argtypes = [I64, P, P]
     L.oracle_dot.restype = F64
     L.oracle_dot_abs.argtypes = [I64, P, P]
@@ -122,6 +125,23 @@ def cols(col_idx) -> int:
 
 
 # ---------------------------------------------------------------- SpMV / dot
+
+def spmv_csr_par(row_ptr, col_idx, vals, x) -> np.ndarray:
+    """spmv_csr for float64 data with the rows shared among host threads
+    (identical result); for timing the host baseline on all its cores."""
+    rp = _c(row_ptr, np.int32)
+    ci = _c(col_idx, np.int32)
+    rows = rp.size - 1
+    y = np.empty(rows, dtype=np.float64)
+    lib().oracle_spmv_csr_f64_par(rows, _p(rp), _p(ci), _p(_c(vals, np.float64)),
+                                  _p(_c(x, np.float64)), _p(y))
+    return y
+
+
+def threads() -> int:
+    """Host threads the parallel oracle product uses (OMP_NUM_THREADS)."""
+    return int(lib().oracle_threads())
+
 
 def spmv_csr(row_ptr, col_idx, vals, x) -> np.ndarray:
     """y = A x in binary64 (float32 inputs are widened first)."""

@@ -14,6 +14,7 @@
  * Paper: Ginsbach, Collie, O'Boyle, "Automatically Harnessing Sparse
  * Acceleration", CC 2020.  Section names below refer to that paper.
  */
+#include <omp.h>
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -88,6 +89,28 @@ void oracle_spmv_csr_f64(int32_t rows, const int32_t *row_ptr,
             s += vals[k] * x[col_idx[k]];
         y[i] = s;
     }
+}
+
+/* The same product with the rows shared among host threads (OpenMP): each
+ * row is formed exactly as above, so the result equals the serial one bit
+ * for bit.  Only used to time the host baseline on all of its cores. */
+void oracle_spmv_csr_f64_par(int32_t rows, const int32_t *row_ptr,
+                             const int32_t *col_idx, const double *vals,
+                             const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < rows; ++i) {
+        double s = 0.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            s += vals[k] * x[col_idx[k]];
+        y[i] = s;
+    }
+}
+
+/* Threads the parallel product uses. */
+int oracle_threads(void)
+{
+    return omp_get_max_threads();
 }
 
 /* Same product for float32 storage: every operand is widened to binary64

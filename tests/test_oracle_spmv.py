@@ -138,3 +138,14 @@ def test_nan_propagates():
                         for i in range(A.rows)])
     assert np.array_equal(np.isnan(y), touches)
 
+
+
+def test_row_parallel_product_is_the_serial_one():
+    """The host-baseline product that shares rows among threads forms every
+    row exactly as the serial loop does."""
+    A = gen.ragged(20000, 30000, seed=31, max_len=300, long_rows=2, long_len=9000)
+    x = gen.vector(A.cols, 32)
+    y = oracle.spmv_csr(A.row_ptr, A.col_idx, A.vals, x)
+    yp = oracle.spmv_csr_par(A.row_ptr, A.col_idx, A.vals, x)
+    assert np.array_equal(y, yp)
+    assert oracle.threads() >= 1
