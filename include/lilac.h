@@ -179,13 +179,12 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * at a time and gathers from there, with 16-bit column offsets.  Row
  * blocks hold at most 1024 rows, enough blocks for every CU but at least
  * the rows that weigh as much as one copy of x.  It suits matrices whose
- * non-zeros scatter over x; for others it is not built.  LILAC_LAYOUT_AUTO
- * (the default) picks it for gather-heavy matrices (sampled distinct
- * 128-byte x lines per non-zero at least 0.3, at least 16384 non-zeros)
- * with at most 64 panels, no
- * row longer than 1024, and copies of x at most four times the matrix
- * bytes.  Batched calls run all column-panel matrices of a batch in one
- * launch, with the same results.  LILAC_LAYOUT_HOT: a second copy for
+ * non-zeros scatter over x; it is built only for at most 64 panels (else
+ * the rows layout is used).  LILAC_LAYOUT_AUTO (the default) picks it for
+ * gather-heavy matrices (sampled distinct 128-byte x lines per non-zero at
+ * least 0.3, at least 16384 non-zeros) with no row longer than 1024 and
+ * copies of x at most four times the matrix bytes.  Batched calls run all
+ * column-panel matrices of a batch in one launch, with the same results.  LILAC_LAYOUT_HOT: a second copy for
  * matrices whose most referenced columns have the lowest indices (a graph
  * relabelled by decreasing out-degree, as lilac_pagerank does by itself for
  * graphs of at least 65536 vertices): the first 32512 (float32) or 16256

@@ -37,6 +37,21 @@ __device__ __forceinline__ void gst(T *p, T v)
     *(__attribute__((address_space(1))) T *)p = v;
 }
 
+// Set bits of a wavefront mask in the lanes below this one.
+__device__ __forceinline__ int32_t lanes_below(uint64_t m)
+{
+    return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Cross-lane move of a double with a DPP pattern (two 32-bit halves); a
 // lane with no source lane gets 0 (bound_ctrl), so no old value has to be
 // set up first.
@@ -692,46 +707,65 @@ __global__ __launch_bounds__(kBlock) void k_line_reuse(int32_t rows,
     }
 }
 
-// Entries of each row per panel (one thread per row; cnt pre-zeroed).
+// Entries of each row per panel: one wavefront per row, 64 entries at a
+// time, one ballot per panel (cnt pre-zeroed).
 __global__ __launch_bounds__(kBlock) void k_panel_count(PanelDesc pd,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
                                                         int32_t *__restrict__ cnt)
 {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (i >= pd.rows)
-        return;
-    const int32_t b = i / pd.rb, rl = i - b * pd.rb;
+        return;  // whole wavefronts
+    const int32_t b = (int32_t)(i / pd.rb), rl = (int32_t)(i - (int64_t)b * pd.rb);
     const int32_t a = rp[i], e = rp[i + 1];
-    for (int32_t p = 0; p < pd.np; ++p) {
-        int32_t n = 0;
-        for (int32_t k = a; k < e; ++k)
-            n += (col[k] / pd.pw == p) ? 1 : 0;
-        cnt[(int64_t)(b * pd.np + p) * (pd.rb + 1) + rl] = n;
+    int32_t mine = 0;  // lane p < np counts panel p
+    for (int32_t base = a; base < e; base += 64) {
+        const int32_t k = base + lane;
+        const int32_t pan = (k < e) ? col[k] / pd.pw : -1;
+        for (int32_t p = 0; p < pd.np; ++p) {
+            const int32_t n = __popcll(__ballot(pan == p));
+            if (lane == p)
+                mine += n;
+        }
     }
+    if (lane < pd.np)
+        cnt[(int64_t)(b * pd.np + lane) * (pd.rb + 1) + rl] = mine;
 }
 
-// Move each row's entries to their panels (stable inside a row).
+// Move each row's entries to their panels, keeping their order inside a
+// row: one wavefront per row, 64 entries at a time, positions from ballots.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_panel_scatter(
     PanelDesc pd, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ vals, const int32_t *__restrict__ ptr,
     V *__restrict__ pv, uint32_t *__restrict__ prc)
 {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (i >= pd.rows)
-        return;
-    const int32_t b = i / pd.rb, rl = i - b * pd.rb;
+        return;  // whole wavefronts
+    const int32_t b = (int32_t)(i / pd.rb), rl = (int32_t)(i - (int64_t)b * pd.rb);
     const int32_t a = rp[i], e = rp[i + 1];
-    for (int32_t p = 0; p < pd.np; ++p) {
-        int32_t pos = ptr[(int64_t)(b * pd.np + p) * (pd.rb + 1) + rl];
-        for (int32_t k = a; k < e; ++k) {
-            const int32_t cc = col[k];
-            if (cc / pd.pw == p) {
-                pv[pos] = vals[k];
-                prc[pos] = ((uint32_t)rl << 16) | (uint32_t)(cc - p * pd.pw);
-                ++pos;
-            }
+    // lane p < np holds the next free position of panel p
+    int32_t next = (lane < pd.np) ? ptr[(int64_t)(b * pd.np + lane) * (pd.rb + 1) + rl] : 0;
+    for (int32_t base = a; base < e; base += 64) {
+        const int32_t k = base + lane;
+        const int32_t c = (k < e) ? col[k] : 0;
+        const int32_t pan = (k < e) ? c / pd.pw : -1;
+        int32_t pos = 0;
+        for (int32_t p = 0; p < pd.np; ++p) {
+            const uint64_t m = __ballot(pan == p);
+            const int32_t start = __shfl(next, p, 64);
+            if (pan == p)
+                pos = start + lanes_below(m);
+            if (lane == p)
+                next += __popcll(m);
+        }
+        if (k < e) {
+            pv[pos] = vals[k];
+            prc[pos] = ((uint32_t)rl << 16) | (uint32_t)(c - pan * pd.pw);
         }
     }
 }
@@ -1079,19 +1113,22 @@ __global__ __launch_bounds__(kBlock) void k_band_pack(BandDesc bd,
         rc[k] = (rl << 16) | (uint32_t)(col[k] - base);
 }
 
-// Hot entries of each row (one thread per row).
+// Hot entries of each row: one wavefront per row, 64 entries at a time.
 __global__ __launch_bounds__(kBlock) void k_hot_count(HotDesc hd,
                                                       const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ col,
                                                       int32_t *__restrict__ cnt)
 {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (i >= hd.rows)
-        return;
+        return;  // whole wavefronts
     int32_t n = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+    for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += 64)
         n += (col[k] < hd.hot) ? 1 : 0;
-    cnt[i] = n;
+    n = wave_sum_i32(n);
+    if (lane == 0)
+        cnt[i] = n;
 }
 
 __global__ __launch_bounds__(kBlock) void k_hot_split(HotDesc hd,
@@ -1104,17 +1141,20 @@ __global__ __launch_bounds__(kBlock) void k_hot_split(HotDesc hd,
     bsplit[b] = hd.bent[b] + (hx[hd.brow[b + 1]] - hx[hd.brow[b]]);
 }
 
-// Move each row's entries to the hot or cold part of its block (stable
-// inside a row).  hx: exclusive scan of the per-row hot counts.
+// Move each row's entries to the hot or cold part of its block (order kept
+// inside a row): one wavefront per row, positions from ballots.  hx:
+// exclusive scan of the per-row hot counts.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_hot_scatter(
     HotDesc hd, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ vals, const int32_t *__restrict__ hx,
     V *__restrict__ hv, uint32_t *__restrict__ hrc, uint16_t *__restrict__ hkey)
 {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= hd.rows)
-        return;
+    const int64_t iw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (iw >= hd.rows)
+        return;  // whole wavefronts
+    const int32_t i = (int32_t)iw;
     // block of row i: the last b with brow[b] <= i
     int32_t lo = 0, hi = hd.nblk - 1;
     while (lo < hi) {
@@ -1129,18 +1169,25 @@ __global__ __launch_bounds__(kBlock) void k_hot_scatter(
     const int32_t before = hx[i] - hx[hd.brow[b]];   // hot entries of earlier rows
     int32_t hp = hd.bent[b] + before;
     int32_t cp = hd.bsplit[b] + (rp[i] - hd.bent[b]) - before;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int32_t c = col[k];
-        if (c < hd.hot) {
-            hv[hp] = vals[k];
-            hrc[hp] = (rl << 16) | (uint32_t)c;
-            ++hp;
-        } else {
-            hv[cp] = vals[k];
-            hrc[cp] = (uint32_t)c;
-            hkey[cp] = (uint16_t)rl;
-            ++cp;
+    const int32_t e = rp[i + 1];
+    for (int32_t base = rp[i]; base < e; base += 64) {
+        const int32_t k = base + lane;
+        const bool in = k < e;
+        const int32_t c = in ? col[k] : 0;
+        const bool hot = in && c < hd.hot;
+        const uint64_t mh = __ballot(hot), mc = __ballot(in && !hot);
+        if (hot) {
+            const int32_t pos = hp + lanes_below(mh);
+            hv[pos] = vals[k];
+            hrc[pos] = (rl << 16) | (uint32_t)c;
+        } else if (in) {
+            const int32_t pos = cp + lanes_below(mc);
+            hv[pos] = vals[k];
+            hrc[pos] = (uint32_t)c;
+            hkey[pos] = (uint16_t)rl;
         }
+        hp += __popcll(mh);
+        cp += __popcll(mc);
     }
 }
 
@@ -2248,7 +2295,7 @@ void launch_spmv_hot(lilac_dtype dt, const HotDesc &hd, const void *x, void *y,
 void launch_hot_count(const HotDesc &hd, const int32_t *rp, const int32_t *col,
                       int32_t *cnt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_hot_count, dim3(grid_for(hd.rows, kBlock, INT_MAX)),
+    hipLaunchKernelGGL(k_hot_count, dim3(grid_for((int64_t)hd.rows * 64, kBlock, INT_MAX)),
                        dim3(kBlock), 0, s, hd, rp, col, cnt);
     check_launch("k_hot_count");
 }
@@ -2265,7 +2312,7 @@ void launch_hot_scatter(lilac_dtype dt, const HotDesc &hd, const int32_t *rp,
                         const int32_t *col, const void *vals, const int32_t *hx,
                         void *hv, uint32_t *hrc, uint16_t *hkey, hipStream_t s)
 {
-    dim3 g(grid_for(hd.rows, kBlock, INT_MAX)), b(kBlock);
+    dim3 g(grid_for((int64_t)hd.rows * 64, kBlock, INT_MAX)), b(kBlock);
     if (dt == LILAC_F64)
         hipLaunchKernelGGL(k_hot_scatter<double>, g, b, 0, s, hd, rp, col,
                            (const double *)vals, hx, (double *)hv, hrc, hkey);
@@ -2302,7 +2349,7 @@ void panels_prepare()
 void launch_panel_count(const PanelDesc &pd, const int32_t *rp,
                         const int32_t *col, int32_t *cnt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_panel_count, dim3(grid_for(pd.rows, kBlock, INT_MAX)),
+    hipLaunchKernelGGL(k_panel_count, dim3(grid_for((int64_t)pd.rows * 64, kBlock, INT_MAX)),
                        dim3(kBlock), 0, s, pd, rp, col, cnt);
     check_launch("k_panel_count");
 }
@@ -2311,7 +2358,7 @@ void launch_panel_scatter(lilac_dtype dt, const PanelDesc &pd, const int32_t *rp
                           const int32_t *col, const void *vals, const int32_t *ptr,
                           void *pv, uint32_t *prc, hipStream_t s)
 {
-    dim3 g(grid_for(pd.rows, kBlock, INT_MAX)), b(kBlock);
+    dim3 g(grid_for((int64_t)pd.rows * 64, kBlock, INT_MAX)), b(kBlock);
     if (dt == LILAC_F64)
         hipLaunchKernelGGL(k_panel_scatter<double>, g, b, 0, s, pd, rp, col,
                            (const double *)vals, ptr, (double *)pv, prc);

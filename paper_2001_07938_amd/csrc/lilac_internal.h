@@ -117,6 +117,7 @@ constexpr int kPanelWaves = kPanelThreads / 64;
 constexpr int kPanelMaxRb = 1024;              // rows per block (sums in LDS)
 constexpr int kPanelLds = 160 * 1024;          // LDS of one workgroup
 constexpr int kPanelChunks = 2;                // 128-entry chunks in flight
+constexpr int kPanelMaxPanels = 64;            // one lane per panel in the build
 // widest panel (elements) for a value size
 constexpr int panel_width(int vsize)
 {

@@ -349,7 +349,7 @@ static bool panels_eligible(const CsrHandle &h)
     if (h.rows == 0 || h.nnz < kOwnLayoutMinNnz)
         return false;
     const int64_t np = panel_count(h);
-    if (np < 1 || np > 64)
+    if (np < 1 || np > kPanelMaxPanels)
         return false;
     if (h.bin_off[NCLASS] - h.bin_off[C_W64 + 1] > 0)
         return false;  // rows longer than the wavefront class bound
@@ -398,6 +398,8 @@ static void build_panels(CsrHandle &h, hipStream_t s)
     pd.cols = h.cols;
     pd.pw = panel_cols(h.dt);
     pd.np = (int32_t)panel_count(h);
+    if (pd.np < 1 || pd.np > kPanelMaxPanels)
+        fail(LILAC_ERR_DEVICE, "column-panel layout needs 1 to 64 panels");
     panels_prepare();
     pd.rb = panel_rows(h);
     pd.nblk = (int32_t)((h.rows + pd.rb - 1) / pd.rb);
@@ -689,7 +691,7 @@ static void analyse(CsrHandle &h, hipStream_t s)
         h.line_ratio = measure_line_ratio(h, s);
     const int64_t np_req = panel_count(h);
     const bool want_panels =
-        (h.plan.layout == LAYOUT_PANELS && np_req <= 1024) ||
+        (h.plan.layout == LAYOUT_PANELS && np_req <= kPanelMaxPanels) ||
         (h.plan.layout == LAYOUT_AUTO && panels_eligible(h));
     // the band layout: on request, or automatically for matrices whose
     // columns are local (not gather-heavy) and whose rows are not all short
