@@ -536,6 +536,11 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
     const V *pv = (const V *)pd.vals;
     for (int i = threadIdx.x; i < kPanelMaxRb; i += kPanelThreads)
         acc[i] = 0.0;
+    // the dot operand of this thread's row (rows <= threads), read now so
+    // the epilogue does not wait for it
+    double wrow = 0.0;
+    if (DOT && (int32_t)threadIdx.x < nr)
+        wrow = (double)gld(w + r0 + threadIdx.x);
     const bool aligned = (((uintptr_t)x) & 15) == 0;
     for (int32_t p = 0; p < pd.np; ++p) {
         const int32_t c0 = p * pd.pw;
@@ -618,11 +623,12 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
     }
     __syncthreads();
     double dacc = 0.0;
-    for (int32_t i = threadIdx.x; i < nr; i += kPanelThreads) {
-        const V out = epilogue<V>(acc[i], epi);
-        gst(y + r0 + i, out);
+    static_assert(kPanelMaxRb <= kPanelThreads, "one row per thread in the epilogue");
+    if ((int32_t)threadIdx.x < nr) {
+        const V out = epilogue<V>(acc[threadIdx.x], epi);
+        gst(y + r0 + threadIdx.x, out);
         if (DOT)
-            dacc = fma((double)gld(w + r0 + i), (double)out, dacc);
+            dacc = wrow * (double)out;
     }
     if (DOT) {
         const double tot = block_sum<kPanelWaves>(dacc, (double *)xs);
