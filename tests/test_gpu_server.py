@@ -19,7 +19,10 @@ def _dev(a):
 
 
 def _workload():
-    spd = [gen.spd_random(6000, 30, seed=1), gen.stencil(16, 7), gen.stencil(10, 27)]
+    # layouts: column panels (spd 40000), band (spd 6000, stencils, random
+    # rows), row-class tiles (ragged with long rows)
+    spd = [gen.spd_random(6000, 30, seed=1), gen.stencil(16, 7), gen.stencil(10, 27),
+           gen.spd_random(40000, 60, seed=4)]
     other = [gen.random_rows(9000, 5, 60, seed=2),
              gen.ragged(2500, 30000, seed=3, long_rows=2, long_len=20000)]
     return spd, other
@@ -51,6 +54,15 @@ def _run(S, reqs, iters, together):
         S.wait(t)
     torch.cuda.synchronize()
     return [o.cpu().numpy() for o in outs]
+
+
+def test_server_layouts_cover_all_grouped_paths():
+    spd, other = _workload()
+    hs = [L.Csr.from_gen(A) for A in spd + other]
+    lays = {h.info().layout for h in hs}
+    for h in hs:
+        h.destroy()
+    assert {L.LAYOUT_PANELS, L.LAYOUT_BAND, L.LAYOUT_ROWS} <= lays, lays
 
 
 def test_alone_equals_mix_and_oracle():
@@ -126,7 +138,7 @@ def test_trace_replay_small():
     ids = [S.add_matrix(A) for A in spd + other]
     tr = gen.poisson_trace(2000.0, 400, pool_size=len(ids), seed=9)
     mats = np.array(ids)[tr.matrix % len(ids)]
-    kind = np.where(np.isin(mats, ids[:3]), tr.kind, 0)  # CG only on SPD ones
+    kind = np.where(np.isin(mats, ids[:len(spd)]), tr.kind, 0)  # CG only on SPD ones
     st = S.run_trace(tr.arrival_ns, kind, mats, 10)
     assert st["completed"] == 400 and st["failed"] == 0
     assert st["cg_done"] == int(kind.sum())
