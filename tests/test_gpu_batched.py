@@ -127,3 +127,24 @@ def test_batched_mixed_layouts_bitwise():
         check_spmv(A, x.cpu().numpy(), y.cpu().numpy(), TOL_F64)
     for h in hs:
         h.destroy()
+
+
+def test_full_size_batched512():
+    """The batched workload at full size (512 matrices, 430M non-zeros) in
+    the launch the benchmark times: every row against the oracle, every
+    matrix bitwise equal to its single call."""
+    mats = [s.build() for s in gen.batch_specs()]
+    hs = [L.Csr.from_gen(A) for A in mats]
+    xs_h = [gen.vector(A.cols, 1000 + i) for i, A in enumerate(mats)]
+    xs = [_dev(x) for x in xs_h]
+    ys = [torch.empty(A.rows, dtype=torch.float64, device=DEV) for A in mats]
+    L.lilac_spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    y1 = torch.empty(max(A.rows for A in mats), dtype=torch.float64, device=DEV)
+    for h, A, x, xh, y in zip(hs, mats, xs, xs_h, ys):
+        h.spmv(x, y1[:A.rows])
+        torch.cuda.synchronize()
+        assert torch.equal(y, y1[:A.rows]), A.name
+        check_spmv(A, xh, y.cpu().numpy(), TOL_F64)
+    for h in hs:
+        h.destroy()

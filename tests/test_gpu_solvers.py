@@ -158,3 +158,19 @@ def test_pagerank_after_value_update():
     ref = oracle.pagerank(A.row_ptr, A.col_idx, vals2, x0.astype(np.float64), d, 3)
     assert np.sum(np.abs(_host(xd) - ref)) <= 3 * TOL_F32 * np.sum(np.abs(ref))
     h.destroy()
+
+
+def test_full_size_pagerank_rmat22():
+    """PageRank on the full R-MAT 2^22 graph (relabelled hot-column copy),
+    20 steps against the float64 oracle run."""
+    A = gen.rmat_pagerank()
+    n = A.rows
+    d = float(np.float32(0.85))
+    x0 = np.full(n, 1.0 / n, dtype=np.float32)
+    h = L.Csr.from_gen(A)
+    xd = _dev(x0)
+    h.pagerank(d, 20, xd)
+    x20 = _host(xd)
+    ref = oracle.pagerank(A.row_ptr, A.col_idx, A.vals, x0.astype(np.float64), d, 20)
+    assert np.sum(np.abs(x20 - ref)) <= 20 * TOL_F32 * np.sum(np.abs(ref))
+    h.destroy()
