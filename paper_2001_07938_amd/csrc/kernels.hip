@@ -528,7 +528,6 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
     double *acc = (double *)smem;                                 // row sums
     V *xs = (V *)(smem + kPanelMaxRb * sizeof(double));           // x panel
     constexpr int VV = 16 / sizeof(V);
-    typedef V vec_t __attribute__((ext_vector_type(VV)));
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t r0 = b * pd.rb;
@@ -542,16 +541,25 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
     if (DOT && (int32_t)threadIdx.x < nr)
         wrow = (double)gld(w + r0 + threadIdx.x);
     const bool aligned = (((uintptr_t)x) & 15) == 0;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     for (int32_t p = 0; p < pd.np; ++p) {
         const int32_t c0 = p * pd.pw;
         const int32_t width = min(pd.pw, pd.cols - c0);
         __syncthreads();  // the previous panel is no longer read
+        // 16-byte pieces straight from memory into LDS (no registers): each
+        // wavefront instruction fills 1 KiB at a uniform LDS address
         const int32_t nvec = aligned ? width / VV : 0;
-        for (int32_t i = threadIdx.x; i < nvec; i += kPanelThreads)
-            *(vec_t *)(xs + i * VV) = gld((const vec_t *)(x + c0 + i * VV));
+        for (int32_t c = wv; c * 64 < nvec; c += kPanelWaves) {
+            const int32_t i = c * 64 + lane;
+            if (i < nvec)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(x + c0 + i * VV),
+                    (__attribute__((address_space(3))) void *)(xs + c * 64 * VV), 16, 0, 0);
+        }
         for (int32_t e = nvec * VV + threadIdx.x; e < width; e += kPanelThreads)
             xs[e] = gld(x + c0 + e);
-        __syncthreads();  // the panel is in LDS
+        __builtin_amdgcn_s_waitcnt(0);  // the direct loads have landed
+        __syncthreads();                 // the panel is in LDS
         const int32_t *wp = pd.wptr + ((int64_t)b * pd.np + p) * (kPanelWaves + 1);
         // uniform over the wavefront: scalar registers, scalar branches
         const int32_t ks = __builtin_amdgcn_readfirstlane(gld(wp + wave));
