@@ -530,9 +530,9 @@ static bool build_band(CsrHandle &h, hipStream_t s)
     }
     dev_free(d);
     // about eight blocks per CU (they run eight at a time on one), between
-    // 1024 entries (short chains for small matrices) and 16384
+    // 2048 entries (short chains for small matrices) and 32768
     const int64_t target = std::min<int64_t>(
-        16384, std::max<int64_t>(1024, h.nnz / ((int64_t)ctx().cu * 8)));
+        32768, std::max<int64_t>(2048, h.nnz / ((int64_t)ctx().cu * 8)));
     std::vector<int32_t> brow{0}, cbase;
     int32_t start = 0;
     int64_t bmin = INT64_MAX, bmax = -1;
