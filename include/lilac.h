@@ -350,9 +350,10 @@ typedef struct {
 } lilac_server_stats;
 
 int lilac_server_create(lilac_server_t *s, const lilac_server_config *cfg);
-/* Registers a float64 CSR matrix by its host arrays, which the caller keeps
- * valid and unchanged until lilac_server_destroy; it is uploaded when a
- * request first needs it.  cols < 0 means cols = rows.  Must be called
+/* Registers a float64 CSR matrix given by host arrays: the server copies
+ * them into pinned host memory (so the caller may free or change its arrays
+ * after the call) and uploads the matrix when a request first needs it, and
+ * again after an eviction.  cols < 0 means cols = rows.  Must be called
  * before the first request is submitted. */
 int lilac_server_add_matrix(lilac_server_t s, int rows, int cols, int64_t nnz,
                             const int *row_ptr, const int *col_idx,

@@ -438,9 +438,11 @@ bool is_device_ptr(const void *p);
 std::recursive_mutex &lib_mutex();
 void set_last_error(const std::string &msg);
 int lib_device();
+// inputs_ready: device inputs are complete (the caller synchronised the
+// stream that wrote them), so no device-wide wait is needed.
 CsrHandle *create_handle(int rows, int cols, int64_t nnz, const int32_t *rp,
                          const int32_t *col, const void *vals, lilac_dtype dt,
-                         unsigned flags);
+                         unsigned flags, bool inputs_ready = false);
 void destroy_handle(CsrHandle *h);
 MatDesc make_desc(const CsrHandle &h, const void *x, void *y, const void *w,
                   double *chunk_part);

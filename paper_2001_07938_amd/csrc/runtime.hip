@@ -775,7 +775,7 @@ void destroy_handle(CsrHandle *h);
 CsrHandle *create_handle(int rows, int cols, int64_t nnz,
                                 const int32_t *rp, const int32_t *col,
                                 const void *vals, lilac_dtype dt,
-                                unsigned flags)
+                                unsigned flags, bool inputs_ready)
 {
     if (rows < 0)
         fail(LILAC_ERR_ARG, "rows must be >= 0");
@@ -791,7 +791,7 @@ CsrHandle *create_handle(int rows, int cols, int64_t nnz,
         fail(LILAC_ERR_ARG, "unknown dtype");
     Context &c = ctx();
     // device inputs may still be in flight on the caller's streams
-    if (is_device_ptr(rp) || is_device_ptr(col) || is_device_ptr(vals))
+    if (!inputs_ready && (is_device_ptr(rp) || is_device_ptr(col) || is_device_ptr(vals)))
         HIPC(hipDeviceSynchronize());
     auto *h = new CsrHandle();
     h->rows = rows;

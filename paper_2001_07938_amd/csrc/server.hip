@@ -49,6 +49,7 @@ struct SMatrix {
     int refs = 0;              // admitted requests using it
     double *vin = nullptr, *vout = nullptr;  // trace-mode vectors
     int64_t spmv_bytes = 0;    // credited bytes of one product
+    void *pin = nullptr;       // pinned host copy holding rp, col, vals
 };
 
 // Per-slot device workspace of an admitted request.
@@ -161,10 +162,35 @@ void upload_loop(Server *S)
         }
         SMatrix &m = S->mats[id];
         CsrHandle *h = nullptr;
+        // the arrays go up from pinned host memory into staging buffers
+        // without the library lock (the scheduler may need it meanwhile, to
+        // evict); the lock is taken only to build the handle from them
+        int32_t *d_rp = nullptr, *d_col = nullptr;
+        double *d_vals = nullptr;
+        const size_t b_rp = (size_t)(m.rows + 1) * 4, b_col = (size_t)m.nnz * 4,
+                     b_vals = (size_t)m.nnz * 8;
         try {
+            {
+                std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+                d_rp = (int32_t *)dev_alloc(b_rp);
+                d_col = (int32_t *)dev_alloc(std::max<size_t>(b_col, 4));
+                d_vals = (double *)dev_alloc(std::max<size_t>(b_vals, 8));
+            }
+            HIPC(hipMemcpyAsync(d_rp, m.rp, b_rp, hipMemcpyHostToDevice, S->up_stream));
+            if (m.nnz) {
+                HIPC(hipMemcpyAsync(d_col, m.col, b_col, hipMemcpyHostToDevice, S->up_stream));
+                HIPC(hipMemcpyAsync(d_vals, m.vals, b_vals, hipMemcpyHostToDevice,
+                                    S->up_stream));
+            }
+            HIPC(hipStreamSynchronize(S->up_stream));
             std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-            h = create_handle(m.rows, m.cols, m.nnz, m.rp, m.col, m.vals,
-                              LILAC_F64, 0);
+            h = create_handle(m.rows, m.cols, m.nnz, d_rp, d_col, d_vals, LILAC_F64, 0,
+                              true);
+            dev_free(d_rp);
+            dev_free(d_col);
+            dev_free(d_vals);
+            d_rp = d_col = nullptr;
+            d_vals = nullptr;
             m.vin = (double *)dev_alloc((size_t)std::max(1, m.cols) * 8);
             m.vout = (double *)dev_alloc((size_t)std::max(1, m.rows) * 8);
             // trace-mode operands: x (or b) = 1
@@ -173,6 +199,12 @@ void upload_loop(Server *S)
                                 hipMemcpyHostToDevice, S->up_stream));
             HIPC(hipStreamSynchronize(S->up_stream));
         } catch (const Error &e) {
+            {
+                std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+                dev_free(d_rp);
+                dev_free(d_col);
+                dev_free(d_vals);
+            }
             std::lock_guard<std::mutex> lk(S->up_mu);
             S->up_failed.push_back(id);
             S->err = e.msg;
@@ -771,9 +803,21 @@ int lilac_server_add_matrix(lilac_server_t hs, int rows, int cols, int64_t nnz,
         m.rows = rows;
         m.cols = cols >= 0 ? cols : rows;
         m.nnz = nnz;
-        m.rp = row_ptr;
-        m.col = col_idx;
-        m.vals = vals;
+        // a pinned copy: uploads then run at DMA speed, and the caller's
+        // arrays are free once this returns
+        const size_t b_rp = (size_t)(rows + 1) * 4, b_col = (size_t)nnz * 4;
+        const size_t b_col_pad = (b_col + 7) & ~(size_t)7;
+        HIPC(hipHostMalloc(&m.pin, b_rp + b_col_pad + (size_t)nnz * 8 + 8,
+                           hipHostMallocDefault));
+        char *base = (char *)m.pin;
+        std::memcpy(base, row_ptr, b_rp);
+        if (nnz) {
+            std::memcpy(base + b_rp, col_idx, b_col);
+            std::memcpy(base + b_rp + b_col_pad, vals, (size_t)nnz * 8);
+        }
+        m.rp = (const int32_t *)base;
+        m.col = (const int32_t *)(base + b_rp);
+        m.vals = (const double *)(base + b_rp + b_col_pad);
         S->mats.push_back(m);
         S->max_rows = std::max(S->max_rows, std::max(m.rows, m.cols));
         *id = (int)S->mats.size() - 1;
@@ -950,6 +994,8 @@ int lilac_server_destroy(lilac_server_t hs)
                 destroy_handle(m.h);
             dev_free(m.vin);
             dev_free(m.vout);
+            if (m.pin)
+                (void)hipHostFree(m.pin);
         }
         for (auto &sl : S->slots)
             free_slot_mem(sl);
