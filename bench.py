@@ -53,13 +53,18 @@ def cg_iter_bytes(A) -> int:
 
 
 def kernel_source_digest() -> str:
-    """SHA-256 over the device sources (kernels and their shared header): a
-    stored counter reading is reported only while this still matches."""
+    """SHA-256 over the device sources (kernels and their shared header)
+    with comments and blank space removed: a stored counter reading is
+    reported only while the code it was taken from is unchanged."""
     import hashlib
+    import re
     hsh = hashlib.sha256()
     for rel in ("kernels.hip", "lilac_internal.h"):
-        with open(os.path.join(ROOT, "paper_2001_07938_amd", "csrc", rel), "rb") as f:
-            hsh.update(f.read())
+        with open(os.path.join(ROOT, "paper_2001_07938_amd", "csrc", rel)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        hsh.update(" ".join(text.split()).encode())
     return hsh.hexdigest()
 
 

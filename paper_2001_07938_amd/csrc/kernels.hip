@@ -1,11 +1,15 @@
-// Device code of liblilac.so for gfx950 (CDNA4, wave64): CSR analysis,
-// the tiled CSR product, the split-row finaliser, dot products and the
-// conjugate-gradient vector kernels.
+// Device code of liblilac.so for gfx950 (CDNA4, wave64): CSR analysis and
+// the layout builds, the CSR product in its four storage layouts (row-class
+// tiles with the split-row finaliser, column panels, hot columns, band) and
+// their grouped launches, dot products, the conjugate-gradient vector
+// kernels (single and batched), PageRank relabelling, JDS and BFS.
 //
-// Every reduction here has a fixed shape (lane groups reduce with a xor
-// butterfly, workgroups combine their four wavefronts in index order, split
-// rows add their chunk sums in chunk order), so a given matrix and plan
-// always give bitwise identical results, whatever else runs on the GPU.
+// Every reduction here has a fixed shape (lane groups reduce with DPP moves
+// in a fixed pattern, segmented scans run over lanes in order, workgroups
+// combine their wavefronts in index order, split rows add their chunk sums
+// in chunk order, carries between wavefronts are added in slot order), so a
+// given matrix, layout and plan always give bitwise identical results,
+// whatever else runs on the GPU.
 #include <algorithm>
 
 #include "lilac_internal.h"
