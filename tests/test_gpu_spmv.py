@@ -402,14 +402,14 @@ def test_hot_layout_fused_dot_unaligned_x_and_fallback():
 
 
 def test_value_updates_reach_panel_and_hot_copies():
-    """The column-panel and hot-column copies hold the values too: new values
-    (update or invalidate) must reach them, and the CG graph built on the old
-    copy must not be replayed."""
+    """The column-panel and hot-column copies hold the values too (the band
+    layout reads the CSR values): new values must reach every layout, and
+    the CG graph built on the old copy must not be replayed."""
     A = gen.spd_random(40000, 60, seed=6)
     x = gen.vector(A.cols, 80)
     b = gen.vector(A.rows, 81)
     bd = _dev(b)  # same right-hand side and solution arrays: same graph key
-    for lay in (L.LAYOUT_PANELS, L.LAYOUT_HOT):
+    for lay in (L.LAYOUT_PANELS, L.LAYOUT_HOT, L.LAYOUT_BAND, L.LAYOUT_ROWS):
         h = L.Csr.from_gen(A)
         h.set_layout(lay)
         assert h.info().layout == lay
