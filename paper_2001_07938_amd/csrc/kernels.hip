@@ -546,9 +546,45 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
         wrow = (double)gld(w + r0 + threadIdx.x);
     const bool aligned = (((uintptr_t)x) & 15) == 0;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
+    typedef V pair_t __attribute__((ext_vector_type(2)));
+    typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
+    // entry range of this wavefront in panel q; uniform over the wavefront
+    // (scalar registers, scalar branches)
+    // (scalar loads: the table is read-only while the kernel runs)
+    auto range = [&](int32_t q, int32_t &rs, int32_t &re) {
+        typedef const __attribute__((address_space(4))) int32_t *cptr;
+        const cptr wp = (cptr)(pd.wptr + ((int64_t)b * pd.np + q) * (kPanelWaves + 1));
+        rs = wp[wv];
+        re = wp[wv + 1];
+    };
+    // chunks of 128 entries from an even start: lane j holds the two
+    // consecutive entries at + 2j and at + 2j + 1 (one 16-byte value load,
+    // one 8-byte index load).  The entries of the next step are requested
+    // before this step's arithmetic (the first step of the next panel before
+    // that panel is copied), so loads stay in flight while the wavefront
+    // computes or waits.
+    pair_t nv[kPanelChunks];
+    upair_t nrc[kPanelChunks];
+    auto request = [&](int32_t at, int32_t rb, int32_t re) {
+#pragma unroll
+        for (int u = 0; u < kPanelChunks; ++u) {
+            const int32_t e = at + u * 128 + 2 * lane;
+            const int32_t ea = (e < re) ? e : rb;
+            nv[u] = ld_stream((const pair_t *)(pv + ea));
+            nrc[u] = ld_stream((const upair_t *)(pd.rc + ea));
+        }
+    };
+    int32_t ks = 0, ke = 0;
+    if (pd.np > 0)
+        range(0, ks, ke);
+    if ((ks & ~1) < ke)
+        request(ks & ~1, ks & ~1, ke);
     for (int32_t p = 0; p < pd.np; ++p) {
         const int32_t c0 = p * pd.pw;
         const int32_t width = min(pd.pw, pd.cols - c0);
+        int32_t nks = 0, nke = 0;  // the next panel's range
+        if (p + 1 < pd.np)
+            range(p + 1, nks, nke);
         __syncthreads();  // the previous panel is no longer read
         // 16-byte pieces straight from memory into LDS (no registers): each
         // wavefront instruction fills 1 KiB at a uniform LDS address
@@ -564,26 +600,22 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
             xs[e] = gld(x + c0 + e);
         __builtin_amdgcn_s_waitcnt(0);  // the direct loads have landed
         __syncthreads();                 // the panel is in LDS
-        const int32_t *wp = pd.wptr + ((int64_t)b * pd.np + p) * (kPanelWaves + 1);
-        // uniform over the wavefront: scalar registers, scalar branches
-        const int32_t ks = __builtin_amdgcn_readfirstlane(gld(wp + wave));
-        const int32_t ke = __builtin_amdgcn_readfirstlane(gld(wp + wave + 1));
-        // chunks of 128 entries from an even start: lane j holds the two
-        // consecutive entries base + 2j and base + 2j + 1 (one 16-byte value
-        // load, one 8-byte index load)
         const int32_t kb = ks & ~1;
+        const int32_t nkb = nks & ~1;
+        if (kb >= ke && nkb < nke)
+            request(nkb, nkb, nke);  // nothing here: the next panel's first step
         for (int32_t base = kb; base < ke; base += 128 * kPanelChunks) {
-            typedef V pair_t __attribute__((ext_vector_type(2)));
-            typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
             pair_t v[kPanelChunks];
             upair_t rc[kPanelChunks];
 #pragma unroll
             for (int u = 0; u < kPanelChunks; ++u) {
-                const int32_t e = base + u * 128 + 2 * lane;
-                const int32_t ea = (e < ke) ? e : kb;
-                v[u] = ld_stream((const pair_t *)(pv + ea));
-                rc[u] = ld_stream((const upair_t *)(pd.rc + ea));
+                v[u] = nv[u];
+                rc[u] = nrc[u];
             }
+            if (base + 128 * kPanelChunks < ke)
+                request(base + 128 * kPanelChunks, kb, ke);
+            else if (nkb < nke)
+                request(nkb, nkb, nke);
             // all chunks in lockstep (independent scans interleave); the sums
             // reach the rows chunk by chunk, in order.  Chunks wholly inside
             // [ks, ke) (most of them) skip the bound checks.
@@ -632,6 +664,8 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                     acc[k1[u]] += incl[u];
             }
         }
+        ks = nks;
+        ke = nke;
     }
     __syncthreads();
     double dacc = 0.0;
