@@ -851,33 +851,85 @@ constexpr int32_t kKeyEnd = 1 << 16;
 // otherwise the word is the column of x and the row comes from key[].  The
 // entries of the next chunk are requested before the gathers of the
 // current one are used.  NW wavefronts share the part; XG: xsrc is in
-// device memory (else in LDS).
-template <typename V, bool HOT, int NW = kPanelWaves, bool XG = !HOT>
+// device memory (else in LDS).  PRE: the first chunk was requested earlier
+// into *pre (hot_first, same part and wavefront).
+template <typename V>
+struct HotChunk {
+    typedef V pair_t __attribute__((ext_vector_type(2)));
+    typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
+    typedef uint16_t kpair_t __attribute__((ext_vector_type(2)));
+    pair_t v;
+    upair_t rc;
+    kpair_t kk;
+};
+
+// This wavefront's share [ks, ke) of a part [s, e) split evenly between NW.
+template <int NW>
+__device__ __forceinline__ void hot_share(int32_t s, int32_t e, int wave, int32_t &ks,
+                                          int32_t &ke)
+{
+    const int64_t n = (int64_t)e - s;
+    ks = __builtin_amdgcn_readfirstlane(s + (int32_t)(n * wave / NW));
+    ke = __builtin_amdgcn_readfirstlane(s + (int32_t)(n * (wave + 1) / NW));
+}
+
+// Requests the first chunk of this wavefront's share of a part (nothing if
+// the share is empty).
+template <typename V, bool HOT, int NW = kPanelWaves>
+__device__ __forceinline__ void hot_first(const V *__restrict__ pv,
+                                          const uint32_t *__restrict__ prc,
+                                          const uint16_t *__restrict__ pkey, int32_t s,
+                                          int32_t e, int wave, int lane, HotChunk<V> &c)
+{
+    typedef typename HotChunk<V>::pair_t pair_t;
+    typedef typename HotChunk<V>::upair_t upair_t;
+    typedef typename HotChunk<V>::kpair_t kpair_t;
+    int32_t ks, ke;
+    hot_share<NW>(s, e, wave, ks, ke);
+    const int32_t kb = ks & ~1;
+    if (kb < ke) {
+        const int32_t en = kb + 2 * lane;
+        const int32_t ea = (en < ke) ? en : kb;
+        c.v = ld_stream((const pair_t *)(pv + ea));
+        c.rc = ld_stream((const upair_t *)(prc + ea));
+        if (!HOT)
+            c.kk = ld_stream((const kpair_t *)(pkey + ea));
+    }
+}
+
+template <typename V, bool HOT, int NW = kPanelWaves, bool XG = !HOT, bool PRE = false>
 __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
                                          const uint32_t *__restrict__ prc,
                                          const uint16_t *__restrict__ pkey,
                                          int32_t s, int32_t e, const V *xsrc,
                                          double *acc, int32_t *ckey, double *csum,
-                                         int wave, int lane)
+                                         int wave, int lane,
+                                         const HotChunk<V> *pre = nullptr)
 {
-    typedef V pair_t __attribute__((ext_vector_type(2)));
-    typedef uint32_t upair_t __attribute__((ext_vector_type(2)));
-    typedef uint16_t kpair_t __attribute__((ext_vector_type(2)));
-    const int64_t n = (int64_t)e - s;
-    const int32_t ks = __builtin_amdgcn_readfirstlane(s + (int32_t)(n * wave / NW));
-    const int32_t ke = __builtin_amdgcn_readfirstlane(s + (int32_t)(n * (wave + 1) / NW));
+    typedef typename HotChunk<V>::pair_t pair_t;
+    typedef typename HotChunk<V>::upair_t upair_t;
+    typedef typename HotChunk<V>::kpair_t kpair_t;
+    int32_t ks, ke;
+    hot_share<NW>(s, e, wave, ks, ke);
     const int32_t kb = ks & ~1;
     pair_t v;
     upair_t rc;
     kpair_t kk;
     int32_t first = -1;
     if (kb < ke) {
-        const int32_t en = kb + 2 * lane;
-        const int32_t ea = (en < ke) ? en : kb;
-        v = ld_stream((const pair_t *)(pv + ea));
-        rc = ld_stream((const upair_t *)(prc + ea));
-        if (!HOT)
-            kk = ld_stream((const kpair_t *)(pkey + ea));
+        if (PRE) {
+            v = pre->v;
+            rc = pre->rc;
+            if (!HOT)
+                kk = pre->kk;
+        } else {
+            const int32_t en = kb + 2 * lane;
+            const int32_t ea = (en < ke) ? en : kb;
+            v = ld_stream((const pair_t *)(pv + ea));
+            rc = ld_stream((const upair_t *)(prc + ea));
+            if (!HOT)
+                kk = ld_stream((const kpair_t *)(pkey + ea));
+        }
         // the share's first entry is entry 0 or 1 of lane 0
         const int32_t f0 = HOT ? (int32_t)(rc.x >> 16) : (int32_t)kk.x;
         const int32_t f1 = HOT ? (int32_t)(rc.y >> 16) : (int32_t)kk.y;
@@ -970,25 +1022,42 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
     for (int i = threadIdx.x; i < 2 * kHotRows; i += kPanelThreads)
         acc_h[i] = 0.0;  // both sum arrays
     double dacc = 0.0;
+    // the first chunk of the wavefront's first part of block bb is requested
+    // before the barriers that end the previous block
+    typedef const __attribute__((address_space(4))) int32_t *cptr;
+    HotChunk<V> pre;
+    auto prefetch = [&](int32_t bb) {
+        const int32_t pe0 = ((cptr)hd.bent)[bb], pes = ((cptr)hd.bsplit)[bb];
+        const int32_t pe1 = ((cptr)hd.bent)[bb + 1];
+        if (wave & 1)
+            hot_first<V, false>(pv, hd.rc, hd.key, pes, pe1, wave, lane, pre);
+        else
+            hot_first<V, true>(pv, hd.rc, hd.key, pe0, pes, wave, lane, pre);
+    };
+    if ((int32_t)blockIdx.x < hd.nblk)
+        prefetch(blockIdx.x);
     for (int32_t b = blockIdx.x; b < hd.nblk; b += gridDim.x) {
-        const int32_t r0 = gld(hd.brow + b);
-        const int32_t nr = gld(hd.brow + b + 1) - r0;
-        const int32_t e0 = gld(hd.bent + b), es = gld(hd.bsplit + b);
-        const int32_t e1 = gld(hd.bent + b + 1);
+        const int32_t r0 = ((cptr)hd.brow)[b];
+        const int32_t nr = ((cptr)hd.brow)[b + 1] - r0;
+        const int32_t e0 = ((cptr)hd.bent)[b], es = ((cptr)hd.bsplit)[b];
+        const int32_t e1 = ((cptr)hd.bent)[b + 1];
         __syncthreads();  // hot columns staged, sums of the last block cleared
         if (wave & 1) {
-            hot_part<V, false>(pv, hd.rc, hd.key, es, e1, x, acc_c,
-                               ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
-                               wave, lane);
+            hot_part<V, false, kPanelWaves, true, true>(
+                pv, hd.rc, hd.key, es, e1, x, acc_c, ckey + kPanelWaves + wave,
+                csum + kPanelWaves + wave, wave, lane, &pre);
             hot_part<V, true>(pv, hd.rc, hd.key, e0, es, xs, acc_h, ckey + wave,
                               csum + wave, wave, lane);
         } else {
-            hot_part<V, true>(pv, hd.rc, hd.key, e0, es, xs, acc_h, ckey + wave,
-                              csum + wave, wave, lane);
+            hot_part<V, true, kPanelWaves, false, true>(pv, hd.rc, hd.key, e0, es, xs,
+                                                        acc_h, ckey + wave, csum + wave,
+                                                        wave, lane, &pre);
             hot_part<V, false>(pv, hd.rc, hd.key, es, e1, x, acc_c,
                                ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
                                wave, lane);
         }
+        if (b + (int32_t)gridDim.x < hd.nblk)
+            prefetch(b + gridDim.x);
         __syncthreads();  // all runs are in
         if (wave == 0) {
             // lanes 0-15: hot slots, 16-31: cold slots.  A slot leads its
