@@ -177,8 +177,9 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * copy of the matrix in which the columns are cut into panels that fit the
  * LDS and the rows into blocks; each workgroup stages one panel of x in LDS
  * at a time and gathers from there, with 16-bit column offsets.  Row
- * blocks hold at most 1024 rows, enough blocks for every CU but at least
- * the rows that weigh as much as one copy of x.  It suits matrices whose
+ * blocks hold at most 4096 rows, enough blocks for every CU but at least
+ * the rows that weigh as much as one copy of x; the block's row sums and
+ * one panel share the LDS.  It suits matrices whose
  * non-zeros scatter over x; it is built only for at most 64 panels (else
  * the rows layout is used).  LILAC_LAYOUT_AUTO (the default) picks it for
  * gather-heavy matrices (sampled distinct 128-byte x lines per non-zero at

@@ -530,14 +530,14 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                                             unsigned char *smem)
 {
     double *acc = (double *)smem;                                 // row sums
-    V *xs = (V *)(smem + kPanelMaxRb * sizeof(double));           // x panel
+    V *xs = (V *)(smem + panel_sum_bytes(pd.rb));                 // x panel
     constexpr int VV = 16 / sizeof(V);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int32_t r0 = b * pd.rb;
     const int32_t nr = min(pd.rb, pd.rows - r0);
     const V *pv = (const V *)pd.vals;
-    for (int i = threadIdx.x; i < kPanelMaxRb; i += kPanelThreads)
+    for (int i = threadIdx.x; i < pd.rb; i += kPanelThreads)
         acc[i] = 0.0;
     // the dot operand of this thread's row (rows <= threads), read now so
     // the epilogue does not wait for it
@@ -669,12 +669,12 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
     }
     __syncthreads();
     double dacc = 0.0;
-    static_assert(kPanelMaxRb <= kPanelThreads, "one row per thread in the epilogue");
-    if ((int32_t)threadIdx.x < nr) {
-        const V out = epilogue<V>(acc[threadIdx.x], epi);
-        gst(y + r0 + threadIdx.x, out);
+    for (int32_t i = threadIdx.x; i < nr; i += kPanelThreads) {
+        const V out = epilogue<V>(acc[i], epi);
+        gst(y + r0 + i, out);
         if (DOT)
-            dacc = wrow * (double)out;
+            dacc = fma(i == (int32_t)threadIdx.x ? wrow : (double)gld(w + r0 + i),
+                       (double)out, dacc);
     }
     if (DOT) {
         const double tot = block_sum<kPanelWaves>(dacc, (double *)xs);

@@ -114,14 +114,19 @@ struct PanelIO {
 };
 constexpr int kPanelThreads = 1024;            // 16 wave64: one workgroup per CU
 constexpr int kPanelWaves = kPanelThreads / 64;
-constexpr int kPanelMaxRb = 1024;              // rows per block (sums in LDS)
+constexpr int kPanelMaxRb = 4096;              // rows per block (sums in LDS)
 constexpr int kPanelLds = 160 * 1024;          // LDS of one workgroup
 constexpr int kPanelChunks = 2;                // 128-entry chunks in flight
 constexpr int kPanelMaxPanels = 64;            // one lane per panel in the build
-// widest panel (elements) for a value size
-constexpr int panel_width(int vsize)
+// LDS bytes of the row sums of a block of rb rows (the x panel follows)
+constexpr int panel_sum_bytes(int rb)
 {
-    return (kPanelLds - kPanelMaxRb * 8) / vsize;
+    return (rb * 8 + 15) & ~15;
+}
+// widest panel (elements) for a value size and rb rows per block
+constexpr int panel_width(int vsize, int rb)
+{
+    return (kPanelLds - panel_sum_bytes(rb)) / vsize;
 }
 
 // Hot-column layout, for matrices whose most referenced columns come first

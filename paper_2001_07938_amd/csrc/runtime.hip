@@ -310,11 +310,15 @@ static int64_t analysis_bytes(const CsrHandle &h)
     return b;
 }
 
-// Columns per panel: a panel of x and the row sums fill the LDS.
-static int32_t panel_cols(lilac_dtype dt) { return panel_width((int)dtype_size(dt)); }
+static int32_t panel_rows(const CsrHandle &h);
+// Columns per panel: a panel of x and the row sums of a block fill the LDS.
+static int32_t panel_cols(const CsrHandle &h)
+{
+    return panel_width((int)dtype_size(h.dt), panel_rows(h));
+}
 static int64_t panel_count(const CsrHandle &h)
 {
-    return h.cols > 0 ? ((int64_t)h.cols + panel_cols(h.dt) - 1) / panel_cols(h.dt) : 0;
+    return h.cols > 0 ? ((int64_t)h.cols + panel_cols(h) - 1) / panel_cols(h) : 0;
 }
 
 // Rows per block of the column-panel layout: enough blocks for every CU,
@@ -396,7 +400,7 @@ static void build_panels(CsrHandle &h, hipStream_t s)
     PanelDesc pd{};
     pd.rows = h.rows;
     pd.cols = h.cols;
-    pd.pw = panel_cols(h.dt);
+    pd.pw = panel_cols(h);
     pd.np = (int32_t)panel_count(h);
     if (pd.np < 1 || pd.np > kPanelMaxPanels)
         fail(LILAC_ERR_DEVICE, "column-panel layout needs 1 to 64 panels");

@@ -307,6 +307,47 @@ def test_panel_layout_f32_and_fused_dot():
     h.destroy()
 
 
+def test_panel_layout_tall_row_blocks():
+    """Short scattered rows over many columns: row blocks of 4096 rows (the
+    row sums take 32 KiB of LDS, panels of 16384 float64 columns, several
+    rows per thread in the epilogue and the fused dot), with a partial last
+    block."""
+    A = gen.random_rows(120000, 3, 9, seed=13)
+    h = L.Csr.from_gen(A)
+    inf = h.info()
+    assert inf.layout == L.LAYOUT_PANELS  # chosen automatically
+    assert inf.npanels == 8               # 16384-column panels
+    x = gen.vector(A.cols, 67)
+    w = gen.vector(A.rows, 68)
+    yd = torch.full((A.rows,), np.nan, dtype=torch.float64, device=DEV)
+    out = torch.empty(1, dtype=torch.float64, device=DEV)
+    h.spmv_dot(_dev(x), yd, _dev(w), out)
+    y = _host(yd)
+    check_spmv(A, x, y, TOL_F64)
+    assert abs(_host(out)[0] - oracle.dot(w, y)) <= TOL_F64 * oracle.dot_abs(w, y)
+    yd2 = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(x), yd2)
+    assert np.array_equal(_host(yd2), y)
+    h.destroy()
+    A.vals = gen.int_vector(A.nnz, 69)
+    xi = gen.int_vector(A.cols, 70)
+    h = L.Csr.from_gen(A)
+    assert h.info().layout == L.LAYOUT_PANELS
+    yd = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+    h.spmv(_dev(xi), yd)
+    assert np.array_equal(_host(yd), oracle.spmv_csr(A.row_ptr, A.col_idx, A.vals, xi))
+    h.destroy()
+    B = gen.random_rows(120000, 3, 9, seed=13, dtype=np.float32)
+    h = L.Csr.from_gen(B)
+    inf = h.info()
+    assert inf.layout == L.LAYOUT_PANELS and inf.npanels == 4  # 32768 float32 columns
+    x32 = gen.vector(B.cols, 71, dtype=np.float32)
+    yd = torch.empty(B.rows, dtype=torch.float32, device=DEV)
+    h.spmv(_dev(x32), yd)
+    check_spmv(B, x32, _host(yd), TOL_F32)
+    h.destroy()
+
+
 def test_panel_layout_unaligned_x():
     """x starting 8 bytes past a 16-byte boundary takes the scalar staging
     path of the panel kernel."""
