@@ -14,8 +14,9 @@ and the oracle's CPU time on the same input.
 Other workloads (--workload): spmv16 (single product, n = 4096, 16 per row),
 pagerank (R-MAT 2^22, 2^26 edge draws, float32, 20 steps), batched (512
 matrices in one grouped launch), serve (Poisson request stream over resident
-matrices), marshal (cached versus per-call upload of the paper-shaped call).  --workload all adds every other workload's figures under
-"extras" of the same line.
+matrices), marshal (cached versus per-call upload of the paper-shaped call),
+csr64 (2^31 + 8192 non-zeros through the 64-bit-offset handle).  --workload
+all adds every other workload's figures under "extras" of the same line.
 """
 from __future__ import annotations
 
@@ -349,6 +350,30 @@ def run_serve(args, torch, L, gen):
     return out
 
 
+def run_csr64(args, torch, L, gen):
+    """A matrix past the 32-bit offset range: 2^22 + 16 rows of 512 float32
+    entries (2^31 + 8192 non-zeros, 17.2 GB) through the 64-bit-offset
+    handle (two row parts, one batched launch); each row holds 512
+    consecutive columns at a random offset (the byte-bound case; the parity
+    test spreads them over all of x instead).  Algorithmic bytes as for any
+    product, with the device's 32-bit offsets of each part."""
+    rows, k, cols = (1 << 22) + 16, 512, 1 << 22
+    A = gen.strided_rows(rows, k, cols, seed=gen.BASE_SEED + 65, window=True)
+    m = L.Csr64.from_gen(A, cols=cols)
+    nparts = m.info()[3]
+    kb = A.nnz * 8 + (rows + nparts) * 4 + cols * 4 + rows * 4
+    nnz = A.nnz
+    del A
+    x = torch.rand(cols, dtype=torch.float32, device="cuda")
+    y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    m.spmv(x, y)
+    ms = time_events(lambda: m.spmv(x, y), 10, stream)
+    m.destroy()
+    return {"workload": "csr64_window512_2p31", "nnz": nnz, "parts": nparts,
+            "ms_per_product": round(ms, 3), "GBps": round(kb / (ms * 1e-3) / 1e9, 1)}
+
+
 def run_marshal(args, torch, L, gen):
     """The paper's marshaling comparison on MI355X: the paper-shaped call
     with host arrays, the matrix cached on the device after the first call
@@ -382,7 +407,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cg",
                     choices=["cg", "spmv16", "pagerank", "batched", "serve",
-                             "marshal", "all"])
+                             "marshal", "csr64", "all"])
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -401,7 +426,7 @@ def main():
     else:
         fn = {"spmv16": run_spmv16, "pagerank": run_pagerank,
               "batched": run_batched, "serve": run_serve,
-              "marshal": run_marshal}[args.workload]
+              "marshal": run_marshal, "csr64": run_csr64}[args.workload]
         extra = fn(args, torch, L, gen)
         res = run_cg(args, torch, L, gen, extras_only=True)
         res["extras"] = {args.workload: extra}
@@ -409,7 +434,7 @@ def main():
         res["extras"] = {}
         for name, fn in (("spmv16", run_spmv16), ("pagerank", run_pagerank),
                          ("batched", run_batched), ("marshal", run_marshal),
-                         ("serve", run_serve)):
+                         ("csr64", run_csr64), ("serve", run_serve)):
             log(f"[{name}] ...")
             res["extras"][name] = fn(args, torch, L, gen)
     out = {

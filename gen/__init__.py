@@ -242,6 +242,46 @@ def ragged(rows: int, cols: int, seed: int, max_len: int = 200,
                vals, f"ragged{rows}x{cols}")
 
 
+def strided_rows(rows: int, k: int, cols: int, seed: int,
+                 dtype=np.float32, chunk_rows: int = 1 << 17,
+                 window: bool = False) -> Csr:
+    """Exactly k distinct columns per row, {(a_i + j*s) mod cols : j < k}
+    with s = cols // k and a seeded random offset a_i, stored in ascending
+    order; with ``window`` instead the k consecutive columns a_i ... a_i +
+    k - 1 (a_i <= cols - k).  Integer values in [-8, 8] (exact in float32
+    and float64).  The row offsets are int64, so rows * k may reach past
+    2^31 (the matrices of the 64-bit-offset handles); built in chunks of
+    rows."""
+    if k < 1 or cols < k:
+        raise ValueError("need 1 <= k <= cols")
+    rng = _rng(seed)
+    s = 1 if window else cols // k
+    nnz = rows * k
+    row_ptr = np.arange(rows + 1, dtype=np.int64) * k
+    col_idx = np.empty(nnz, dtype=np.int32)
+    vals = np.empty(nnz, dtype=dtype)
+    a_all = rng.integers(0, cols - k + 1 if window else cols, rows, dtype=np.int64)
+    j = np.arange(k, dtype=np.int64)
+    for r0 in range(0, rows, chunk_rows):
+        r1 = min(rows, r0 + chunk_rows)
+        a = a_all[r0:r1, None]
+        if window:
+            c = a.astype(np.int32) + j.astype(np.int32)[None, :]
+        elif k * s == cols:
+            # the steps cover cols exactly: the row is a % s, a % s + s, ...
+            c = ((a % s).astype(np.int32) + (j * s).astype(np.int32)[None, :])
+        else:
+            # entries j >= j0 wrap past cols; listing them first keeps the
+            # row sorted
+            j0 = np.minimum(k, -((a - cols) // s))
+            m = (j[None, :] + j0) % k
+            c = a + m * s
+            c -= cols * (c >= cols)
+        col_idx[r0 * k:r1 * k] = c.reshape(-1)
+        vals[r0 * k:r1 * k] = rng.integers(-8, 9, (r1 - r0) * k, dtype=np.int8)
+    return Csr(rows, cols, row_ptr, col_idx, vals, f"strided{rows}x{k}")
+
+
 def identity(n: int) -> Csr:
     return Csr(n, n, np.arange(n + 1, dtype=np.int32),
                np.arange(n, dtype=np.int32), np.ones(n), f"eye{n}")

@@ -275,6 +275,39 @@ int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
  */
 int lilac_csr_tune(lilac_csr_t h, double *best_us);
 
+/* ---- 64-bit row offsets ------------------------------------------------ */
+
+/*
+ * Matrices with 2^31 - 8192 or more non-zeros (the CSR arrays of the CSR
+ * paragraph of section "Sparse Matrix Variations in LiLAC-What", with
+ * int64 row offsets; column indices stay int32).  The rows are cut into
+ * consecutive parts of at most 2^31 - 2^20 non-zeros each (the environment
+ * variable LILAC_PART_NNZ, read when a matrix is created, lowers that bound
+ * so that small matrices can be split for tests); each part is an ordinary
+ * handle over its rows with its row offsets rebased to 32 bits, and a
+ * product runs all parts as one batched call (lilac_spmv_batched) with the
+ * shared x and y offset by each part's first row.
+ *
+ * lilac_csr64_create: row_ptr int64[rows+1], col_idx int32[nnz] and vals
+ * (F64 or F32)[nnz], host or device, owned by the caller and read only
+ * during the call (the parts keep their own device copies).  cols < 0:
+ * max(col_idx)+1 per part.  Validation as lilac_csr_create, over all parts
+ * (row_ptr[0] == 0, non-decreasing, row_ptr[rows] == nnz; LILAC_ERR_CSR
+ * otherwise); LILAC_ERR_UNSUPPORTED if one row alone exceeds the part
+ * bound.  Blocking.
+ */
+typedef struct lilac_csr64_s *lilac_csr64_t;
+int lilac_csr64_create(lilac_csr64_t *h, int rows, int cols, int64_t nnz,
+                       const int64_t *row_ptr, const int *col_idx, const void *vals,
+                       lilac_dtype dt);
+/* y = A x for device x[cols] and y[rows] of the handle's dtype; y is
+ * overwritten.  Async on `stream` (NULL: the library's stream). */
+int lilac_csr64_spmv(lilac_csr64_t h, const void *x, void *y, void *stream);
+/* Sizes and the number of parts; any output may be NULL. */
+int lilac_csr64_info(lilac_csr64_t h, int *rows, int *cols, int64_t *nnz, int *nparts);
+/* Waits for the library's work on the parts, then frees them. */
+int lilac_csr64_destroy(lilac_csr64_t h);
+
 /* ---- second format and graph traversal -------------------------------- */
 /*
  * y = A x with A in Jagged Diagonal Storage (section "Sparse Matrix

@@ -19,7 +19,7 @@ import torch  # noqa: F401  (shares its HIP runtime with the library)
 __all__ = [
     "LilacError", "lib", "lilac_spmv_csr", "lilac_spmv_csr_f32", "lilac_dot",
     "lilac_invalidate", "lilac_release_all", "lilac_init", "lilac_finalize",
-    "lilac_dot_dev", "lilac_spmv_batched", "Csr", "F64", "F32",
+    "lilac_dot_dev", "lilac_spmv_batched", "Csr", "Csr64", "F64", "F32",
     "KEEP_HOST", "CG_GRAPH", "NCLASS", "HEADER_FUNCTIONS",
 ]
 
@@ -82,6 +82,10 @@ _SIGS = {
     "lilac_cg": ([_P, _P, _P, _I, ctypes.c_uint, _P, _P, _P], _I),
     "lilac_pagerank": ([_P, ctypes.c_float, _I, _P, _P], _I),
     "lilac_spmv_batched": ([_I, _P, _P, _P, _P], _I),
+    "lilac_csr64_create": ([ctypes.POINTER(_P), _I, _I, _I64, _P, _P, _P, _I], _I),
+    "lilac_csr64_spmv": ([_P, _P, _P, _P], _I),
+    "lilac_csr64_info": ([_P, _P, _P, _P, _P], _I),
+    "lilac_csr64_destroy": ([_P], _I),
     "lilac_csr_tune": ([_P, _P], _I),
     "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
     "lilac_spmv_jds": ([_I, _I, _P, _P, _P, _P, _P, _P, _P], _I),
@@ -347,6 +351,65 @@ class Csr:
         try:
             if getattr(self, "handle", None) and _lib is not None:
                 _lib.lilac_csr_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Csr64:
+    """CSR matrix with int64 row offsets (lilac_csr64_create ...
+    lilac_csr64_destroy): consecutive row parts, each an ordinary handle."""
+
+    def __init__(self, row_ptr, col_idx, vals, cols: int = -1):
+        if isinstance(row_ptr, torch.Tensor):
+            if row_ptr.dtype != torch.int64:
+                raise TypeError("row_ptr must be int64")
+            rp = row_ptr
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = _as_i32(col_idx)
+        if isinstance(vals, torch.Tensor):
+            if vals.dtype not in (torch.float32, torch.float64):
+                raise TypeError("vals must be float32 or float64")
+            dt = F32 if vals.dtype == torch.float32 else F64
+        else:
+            vals = np.ascontiguousarray(vals)
+            if vals.dtype not in (np.float32, np.float64):
+                vals = vals.astype(np.float64)
+            dt = F32 if vals.dtype == np.float32 else F64
+        rows = (rp.numel() if isinstance(rp, torch.Tensor) else rp.size) - 1
+        nnz = ci.numel() if isinstance(ci, torch.Tensor) else ci.size
+        h = ctypes.c_void_p()
+        _check(lib().lilac_csr64_create(ctypes.byref(h), rows, cols, nnz, _ptr(rp),
+                                        _ptr(ci), _ptr(vals), dt))
+        self.handle = h.value
+        self.dtype = dt
+        self.rows, self.cols, self.nnz, self.nparts = self.info()
+
+    @classmethod
+    def from_gen(cls, A, **kw):
+        return cls(A.row_ptr, A.col_idx, A.vals, **kw)
+
+    def info(self):
+        """(rows, cols, nnz, nparts)."""
+        r, c, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        z = ctypes.c_int64()
+        _check(lib().lilac_csr64_info(self.handle, ctypes.byref(r), ctypes.byref(c),
+                                      ctypes.byref(z), ctypes.byref(p)))
+        return r.value, c.value, z.value, p.value
+
+    def spmv(self, x, y, stream=None):
+        _check(lib().lilac_csr64_spmv(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            _check(lib().lilac_csr64_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.lilac_csr64_destroy(self.handle)
                 self.handle = None
         except Exception:
             pass

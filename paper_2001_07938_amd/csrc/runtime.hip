@@ -2252,6 +2252,163 @@ int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
     return guard([&] { run_batched(count, hs, xs, ys, pick_stream(stream)); });
 }
 
+// ------------------------------------------------- 64-bit row offsets
+
+// A matrix with int64 row offsets, kept as consecutive row parts that are
+// ordinary handles (32-bit offsets rebased to each part's first entry).
+struct Csr64 {
+    int rows = 0, cols = 0;
+    int64_t nnz = 0;
+    lilac_dtype dt = LILAC_F64;
+    std::vector<CsrHandle *> parts;
+    std::vector<int32_t> first_row;
+};
+
+// Most non-zeros of one part: below the 32-bit handle bound with room to
+// spare, or less when LILAC_PART_NNZ says so.
+static int64_t part_nnz_limit()
+{
+    int64_t lim = ((int64_t)1 << 31) - ((int64_t)1 << 20);
+    if (const char *e = std::getenv("LILAC_PART_NNZ")) {
+        const long long v = std::strtoll(e, nullptr, 10);
+        if (v >= 1 && v < lim)
+            lim = v;
+    }
+    return lim;
+}
+
+static void destroy_csr64(Csr64 *m)
+{
+    if (!m)
+        return;
+    (void)hipDeviceSynchronize();
+    for (CsrHandle *h : m->parts)
+        destroy_handle(h);
+    delete m;
+}
+
+static Csr64 *create_csr64(int rows, int cols, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col, const void *vals, lilac_dtype dt)
+{
+    if (rows < 0)
+        fail(LILAC_ERR_ARG, "rows must be >= 0");
+    if (nnz < 0)
+        fail(LILAC_ERR_ARG, "nnz must be >= 0");
+    if (!row_ptr)
+        fail(LILAC_ERR_ARG, "row_ptr is NULL");
+    if (nnz > 0 && (!col || !vals))
+        fail(LILAC_ERR_ARG, "col_idx or vals is NULL");
+    if (dt != LILAC_F64 && dt != LILAC_F32)
+        fail(LILAC_ERR_ARG, "unknown dtype");
+    // the offsets are needed on the host to cut the parts
+    std::vector<int64_t> rp((size_t)rows + 1);
+    if (is_device_ptr(row_ptr)) {
+        HIPC(hipDeviceSynchronize());
+        HIPC(hipMemcpy(rp.data(), row_ptr, rp.size() * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(rp.data(), row_ptr, rp.size() * 8);
+    }
+    if (rp[0] != 0 || rp[rows] != nnz)
+        fail(LILAC_ERR_CSR, "invalid CSR: row_ptr[0] != 0 or row_ptr[rows] != nnz");
+    for (int64_t r = 0; r < rows; ++r)
+        if (rp[r + 1] < rp[r])
+            fail(LILAC_ERR_CSR, "invalid CSR: row_ptr decreases");
+    const int64_t lim = part_nnz_limit();
+    const size_t vs = dtype_size(dt);
+    auto *m = new Csr64();
+    m->rows = rows;
+    m->nnz = nnz;
+    m->dt = dt;
+    try {
+        int64_t r0 = 0;
+        std::vector<int32_t> rb;
+        while (r0 < rows) {
+            if (rp[r0 + 1] - rp[r0] > lim)
+                fail(LILAC_ERR_UNSUPPORTED, "a row has more non-zeros than one part holds");
+            // the last row end within the bound
+            const int64_t r1 =
+                (int64_t)(std::upper_bound(rp.begin() + r0 + 1, rp.end(), rp[r0] + lim) -
+                          rp.begin()) - 1;
+            const int64_t e0 = rp[r0];
+            rb.resize((size_t)(r1 - r0) + 1);
+            for (int64_t r = r0; r <= r1; ++r)
+                rb[(size_t)(r - r0)] = (int32_t)(rp[r] - e0);
+            const int64_t pn = rp[r1] - e0;
+            CsrHandle *h = create_handle((int)(r1 - r0), cols, pn, rb.data(),
+                                         pn > 0 ? col + e0 : col,
+                                         pn > 0 ? (const char *)vals + e0 * (int64_t)vs : vals,
+                                         dt, 0);
+            m->parts.push_back(h);
+            m->first_row.push_back((int32_t)r0);
+            m->cols = std::max(m->cols, h->cols);
+            r0 = r1;
+        }
+        if (cols >= 0)
+            m->cols = cols;
+    } catch (...) {
+        destroy_csr64(m);
+        throw;
+    }
+    return m;
+}
+
+int lilac_csr64_create(lilac_csr64_t *h, int rows, int cols, int64_t nnz,
+                       const int64_t *row_ptr, const int *col_idx, const void *vals,
+                       lilac_dtype dt)
+{
+    return guard([&] {
+        if (!h)
+            fail(LILAC_ERR_ARG, "handle pointer is NULL");
+        *h = nullptr;
+        *h = (lilac_csr64_t)create_csr64(rows, cols, nnz, row_ptr, col_idx, vals, dt);
+    });
+}
+
+int lilac_csr64_spmv(lilac_csr64_t hh, const void *x, void *y, void *stream)
+{
+    return guard([&] {
+        Csr64 *m = (Csr64 *)hh;
+        if (!m)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        if (m->rows > 0 && (!y || (m->cols > 0 && !x)))
+            fail(LILAC_ERR_ARG, "NULL vector");
+        const size_t n = m->parts.size();
+        if (n == 0)
+            return;
+        const size_t vs = dtype_size(m->dt);
+        std::vector<lilac_csr_t> hs(n);
+        std::vector<const void *> xs(n, x);
+        std::vector<void *> ys(n);
+        for (size_t p = 0; p < n; ++p) {
+            hs[p] = (lilac_csr_t)m->parts[p];
+            ys[p] = (char *)y + (int64_t)m->first_row[p] * (int64_t)vs;
+        }
+        run_batched((int)n, hs.data(), xs.data(), ys.data(), pick_stream(stream));
+    });
+}
+
+int lilac_csr64_info(lilac_csr64_t hh, int *rows, int *cols, int64_t *nnz, int *nparts)
+{
+    return guard([&] {
+        const Csr64 *m = (const Csr64 *)hh;
+        if (!m)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        if (rows)
+            *rows = m->rows;
+        if (cols)
+            *cols = m->cols;
+        if (nnz)
+            *nnz = m->nnz;
+        if (nparts)
+            *nparts = (int)m->parts.size();
+    });
+}
+
+int lilac_csr64_destroy(lilac_csr64_t hh)
+{
+    return guard([&] { destroy_csr64((Csr64 *)hh); });
+}
+
 int lilac_bfs(lilac_csr_t hh, int source, int *level, int *nlevels, void *stream)
 {
     return guard([&] {

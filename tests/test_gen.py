@@ -88,3 +88,29 @@ def test_batch_specs_and_trace():
     assert abs(gaps.mean() - 1e-4) < 5e-6
     assert 0.08 < np.mean(tr.matrix >= 64) < 0.12
     assert 0.18 < np.mean(tr.kind) < 0.22
+
+
+def test_strided_rows_exact_k_distinct_sorted_int64_offsets():
+    A = gen.strided_rows(3000, 37, 1000, seed=5, chunk_rows=512)
+    assert A.row_ptr.dtype == np.int64 and A.col_idx.dtype == np.int32
+    assert np.array_equal(A.row_ptr, np.arange(3001) * 37)
+    c = A.col_idx.reshape(3000, 37).astype(np.int64)
+    assert np.all(np.diff(c, axis=1) > 0)
+    assert c.min() >= 0 and c.max() < 1000
+    # every row is {(a + j*s) mod cols : j < k} for one of its own entries a
+    s = 1000 // 37
+    for i in range(0, 3000, 97):
+        row = set(c[i].tolist())
+        assert any({(a + j * s) % 1000 for j in range(37)} == row for a in c[i])
+    v = A.vals
+    assert np.all(v == np.round(v)) and v.min() >= -8 and v.max() <= 8
+    B = gen.strided_rows(3000, 37, 1000, seed=5, chunk_rows=512)
+    assert np.array_equal(A.col_idx, B.col_idx) and np.array_equal(A.vals, B.vals)
+    # steps that cover cols exactly
+    C = gen.strided_rows(500, 16, 256, seed=6)
+    c = C.col_idx.reshape(500, 16)
+    assert np.all(np.diff(c, axis=1) == 16) and np.all(c[:, 0] < 16)
+    # consecutive windows
+    W = gen.strided_rows(400, 9, 100, seed=7, window=True)
+    w = W.col_idx.reshape(400, 9)
+    assert np.all(np.diff(w, axis=1) == 1) and w.min() >= 0 and w.max() < 100
