@@ -220,10 +220,14 @@ static int tile_occupancy(lilac_dtype dt);
 
 // ============================================================ plan / tiles
 
+// Default row classes: two non-zeros per lane where a lane loads single
+// elements (groups of 1 to 4 lanes), eight where it loads 16-byte vectors
+// (8 to 32 lanes: rows of up to 64, 128 and 256), more rows in flight per
+// wavefront than one or two vectors per lane give.
 Plan default_plan()
 {
     Plan p;
-    const int32_t up[NCLASS] = {2, 4, 8, 16, 32, 64, 1024, 8192, INT_MAX};
+    const int32_t up[NCLASS] = {2, 4, 8, 64, 128, 256, 1024, 8192, INT_MAX};
     const int32_t rpg[NCLASS] = {1, 1, 1, 1, 1, 1, 2, 1, 1};
     for (int c = 0; c < NCLASS; ++c) {
         p.upper[c] = up[c];
@@ -515,7 +519,10 @@ static void build_hot(CsrHandle &h, hipStream_t s)
 // fewer than 65536 columns; returns whether it did.  Block bounds are chosen
 // on the host: a new block starts when the current one has kBandRows rows,
 // `target` entries or more, or would span 65536 columns or more.
-static bool build_band(CsrHandle &h, hipStream_t s)
+// Fewest non-zeros per band block, on average, for the automatic choice.
+constexpr int64_t kBandMinEntries = 1024;
+
+static bool build_band(CsrHandle &h, hipStream_t s, bool automatic)
 {
     if (h.rows == 0 || h.nnz == 0)
         return false;
@@ -560,6 +567,12 @@ static bool build_band(CsrHandle &h, hipStream_t s)
     }
     cbase.push_back(bmax >= 0 ? (int32_t)bmin : 0);
     brow.push_back(h.rows);
+    // chosen automatically, the blocks must stay long: rows whose columns
+    // are local to each row but not to their neighbours (windows at
+    // scattered offsets) cut a block at nearly every row, and a workgroup
+    // per few entries is slower than the row-class tiles
+    if (automatic && h.nnz < kBandMinEntries * (int64_t)cbase.size())
+        return false;
     BandDesc bd{};
     bd.rows = h.rows;
     bd.cols = h.cols;
@@ -712,7 +725,7 @@ static void analyse(CsrHandle &h, hipStream_t s)
         build_panels(h, s);
         h.grid = h.pan.nblk;   // one fused-dot partial per row block
         h.fin_blocks = 0;
-    } else if (want_band && build_band(h, s)) {
+    } else if (want_band && build_band(h, s, h.plan.layout == LAYOUT_AUTO)) {
         h.grid = h.band.nblk;  // one fused-dot partial per row block
         h.fin_blocks = 0;
     }

@@ -535,12 +535,18 @@ def test_band_layout_parity(name):
 
 def test_layout_choice_and_band_fallback():
     """The automatic choice: scattered columns -> column panels, local
-    columns -> band, tiny -> rows; a row spanning 65536 columns or more
-    makes the band impossible (rows layout instead)."""
+    columns -> band, tiny -> rows, and rows of consecutive columns at
+    scattered offsets (local within a row, not between rows: band blocks
+    of one row each) -> rows; a row spanning 65536 columns or more makes
+    the band impossible (rows layout instead)."""
+    win = gen.strided_rows(100000, 16, 1 << 21, seed=4, dtype=np.float64, window=True)
+    win = gen.Csr(win.rows, win.cols, win.row_ptr.astype(np.int32), win.col_idx,
+                  win.vals, "window16")
     cases = [(gen.spd_random(40000, 60, seed=6), L.LAYOUT_PANELS),
              (gen.stencil(30, 27), L.LAYOUT_BAND),
              (gen.stencil(30, 7), L.LAYOUT_BAND),
-             (gen.random_rows(2000, 1, 4, seed=3), L.LAYOUT_ROWS)]
+             (gen.random_rows(2000, 1, 4, seed=3), L.LAYOUT_ROWS),
+             (win, L.LAYOUT_ROWS)]
     for A, want in cases:
         h = L.Csr.from_gen(A)
         assert h.info().layout == want, (A.name, h.info().layout)
