@@ -939,6 +939,38 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
         *ckey = first;
         *csum = 0.0;
     }
+    // whether entry j of the chunk at `base` lies in the share, and the
+    // column it gathers (entries outside the share may belong to the other
+    // part, another packing: they gather element 0, which always exists)
+    auto in_share = [&](int32_t base, int j) {
+        const int32_t en = base + 2 * lane + j;
+        return (base >= ks && base + 128 <= ke) || (en >= ks && en < ke);
+    };
+    auto column = [&](uint32_t w, bool ok) {
+        return ok ? (HOT ? (w & 0xFFFFu) : w) : 0u;
+    };
+    auto request = [&](int32_t at, pair_t &rv, upair_t &rr, kpair_t &rk) {
+        const int32_t nn = at + 2 * lane;
+        const int32_t ea = (nn < ke) ? nn : kb;
+        rv = ld_stream((const pair_t *)(pv + ea));
+        rr = ld_stream((const upair_t *)(prc + ea));
+        if (!HOT)
+            rk = ld_stream((const kpair_t *)(pkey + ea));
+    };
+    // gathers from device memory: the next chunk's entries are in hand and
+    // its gathers requested before this chunk's arithmetic, with the entries
+    // of the chunk after it on the way (two memory round trips per chunk,
+    // the second depending on the first, kept in flight together)
+    V gx0 = 0, gx1 = 0;     // gathers of the current chunk
+    pair_t v2;              // entries of the next chunk
+    upair_t rc2;
+    kpair_t kk2;
+    if (XG && kb < ke) {
+        gx0 = gld(xsrc + column(rc.x, in_share(kb, 0)));
+        gx1 = gld(xsrc + column(rc.y, in_share(kb, 1)));
+        if (kb + 128 < ke)
+            request(kb + 128, v2, rc2, kk2);
+    }
     for (int32_t base = kb; base < ke; base += 128) {
         const int32_t en = base + 2 * lane;
         // chunks wholly inside [ks, ke) (most of them) need no bound checks
@@ -951,21 +983,27 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
         // previous wavefront (-1), entries past ke to nobody (kKeyEnd)
         const int32_t k0 = full ? r0 : (en < ks) ? -1 : ok0 ? r0 : kKeyEnd;
         const int32_t k1 = full ? r1 : (en + 1 < ks) ? -1 : ok1 ? r1 : kKeyEnd;
-        // entries outside the share may belong to the other part (another
-        // packing): gather element 0 for them, which always exists
-        const uint32_t c0 = ok0 ? (HOT ? (rc.x & 0xFFFFu) : rc.x) : 0u;
-        const uint32_t c1 = ok1 ? (HOT ? (rc.y & 0xFFFFu) : rc.y) : 0u;
-        const V x0 = XG ? gld(xsrc + c0) : xsrc[c0];
-        const V x1 = XG ? gld(xsrc + c1) : xsrc[c1];
         const pair_t cv = v;
         const int32_t nb = base + 128;
-        if (nb < ke) {
-            const int32_t nn = nb + 2 * lane;
-            const int32_t ea = (nn < ke) ? nn : kb;
-            v = ld_stream((const pair_t *)(pv + ea));
-            rc = ld_stream((const upair_t *)(prc + ea));
-            if (!HOT)
-                kk = ld_stream((const kpair_t *)(pkey + ea));
+        V x0, x1;
+        if (XG) {
+            x0 = gx0;
+            x1 = gx1;
+            if (nb < ke) {
+                v = v2;
+                rc = rc2;
+                if (!HOT)
+                    kk = kk2;
+                gx0 = gld(xsrc + column(rc.x, in_share(nb, 0)));
+                gx1 = gld(xsrc + column(rc.y, in_share(nb, 1)));
+                if (nb + 128 < ke)
+                    request(nb + 128, v2, rc2, kk2);
+            }
+        } else {
+            x0 = xsrc[column(rc.x, ok0)];
+            x1 = xsrc[column(rc.y, ok1)];
+            if (nb < ke)
+                request(nb, v, rc, kk);
         }
         const double p0 = ok0 ? (double)cv.x * (double)x0 : 0.0;
         const double p1 = ok1 ? (double)cv.y * (double)x1 : 0.0;
