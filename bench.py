@@ -411,9 +411,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; "
-                                   "multi-GPU sharding is described in DESIGN.md "
-                                   "but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on exactly one GPU; sharding "
+                                   "over several GPUs is not implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     import gen
