@@ -102,6 +102,9 @@ int lilac_spmv_csr_f32(int rows, const int *row_ptr, const int *col_idx,
  * order.  n == 0 gives 0.  On error returns NaN and sets lilac_last_error.
  */
 double lilac_dot(int64_t n, const double *a, const double *b);
+/* The same for float32 arrays: products and sums in binary64 (the float32
+ * values widened exactly), the total rounded once to float32. */
+float lilac_dot_f32(int64_t n, const float *a, const float *b);
 
 /* Marshaling control for the raw calls: the next call that uses the array
  * containing `ptr` re-uploads it (values only when ptr is a vals array,

@@ -65,6 +65,7 @@ _SIGS = {
     "lilac_spmv_csr": ([_I, _P, _P, _P, _P, _P], _I),
     "lilac_spmv_csr_f32": ([_I, _P, _P, _P, _P, _P], _I),
     "lilac_dot": ([_I64, _P, _P], ctypes.c_double),
+    "lilac_dot_f32": ([_I64, _P, _P], ctypes.c_float),
     "lilac_invalidate": ([_P], _I),
     "lilac_release_all": ([], _I),
     "lilac_csr_create": ([ctypes.POINTER(_P), _I, _I, _I64, _P, _P, _P, _I,
@@ -191,6 +192,15 @@ def lilac_spmv_csr_f32(rows: int, row_ptr, col_idx, vals, x, y):
 
 def lilac_dot(n: int, a, b) -> float:
     r = lib().lilac_dot(n, _ptr(a), _ptr(b))
+    if np.isnan(r):
+        err = lib().lilac_last_error().decode()
+        if err:
+            raise LilacError(-1, err)
+    return r
+
+
+def lilac_dot_f32(n: int, a, b) -> float:
+    r = lib().lilac_dot_f32(n, _ptr(a), _ptr(b))
     if np.isnan(r):
         err = lib().lilac_last_error().decode()
         if err:

@@ -1935,15 +1935,18 @@ __device__ __forceinline__ double sum_parts_1024(const double *__restrict__ part
     return block_sum<16>(acc, lds);
 }
 
+// Partial dot products, one per workgroup (float32 data is widened exactly
+// and accumulated in binary64).
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dot_parts(
-    int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+    int64_t n, const T *__restrict__ a, const T *__restrict__ b,
     double *__restrict__ part)
 {
     __shared__ double lds[kWaves];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)
-        acc = fma(a[i], b[i], acc);
+        acc = fma((double)a[i], (double)b[i], acc);
     const double t = block_sum<kWaves>(acc, lds);
     if (threadIdx.x == 0)
         part[blockIdx.x] = t;
@@ -2673,7 +2676,15 @@ void launch_cgb_xpay(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_
 void launch_dot_parts(int64_t n, const double *a, const double *b,
                       double *part, int32_t nparts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dot_parts, dim3(nparts), dim3(kBlock), 0, s, n, a, b,
+    hipLaunchKernelGGL(k_dot_parts<double>, dim3(nparts), dim3(kBlock), 0, s, n, a, b,
+                       part);
+    check_launch("k_dot_parts");
+}
+
+void launch_dot_parts_f32(int64_t n, const float *a, const float *b,
+                          double *part, int32_t nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_parts<float>, dim3(nparts), dim3(kBlock), 0, s, n, a, b,
                        part);
     check_launch("k_dot_parts");
 }

@@ -372,6 +372,8 @@ void launch_cgb_xpay(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_
 
 void launch_dot_parts(int64_t n, const double *a, const double *b,
                       double *part, int32_t nparts, hipStream_t s);
+void launch_dot_parts_f32(int64_t n, const float *a, const float *b,
+                          double *part, int32_t nparts, hipStream_t s);
 
 // One level of a breadth-first search as a Boolean product over the tiles:
 // every row v with level[v] == -1 that has a column u with level[u] == depth

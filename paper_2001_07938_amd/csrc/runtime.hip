@@ -3,6 +3,7 @@
 // pointer marshaling cache, CG and PageRank drivers (captured as HIP graphs),
 // grouped batched products, the autotuner and the C ABI entry points.
 #include <algorithm>
+#include <type_traits>
 #include <cctype>
 #include <atomic>
 #include <chrono>
@@ -1166,7 +1167,8 @@ static void invalidate_ptr(const void *ptr)
 
 // ===================================================================== dot
 
-static double raw_dot(int64_t n, const double *a, const double *b)
+template <typename T>
+static double raw_dot(int64_t n, const T *a, const T *b)
 {
     if (n < 0)
         fail(LILAC_ERR_ARG, "n must be >= 0");
@@ -1176,8 +1178,8 @@ static double raw_dot(int64_t n, const double *a, const double *b)
         fail(LILAC_ERR_ARG, "a or b is NULL");
     Context &c = ctx();
     hipStream_t s = c.stream;
-    const double *da = a, *db = b;
-    const size_t bytes = (size_t)n * 8;
+    const T *da = a, *db = b;
+    const size_t bytes = (size_t)n * sizeof(T);
     const bool ad = is_device_ptr(a), bd = is_device_ptr(b);
     if (ad || bd)
         HIPC(hipDeviceSynchronize());
@@ -1192,15 +1194,18 @@ static double raw_dot(int64_t n, const double *a, const double *b)
         }
         if (!ad) {
             HIPC(hipMemcpyAsync(c.dot_a, a, bytes, hipMemcpyHostToDevice, s));
-            da = c.dot_a;
+            da = (const T *)c.dot_a;
         }
         if (!bd) {
             HIPC(hipMemcpyAsync(c.dot_b, b, bytes, hipMemcpyHostToDevice, s));
-            db = c.dot_b;
+            db = (const T *)c.dot_b;
         }
     }
     const int32_t np = blas1_parts(n);
-    launch_dot_parts(n, da, db, c.dot_part, np, s);
+    if constexpr (std::is_same<T, float>::value)
+        launch_dot_parts_f32(n, da, db, c.dot_part, np, s);
+    else
+        launch_dot_parts(n, da, db, c.dot_part, np, s);
     launch_sum_parts(c.dot_part, np, c.dot_part + kDotParts, s);
     double r = 0.0;
     HIPC(hipMemcpyAsync(&r, c.dot_part + kDotParts, 8, hipMemcpyDeviceToHost, s));
@@ -2014,6 +2019,13 @@ double lilac_dot(int64_t n, const double *a, const double *b)
     double r = NAN;
     const int st = guard([&] { r = raw_dot(n, a, b); });
     return st == LILAC_OK ? r : NAN;
+}
+
+float lilac_dot_f32(int64_t n, const float *a, const float *b)
+{
+    double r = NAN;
+    const int st = guard([&] { r = raw_dot(n, a, b); });
+    return st == LILAC_OK ? (float)r : NAN;
 }
 
 int lilac_invalidate(const void *ptr)

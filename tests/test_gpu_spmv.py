@@ -248,6 +248,21 @@ def test_dot_raw_and_device():
     assert L.lilac_dot(1 << 20, np.ones(1 << 20), np.ones(1 << 20)) == float(1 << 20)
 
 
+def test_dot_f32_raw_host_and_device():
+    """float32 arrays: products and sums in binary64, one final rounding."""
+    for n in (0, 1, 1000, 150_000, 3_000_001):
+        a = gen.vector(n, 52, dtype=np.float32)
+        b = gen.vector(n, 53, dtype=np.float32)
+        ref = oracle.dot(a.astype(np.float64), b.astype(np.float64))
+        mag = oracle.dot_abs(a.astype(np.float64), b.astype(np.float64))
+        got = L.lilac_dot_f32(n, a, b)
+        assert abs(got - ref) <= TOL_F32 * (mag + abs(ref))
+        if n:
+            assert L.lilac_dot_f32(n, _dev(a), _dev(b)) == got
+    ones = np.ones(1 << 20, dtype=np.float32)
+    assert L.lilac_dot_f32(1 << 20, ones, ones) == float(1 << 20)
+
+
 PANEL_MATS = {
     "spd20k": lambda: gen.spd_random(20000, 60, seed=6),
     "uniform16": lambda: gen.uniform_rows(4096, 16),
