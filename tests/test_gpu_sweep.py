@@ -1,7 +1,8 @@
 """A seeded sweep of small matrices of assorted shapes through every storage
 layout of the product, against the oracle: row lengths from empty to a few
 thousand, scattered and local columns, sorted and unsorted, duplicates,
-float64 and float32, x aligned and 8 bytes off a 16-byte boundary."""
+float64 and float32, x aligned and 8 bytes off a 16-byte boundary, and the
+product with the fused dot (float64)."""
 import numpy as np
 import pytest
 import torch
@@ -60,12 +61,23 @@ def test_sweep_all_layouts(i):
         buf = torch.empty(B.cols + off, dtype=tdt, device=DEV)
         buf[off:] = torch.from_numpy(x).to(DEV)
         xd = buf[off:]
+        w = gen.vector(B.rows, 5000 + i)
+        wd = torch.from_numpy(w).to(DEV)
         for lay in LAYOUTS:
             h.set_layout(lay)
             yd = torch.full((B.rows,), float("nan"), dtype=tdt, device=DEV)
             h.spmv(xd, yd)
             torch.cuda.synchronize()
-            check_spmv(B, x, yd.cpu().numpy(), tol)
+            y = yd.cpu().numpy()
+            check_spmv(B, x, y, tol)
+            if dt == np.float64:
+                # the product with the fused dot: the same y, and w . y
+                y2 = torch.empty_like(yd)
+                out = torch.empty(1, dtype=torch.float64, device=DEV)
+                h.spmv_dot(xd, y2, wd, out)
+                torch.cuda.synchronize()
+                assert np.array_equal(y2.cpu().numpy(), y), (i, lay)
+                assert abs(out.item() - oracle.dot(w, y)) <= TOL_F64 * oracle.dot_abs(w, y)
         h.destroy()
     # integer data: every layout exact
     A.vals = gen.int_vector(A.nnz, 3000 + i)
