@@ -204,7 +204,10 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * entries and add up each row's run with a segmented scan.  LILAC_LAYOUT_AUTO
  * picks it for matrices with at least 16384 non-zeros whose columns are
  * local (sampled distinct 128-byte x lines per non-zero below 0.3) when it
- * is possible.  Re-runs the analysis.
+ * is possible and its blocks average at least 1024 non-zeros (rows whose
+ * columns are local within each row but not between neighbouring rows cut
+ * a block at nearly every row: those stay on the rows layout).  Re-runs
+ * the analysis.
  */
 #define LILAC_LAYOUT_AUTO (-1)
 #define LILAC_LAYOUT_ROWS 0
