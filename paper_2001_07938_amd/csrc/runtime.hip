@@ -221,6 +221,11 @@ static int tile_occupancy(lilac_dtype dt);
 
 // ============================================================ plan / tiles
 
+// Persistent workgroups of the tile kernel per CU by default: four ran
+// faster than eight or more on every matrix shape measured (long and short
+// rows, local and scattered columns), and than two or three.
+constexpr int kTileGroupsPerCu = 4;
+
 // Default row classes: two non-zeros per lane where a lane loads single
 // elements (groups of 1 to 4 lanes), eight where it loads 16-byte vectors
 // (8 to 32 lanes: rows of up to 64, 128 and 256), more rows in flight per
@@ -235,7 +240,7 @@ Plan default_plan()
         p.rpg[c] = rpg[c];
     }
     p.chunk = 4096;
-    p.grid_per_cu = 8;
+    p.grid_per_cu = kTileGroupsPerCu;
     p.layout = LAYOUT_AUTO;
     return p;
 }
@@ -1008,7 +1013,7 @@ static Epi epi_none() { return Epi{EPI_NONE, 0, 0.0, 0.0}; }
 
 int tile_grid(lilac_dtype dt)
 {
-    return ctx().cu * std::max(1, std::min(8, tile_occupancy(dt)));
+    return ctx().cu * std::max(1, std::min(kTileGroupsPerCu, tile_occupancy(dt)));
 }
 
 // Workgroups of the tile kernel that fit on one CU at once.
@@ -1644,7 +1649,7 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
         free_group(g);
         throw;
     }
-    const int occ = std::max(1, std::min(8, tile_occupancy(g->dt)));
+    const int occ = std::max(1, std::min(kTileGroupsPerCu, tile_occupancy(g->dt)));
     g->grid = std::min<int32_t>(g->ntiles, ctx().cu * occ);
     return g;
 }
