@@ -841,18 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_wptr(PanelDesc pd,
 // Row keys inside a block are below 2^16; this one is past every row.
 constexpr int32_t kKeyEnd = 1 << 16;
 
-// One wavefront's share of a block part [s, e) of the hot-column layout.
-// The part is split evenly by entries, so a row can span wavefronts: the
-// run of the wavefront's first row goes to its carry slot (added after the
-// block, in slot order), every other run is added to the row sum in LDS by
-// the one wavefront where it ends.  HOT: the entry's word packs (row << 16)
-// | column offset and the gather reads xsrc[offset] (the LDS copy of the
-// hot columns, or x from a block's first column in the band layout);
-// otherwise the word is the column of x and the row comes from key[].  The
-// entries of the next chunk are requested before the gathers of the
-// current one are used.  NW wavefronts share the part; XG: xsrc is in
-// device memory (else in LDS).  PRE: the first chunk was requested earlier
-// into *pre (hot_first, same part and wavefront).
+// The first chunk of a wavefront's share of a block part, requested ahead.
 template <typename V>
 struct HotChunk {
     typedef V pair_t __attribute__((ext_vector_type(2)));
@@ -897,6 +886,19 @@ __device__ __forceinline__ void hot_first(const V *__restrict__ pv,
     }
 }
 
+// One wavefront's share of a block part [s, e) of the hot-column layout.
+// The part is split evenly by entries, so a row can span wavefronts: the
+// run of the wavefront's first row goes to its carry slot (added after the
+// block, in slot order), every other run is added to the row sum in LDS by
+// the one wavefront where it ends.  HOT: the entry's word packs (row << 16)
+// | column offset and the gather reads xsrc[offset] (the LDS copy of the
+// hot columns, or x from a block's first column in the band layout);
+// otherwise the word is the column of x and the row comes from key[].  The
+// entries of the next chunk are requested before the gathers of the
+// current one are used; with gathers from device memory the next chunk's
+// gathers are requested too.  NW wavefronts share the part; XG: xsrc is in
+// device memory (else in LDS).  PRE: the first chunk was requested earlier
+// into *pre (hot_first, same part and wavefront).
 template <typename V, bool HOT, int NW = kPanelWaves, bool XG = !HOT, bool PRE = false>
 __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
                                          const uint32_t *__restrict__ prc,
