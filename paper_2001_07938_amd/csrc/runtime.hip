@@ -1596,13 +1596,28 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
             HIPC(hipMemcpyAsync(g->d_items, items.data(), items.size() * 4,
                                 hipMemcpyHostToDevice, s));
         }
+        // the grouped launches take the matrices with the most non-zeros per
+        // block first, so that the last workgroups to start are short ones
+        auto heavy_first = [&](bool panels) {
+            std::vector<int> order;
+            for (int j = 0; j < count; ++j) {
+                const CsrHandle *h = g->hs[j];
+                if ((panels ? h->use_panels : h->use_band) && h->rows > 0)
+                    order.push_back(j);
+            }
+            auto per_block = [&](int j) {
+                const CsrHandle *h = g->hs[j];
+                return (double)h->nnz / (double)std::max(1, panels ? h->pan.nblk : h->band.nblk);
+            };
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int b) { return per_block(a) > per_block(b); });
+            return order;
+        };
         std::vector<PanelDesc> pdesc;
         std::vector<PanelIO> pio;
         std::vector<int32_t> pprefix(1, 0);
-        for (int j = 0; j < count; ++j) {
+        for (int j : heavy_first(true)) {
             const CsrHandle *h = g->hs[j];
-            if (!h->use_panels || h->rows == 0)
-                continue;
             pdesc.push_back(h->pan);
             pio.push_back(PanelIO{xs[j], ys[j]});
             pprefix.push_back(pprefix.back() + h->pan.nblk);
@@ -1610,10 +1625,8 @@ static GroupPlan *build_group(int count, const lilac_csr_t *hs,
         std::vector<BandDesc> bdesc;
         std::vector<PanelIO> bio;
         std::vector<int32_t> bprefix(1, 0);
-        for (int j = 0; j < count; ++j) {
+        for (int j : heavy_first(false)) {
             const CsrHandle *h = g->hs[j];
-            if (!h->use_band || h->rows == 0)
-                continue;
             bdesc.push_back(h->band);
             bio.push_back(PanelIO{xs[j], ys[j]});
             bprefix.push_back(bprefix.back() + h->band.nblk);
