@@ -483,7 +483,17 @@ void run_tick(Server *S)
     std::vector<PanelIO> bio;
     std::vector<int32_t> bprefix(1, 0);
     std::vector<Req *> own_hot;
-    for (Req *r : own) {
+    // matrices with the most non-zeros per block first, so that a grouped
+    // launch ends on short blocks
+    std::vector<Req *> heavy(own.begin(), own.end());
+    auto per_block = [&](const Req *r) {
+        const CsrHandle &h = *S->mats[r->mid].h;
+        const int32_t nb = h.use_panels ? h.pan.nblk : h.use_band ? h.band.nblk : 1;
+        return (double)h.nnz / (double)std::max(1, nb);
+    };
+    std::stable_sort(heavy.begin(), heavy.end(),
+                     [&](const Req *a, const Req *b) { return per_block(a) > per_block(b); });
+    for (Req *r : heavy) {
         SMatrix &m = S->mats[r->mid];
         Slot &sl = S->slots[r->slot];
         const PanelIO io = (r->kind == LILAC_REQ_SPMV)
