@@ -1029,7 +1029,8 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
 }
 
 // Product over the hot-column layout.  Persistent: workgroup g copies the
-// hot columns of x into LDS once, then takes row blocks g, g + grid, ...
+// hot columns of x into LDS once, then takes its own list of row blocks
+// (assigned on the host, balanced by work).
 // Each wavefront streams its share of the block's hot part and of its cold
 // part (odd wavefronts cold first, so LDS and global gathers overlap); the
 // two parts add into separate row sums, so no wavefront waits for another
@@ -1074,9 +1075,13 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
         else
             hot_first<V, true>(pv, hd.rc, hd.key, pe0, pes, wave, lane, pre);
     };
-    if ((int32_t)blockIdx.x < hd.nblk)
-        prefetch(blockIdx.x);
-    for (int32_t b = blockIdx.x; b < hd.nblk; b += gridDim.x) {
+    // this workgroup's blocks (a static assignment balanced by work)
+    const int32_t i0 = ((cptr)hd.gptr)[blockIdx.x];
+    const int32_t i1 = ((cptr)hd.gptr)[blockIdx.x + 1];
+    if (i0 < i1)
+        prefetch(((cptr)hd.gblk)[i0]);
+    for (int32_t i = i0; i < i1; ++i) {
+        const int32_t b = ((cptr)hd.gblk)[i];
         const int32_t r0 = ((cptr)hd.brow)[b];
         const int32_t nr = ((cptr)hd.brow)[b + 1] - r0;
         const int32_t e0 = ((cptr)hd.bent)[b], es = ((cptr)hd.bsplit)[b];
@@ -1096,8 +1101,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
                                ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
                                wave, lane);
         }
-        if (b + (int32_t)gridDim.x < hd.nblk)
-            prefetch(b + gridDim.x);
+        if (i + 1 < i1)
+            prefetch(((cptr)hd.gblk)[i + 1]);
         __syncthreads();  // all runs are in
         if (wave == 0) {
             // lanes 0-15: hot slots, 16-31: cold slots.  A slot leads its

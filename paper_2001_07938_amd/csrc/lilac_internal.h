@@ -145,6 +145,8 @@ struct HotDesc {
     const int32_t *brow;     // [nblk + 1]
     const int32_t *bent;     // [nblk + 1]
     const int32_t *bsplit;   // [nblk]
+    const int32_t *gptr;     // [grid + 1]: workgroup g takes blocks gblk[gptr[g] .. gptr[g+1])
+    const int32_t *gblk;     // [nblk]
     int32_t rows, cols, nblk, hot, grid, pad;
 };
 constexpr int kHotRows = 2048;                        // rows per block

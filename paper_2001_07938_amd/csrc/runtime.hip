@@ -3,6 +3,7 @@
 // pointer marshaling cache, CG and PageRank drivers (captured as HIP graphs),
 // grouped batched products, the autotuner and the C ABI entry points.
 #include <algorithm>
+#include <queue>
 #include <type_traits>
 #include <cctype>
 #include <atomic>
@@ -314,7 +315,7 @@ static int64_t analysis_bytes(const CsrHandle &h)
              (int64_t)h.pan.nblk * h.pan.np * (kPanelWaves + 1) * 4;
     if (h.use_hot)
         b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 6) +
-             (int64_t)(3 * h.hot.nblk + 2) * 4;
+             (int64_t)(4 * h.hot.nblk + h.hot.grid + 3) * 4;
     if (h.use_band)
         b += (h.nnz + kPad) * 4 + (int64_t)(3 * h.band.nblk + 2) * 4;
     return b;
@@ -481,17 +482,58 @@ static void build_hot(CsrHandle &h, hipStream_t s)
     brow.push_back(h.rows);
     hd.nblk = (int32_t)brow.size() - 1;
     hd.grid = std::min<int32_t>(hd.nblk, c.cu);
-    std::vector<int32_t> hb((size_t)3 * hd.nblk + 2);
+    // blocks to workgroups: longest first, each to the least loaded
+    // workgroup so far (work = entries + rows), then each workgroup's blocks
+    // in ascending order.  Blocks differ a lot (the densest rows come first
+    // after relabelling), so taking every grid-th block leaves some
+    // workgroups a quarter more work than the mean.
+    std::vector<int32_t> owner((size_t)hd.nblk);
+    {
+        auto work = [&](int32_t b) {
+            return (int64_t)rp[brow[b + 1]] - rp[brow[b]] + (brow[b + 1] - brow[b]);
+        };
+        std::vector<int32_t> order((size_t)hd.nblk);
+        for (int32_t b = 0; b < hd.nblk; ++b)
+            order[b] = b;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return work(a) > work(b); });
+        typedef std::pair<int64_t, int32_t> Load;   // (work so far, workgroup)
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> least;
+        for (int32_t g = 0; g < hd.grid; ++g)
+            least.push(Load(0, g));
+        for (int32_t b : order) {
+            Load l = least.top();
+            least.pop();
+            owner[b] = l.second;
+            l.first += work(b);
+            least.push(l);
+        }
+    }
+    const size_t nb1 = (size_t)hd.nblk + 1;
+    std::vector<int32_t> hb(3 * nb1 - 1 + (size_t)hd.grid + 1 + hd.nblk);
     for (int32_t b = 0; b <= hd.nblk; ++b) {
         hb[b] = brow[b];
-        hb[hd.nblk + 1 + b] = rp[brow[b]];
+        hb[nb1 + b] = rp[brow[b]];
+    }
+    int32_t *gptr = hb.data() + 3 * nb1 - 1;
+    int32_t *gblk = gptr + hd.grid + 1;
+    for (int32_t b = 0; b < hd.nblk; ++b)
+        ++gptr[owner[b] + 1];
+    for (int32_t g = 0; g < hd.grid; ++g)
+        gptr[g + 1] += gptr[g];
+    {
+        std::vector<int32_t> fill(gptr, gptr + hd.grid);
+        for (int32_t b = 0; b < hd.nblk; ++b)
+            gblk[fill[owner[b]]++] = b;
     }
     h.d_hb = (int32_t *)dev_alloc(hb.size() * 4);
     HIPC(hipMemcpyAsync(h.d_hb, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, s));
     hd.brow = h.d_hb;
-    hd.bent = h.d_hb + hd.nblk + 1;
-    int32_t *bsplit = h.d_hb + 2 * (hd.nblk + 1);
+    hd.bent = h.d_hb + nb1;
+    int32_t *bsplit = h.d_hb + 2 * nb1;
     hd.bsplit = bsplit;
+    hd.gptr = h.d_hb + 3 * nb1 - 1;
+    hd.gblk = hd.gptr + hd.grid + 1;
     int32_t *hx = (int32_t *)dev_alloc((size_t)(h.rows + 1) * 4);
     try {
         launch_fill_i32(hx + h.rows, 1, 0, s);
