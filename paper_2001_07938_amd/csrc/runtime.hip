@@ -458,8 +458,9 @@ static bool hot_possible(const CsrHandle &h)
 
 // Builds the hot-column copy of the matrix (see HotDesc).  Block bounds are
 // chosen on the host from row_ptr: a new block starts when the current one
-// has kHotRows rows or at least `target` entries (about six blocks per
-// workgroup).
+// has kHotRows rows or at least one workgroup's share of the entries (few,
+// large blocks cost the fewest barriers; the assignment below balances
+// them).
 static void build_hot(CsrHandle &h, hipStream_t s)
 {
     Context &c = ctx();
@@ -471,7 +472,7 @@ static void build_hot(CsrHandle &h, hipStream_t s)
     std::vector<int32_t> rp((size_t)h.rows + 1);
     HIPC(hipMemcpyAsync(rp.data(), h.d_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    const int64_t target = std::max<int64_t>(8192, h.nnz / ((int64_t)c.cu * 6));
+    const int64_t target = std::max<int64_t>(16384, h.nnz / (int64_t)c.cu);
     std::vector<int32_t> brow{0};
     int32_t start = 0;
     for (int32_t r = 1; r < h.rows; ++r)
