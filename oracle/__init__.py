@@ -9,13 +9,15 @@ C file, built with ``gcc -O2 -ffp-contract=off`` (see ``build``).
 
 Parity status of each function (what pins it, see ``tests/test_oracle_*.py``):
   spmv_csr / spmv_csr_f32 / spmv_abs : pinned (paper's 5x5 example, dense
-      matvec, exact rational arithmetic, identity/permutation, scipy CSR)
+      matvec, exact rational arithmetic, identity/permutation, scipy CSR;
+      the float32 |A||x| scale against scipy on the widened arrays)
   spmv_csr_par                       : pinned (bitwise equal to spmv_csr)
   dot / dot_abs                      : pinned (closed forms, fsum, Fraction)
   cg                                 : pinned (direct solve, k-eigenvalue
       finite termination, zero right-hand side, A-norm monotonicity)
   pagerank_step / pagerank           : pinned (mass identity, cycle fixed
-      point, star closed form)
+      point, star closed form, several steps on a cycle from a non-uniform
+      start against x_k = d^k P^k x0 + (1 - d^k)/N)
   bins / split_chunks / cols / validate : pinned (library sort/search special
       cases, invariants, crafted bad inputs)
   csr_to_jds / spmv_jds              : pinned (paper's JDS example)

@@ -43,6 +43,11 @@ MUTANTS = {
                    T_sol.test_cg_finite_termination_k_eigenvalues]),
     "pagerank_teleport": ("y[i] = d * s + tele;", "y[i] = d * s;",
                           [T_sol.test_pagerank_mass_identity]),
+    "pagerank_no_feedback": ("memcpy(x_inout, y, sizeof(double) * (size_t)rows);", "",
+                             [T_sol.test_pagerank_cycle_several_steps_closed_form]),
+    "abs_f32_drops_x": ("s += fabs((double)vals[k]) * fabs((double)x[col_idx[k]]);",
+                        "s += fabs((double)vals[k]);",
+                        [T_spmv.test_abs_scale_f32_is_the_widened_magnitude]),
     "bins_compare": ("len > upper[b]", "len >= upper[b]",
                      [T_an.test_bins_match_searchsorted_and_stable_sort]),
     "jds_perm_direction": ("perm[order[p]] = p;", "perm[p] = order[p];",

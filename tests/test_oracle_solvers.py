@@ -1,6 +1,7 @@
 """Pins for the oracle's conjugate gradient and PageRank: direct solves,
 finite termination, the zero right-hand side, A-norm monotonicity, PageRank
-mass identity, a cycle's fixed point and a star's closed form.  CPU only."""
+mass identity, a cycle's fixed point, the closed form of several steps on a
+cycle from a non-uniform start, and a star's closed form.  CPU only."""
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
@@ -86,3 +87,25 @@ def test_pagerank_cycle_fixed_point_and_star_closed_form():
     hub = 0.85 * (n - 1) * xf + 0.15 / n
     leaf = 0.85 * np.float64(np.float32(1.0 / (n - 1))) * xf + 0.15 / n
     assert abs(y[0] - hub) <= 1e-15 and np.allclose(y[1:], leaf, rtol=1e-15, atol=0)
+
+
+def test_pagerank_cycle_several_steps_closed_form():
+    """On the directed n-cycle u -> u+1 each step moves every value one
+    vertex on, so from any start x0 the k-th iterate is
+        x_k[v] = d^k x0[(v - k) mod n] + (1 - d^k) / n
+    (the teleport terms (1-d)/n summed over d^0 .. d^(k-1)).  A start that is
+    not the fixed point makes the result depend on k and on d, so an oracle
+    that does not feed each step's result into the next fails here."""
+    n = 61
+    C = gen.cycle_graph(n)
+    x0 = gen.vector(n, 44, lo=0.0, hi=1.0)
+    x0 = x0 / x0.sum()
+    for d in (0.5, 0.85, 0.99):
+        for k in (1, 2, 7, 20):
+            want = d ** k * np.roll(x0, k) + (1.0 - d ** k) / n
+            got = oracle.pagerank(C.row_ptr, C.col_idx, C.vals, x0, d, k)
+            assert np.allclose(got, want, rtol=1e-13, atol=0), (d, k)
+        # the step count matters from this start
+        one = oracle.pagerank(C.row_ptr, C.col_idx, C.vals, x0, d, 1)
+        two = oracle.pagerank(C.row_ptr, C.col_idx, C.vals, x0, d, 2)
+        assert not np.allclose(one, two)

@@ -149,3 +149,25 @@ def test_row_parallel_product_is_the_serial_one():
     yp = oracle.spmv_csr_par(A.row_ptr, A.col_idx, A.vals, x)
     assert np.array_equal(y, yp)
     assert oracle.threads() >= 1
+
+
+def test_abs_scale_f32_is_the_widened_magnitude():
+    """The float32 tolerance scale: sum_k |a_ik| |x_k| of the float32 data
+    widened to binary64, against the library product |A| |x| of the widened
+    arrays.  Products of two float32 values are exact in binary64, so the
+    two differ only by the rounding of the row sums."""
+    A = gen.ragged(500, 700, seed=33, max_len=120, empty_frac=0.1).astype(np.float32)
+    x = gen.vector(A.cols, 34, dtype=np.float32)
+    S = sp.csr_matrix((np.abs(A.vals.astype(np.float64)), A.col_idx, A.row_ptr),
+                      shape=(A.rows, A.cols))
+    want = S @ np.abs(x.astype(np.float64))
+    got = oracle.spmv_abs(A.row_ptr, A.col_idx, A.vals, x)
+    assert got.dtype == np.float64
+    lens = np.diff(A.row_ptr)
+    assert np.all(np.abs(got - want) <= 2.3e-16 * lens * want)
+    # a row with one entry holds that product exactly
+    one = np.nonzero(lens == 1)[0]
+    assert one.size
+    k = A.row_ptr[one]
+    assert np.array_equal(got[one], np.abs(A.vals[k].astype(np.float64)) *
+                          np.abs(x[A.col_idx[k]].astype(np.float64)))
