@@ -156,6 +156,24 @@ def rmat_pagerank(scale: int = 22, n_edges: int = 1 << 26,
     return _from_sorted_keys(nv, nv, dst, src, w, f"rmat{scale}")
 
 
+def relabel_by_degree(A: Csr) -> Csr:
+    """The same graph with vertices renumbered by decreasing number of
+    stored entries per column (most referenced column first, ties in index
+    order), rows and columns renumbered alike; values move with their
+    entries.  A structural relabelling only: no value is computed."""
+    n = A.rows
+    assert A.cols == n
+    deg = np.bincount(A.col_idx, minlength=n)
+    order = np.argsort(-deg, kind="stable")
+    newid = np.empty(n, dtype=np.int64)
+    newid[order] = np.arange(n, dtype=np.int64)
+    r = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))
+    key = (newid[r] << 32) | newid[A.col_idx]
+    o = np.argsort(key, kind="stable")
+    return _from_sorted_keys(n, n, newid[r][o], newid[A.col_idx][o], A.vals[o],
+                             A.name + "_bydeg")
+
+
 def stencil(k: int, points: int = 7) -> Csr:
     """3D Laplacian-style stencil on a k^3 grid with Dirichlet truncation.
     7-point: diagonal 6, neighbours -1.  27-point: diagonal 26, neighbours -1.

@@ -228,8 +228,16 @@ int lilac_spmv(lilac_csr_t h, const void *x, void *y, void *stream);
 int lilac_spmv_dot(lilac_csr_t h, const void *x, void *y, const void *w,
                    double *out, void *stream);
 
-/* out = sum a[i] b[i] with device a, b and a device result.  Async. */
-int lilac_dot_dev(int64_t n, const double *a, const double *b, double *out,
+/*
+ * out = sum a[i] b[i] (the dotproduct computation of section "Backtracking
+ * Search Algorithm") with device a, b of n elements of `dtype` (lilac_dtype)
+ * and a device result of the same dtype.  Products and the fixed two-level
+ * sum are binary64 (float32 data widened exactly); a float32 result is that
+ * total rounded once.  n == 0 stores 0.  The partial sums live in the
+ * library's scratch, so calls on different streams must not overlap.
+ * Async.  Errors: LILAC_ERR_ARG (n < 0, NULL, unknown dtype).
+ */
+int lilac_dot_dev(int64_t n, const void *a, const void *b, void *out, lilac_dtype dtype,
                   void *stream);
 
 /*
@@ -331,6 +339,25 @@ int lilac_csr64_destroy(lilac_csr64_t h);
 int lilac_spmv_jds(int rows, int max_len, const int *perm, const int *nzcnt,
                    const int *jd_ptr, const int *jd_col, const double *jd_val,
                    const double *x, double *y);
+
+/*
+ * CSR -> JDS of a handle's matrix, on the device (section "Sparse Matrix
+ * Variations in LiLAC-What", JDS paragraph and the JDS figure): rows in
+ * order of decreasing non-zero count, equal counts in ascending original
+ * order; perm[i] = new position of original row i; nzcnt[p] = count of the
+ * row at position p; diagonal j holds the j-th entry of every row that has
+ * one, in position order, from jd_ptr[j]; jd_ptr[max_len] = nnz.  The
+ * arrays are exactly what lilac_spmv_jds takes.
+ * *max_len (host) receives the longest row.  With jd_ptr == NULL only
+ * *max_len is computed (a size query).  Otherwise every output is device
+ * memory owned by the caller: perm[rows], nzcnt[rows] int, jd_ptr int with
+ * jd_ptr_len >= max_len + 1 entries, jd_col[nnz] int, jd_val[nnz] of the
+ * handle's dtype.  Integer work and copies only, so the result is exact.
+ * Runs on `stream` (NULL: the library's stream) and returns when done.
+ * Errors: LILAC_ERR_ARG (NULL, host outputs, jd_ptr too short).
+ */
+int lilac_csr_to_jds(lilac_csr_t h, int *perm, int *nzcnt, int *jd_ptr, int jd_ptr_len,
+                     int *jd_col, void *jd_val, int *max_len, void *stream);
 
 /*
  * Breadth-first search levels from `source` by repeated Boolean sparse

@@ -79,7 +79,7 @@ _SIGS = {
     "lilac_csr_set_layout": ([_P, _I], _I),
     "lilac_spmv": ([_P, _P, _P, _P], _I),
     "lilac_spmv_dot": ([_P, _P, _P, _P, _P, _P], _I),
-    "lilac_dot_dev": ([_I64, _P, _P, _P, _P], _I),
+    "lilac_dot_dev": ([_I64, _P, _P, _P, _I, _P], _I),
     "lilac_cg": ([_P, _P, _P, _I, ctypes.c_uint, _P, _P, _P], _I),
     "lilac_pagerank": ([_P, ctypes.c_float, _I, _P, _P], _I),
     "lilac_spmv_batched": ([_I, _P, _P, _P, _P], _I),
@@ -90,6 +90,7 @@ _SIGS = {
     "lilac_csr_tune": ([_P, _P], _I),
     "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
     "lilac_spmv_jds": ([_I, _I, _P, _P, _P, _P, _P, _P, _P], _I),
+    "lilac_csr_to_jds": ([_P, _P, _P, _P, _I, _P, _P, _P, _P], _I),
 }
 
 _lib = None
@@ -158,6 +159,14 @@ def _stream(stream) -> Optional[int]:
     return int(stream) or None
 
 
+def _elem_size(a) -> int:
+    if isinstance(a, torch.Tensor):
+        return a.element_size()
+    if isinstance(a, np.ndarray):
+        return a.itemsize
+    raise TypeError("pass dtype= with a raw pointer")
+
+
 def _as_i32(a):
     if isinstance(a, torch.Tensor):
         if a.dtype != torch.int32:
@@ -208,8 +217,11 @@ def lilac_dot_f32(n: int, a, b) -> float:
     return r
 
 
-def lilac_dot_dev(n: int, a, b, out, stream=None):
-    _check(lib().lilac_dot_dev(n, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
+def lilac_dot_dev(n: int, a, b, out, dtype: int = None, stream=None):
+    """out = a . b on the device; dtype defaults to out's element type."""
+    if dtype is None:
+        dtype = F32 if _elem_size(out) == 4 else F64
+    _check(lib().lilac_dot_dev(n, _ptr(a), _ptr(b), _ptr(out), dtype, _stream(stream)))
 
 
 def lilac_invalidate(ptr):
@@ -346,6 +358,30 @@ class Csr:
         _check(lib().lilac_bfs(self.handle, source, _ptr(level),
                                ctypes.addressof(n), _stream(stream)))
         return n.value
+
+    def to_jds(self, stream=None) -> dict:
+        """JDS arrays of the matrix as device tensors: perm, nzcnt, jd_ptr,
+        col_ind (int32) and val (the handle's dtype), plus max_len."""
+        ml = ctypes.c_int(0)
+        _check(lib().lilac_csr_to_jds(self.handle, None, None, None, 0, None, None,
+                                      ctypes.addressof(ml), _stream(stream)))
+        i32 = dict(dtype=torch.int32, device="cuda")
+        out = dict(perm=torch.empty(max(self.rows, 1), **i32),
+                   nzcnt=torch.empty(max(self.rows, 1), **i32),
+                   jd_ptr=torch.empty(ml.value + 1, **i32),
+                   col_ind=torch.empty(max(self.nnz, 1), **i32),
+                   val=torch.empty(max(self.nnz, 1), dtype=self.torch_dtype,
+                                   device="cuda"))
+        _check(lib().lilac_csr_to_jds(self.handle, _ptr(out["perm"]), _ptr(out["nzcnt"]),
+                                      _ptr(out["jd_ptr"]), ml.value + 1,
+                                      _ptr(out["col_ind"]), _ptr(out["val"]),
+                                      ctypes.addressof(ml), _stream(stream)))
+        for k in ("perm", "nzcnt"):
+            out[k] = out[k][:self.rows]
+        for k in ("col_ind", "val"):
+            out[k] = out[k][:self.nnz]
+        out["max_len"] = ml.value
+        return out
 
     def tune(self) -> float:
         us = ctypes.c_double(0.0)

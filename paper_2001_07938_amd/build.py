@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblilac.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip", "jds.hip"]
 CXX_SOURCES = ["marshal.cpp"]
 
 ARCH = os.environ.get("LILAC_ARCH", "gfx950")

@@ -1959,13 +1959,16 @@ __global__ __launch_bounds__(kBlock) void k_dot_parts(
         part[blockIdx.x] = t;
 }
 
+// The total of the partials, stored as TOut: a float32 result is the
+// binary64 total rounded once.
+template <typename TOut>
 __global__ __launch_bounds__(1024) void k_sum_parts(
-    const double *__restrict__ part, int32_t n, double *__restrict__ out)
+    const double *__restrict__ part, int32_t n, TOut *__restrict__ out)
 {
     __shared__ double lds[16];
     const double t = sum_parts_1024(part, n, lds);
     if (threadIdx.x == 0)
-        *out = t;
+        *out = (TOut)t;
 }
 
 template <typename T>
@@ -2699,7 +2702,15 @@ void launch_dot_parts_f32(int64_t n, const float *a, const float *b,
 void launch_sum_parts(const double *part, int32_t nparts, double *out,
                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, part, nparts,
+    hipLaunchKernelGGL(k_sum_parts<double>, dim3(1), dim3(1024), 0, s, part, nparts,
+                       out);
+    check_launch("k_sum_parts");
+}
+
+void launch_sum_parts_f32(const double *part, int32_t nparts, float *out,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_parts<float>, dim3(1), dim3(1024), 0, s, part, nparts,
                        out);
     check_launch("k_sum_parts");
 }

@@ -254,6 +254,21 @@ void hip_check(hipError_t e, const char *what, const char *file, int line);
 #define HIPC(x) ::lilac::hip_check((x), #x, __FILE__, __LINE__)
 
 // ---- device memory with a byte budget -----------------------------------
+// Every device allocation of the library goes through dev_alloc, which
+// charges it to the library-wide budget (LILAC_HBM_BUDGET) and, when the
+// calling thread has an account set, to that account and each of its
+// parents; an allocation that would take any of them past its limit fails
+// with LILAC_ERR_BUDGET and allocates nothing.  dev_free returns the bytes
+// to the accounts charged at allocation, whichever thread frees.  Accounts
+// are read and changed only under lib_mutex().
+struct Account {
+    int64_t limit = INT64_MAX;
+    int64_t in_use = 0;
+    int64_t peak = 0;
+    Account *parent = nullptr;
+};
+// The calling thread's current account (nullptr: none).
+Account *&thread_account();
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
 int device_cu_count();
@@ -416,6 +431,8 @@ void launch_invert_perm(int32_t rows, const int32_t *perm, int32_t *iperm,
                         hipStream_t s);
 void launch_sum_parts(const double *part, int32_t nparts, double *out,
                       hipStream_t s);
+void launch_sum_parts_f32(const double *part, int32_t nparts, float *out,
+                          hipStream_t s);
 void launch_copy_f64(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_copy_f32(int64_t n, const float *src, float *dst, hipStream_t s);
 
@@ -452,6 +469,13 @@ int lib_device();
 CsrHandle *create_handle(int rows, int cols, int64_t nnz, const int32_t *rp,
                          const int32_t *col, const void *vals, lilac_dtype dt,
                          unsigned flags, bool inputs_ready = false);
+// A handle that takes over device arrays allocated with dev_alloc and
+// already holding the matrix: rp[rows+1], col and vals with room for
+// padded_nnz(nnz) entries.  They belong to the handle from the call on
+// (freed with it, also when the call fails).  Blocking.
+int64_t padded_nnz(int64_t nnz);
+CsrHandle *create_handle_adopt(int rows, int cols, int64_t nnz, int32_t *rp,
+                               int32_t *col, void *vals, lilac_dtype dt);
 void destroy_handle(CsrHandle *h);
 MatDesc make_desc(const CsrHandle &h, const void *x, void *y, const void *w,
                   double *chunk_part);
@@ -460,5 +484,15 @@ void spmv_enqueue(const CsrHandle &h, const void *x, void *y, const Epi &epi,
 void run_cg(CsrHandle &h, const double *b, double *x, int iters,
             unsigned flags, hipStream_t s, double *rho_out, int *iters_done);
 int tile_grid(lilac_dtype dt);   // persistent workgroups for a grouped launch
+
+// ---- CSR -> JDS (jds.hip) ---------------------------------------------------
+// Longest row of the handle's matrix (d_tmp: one device int of scratch).
+// Blocking.
+int32_t jds_max_len(const CsrHandle &h, int32_t *d_tmp, hipStream_t s);
+// The JDS arrays of the handle's matrix into device outputs perm[rows],
+// nzcnt[rows], jd_ptr[max_len+1], jd_col[nnz], jd_val[nnz] (handle's dtype).
+// Blocking.
+void jds_convert(const CsrHandle &h, int32_t max_len, int32_t *perm, int32_t *nzcnt,
+                 int32_t *jd_ptr, int32_t *jd_col, void *jd_val, hipStream_t s);
 
 }  // namespace lilac

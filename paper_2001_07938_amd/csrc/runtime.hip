@@ -59,7 +59,11 @@ struct Context {
     hipStream_t cap = nullptr;      // stream used only for graph capture
     int64_t budget = INT64_MAX;
     int64_t in_use = 0;
-    std::unordered_map<void *, size_t> sizes;
+    struct Charge {
+        size_t bytes;
+        Account *acct;
+    };
+    std::unordered_map<void *, Charge> sizes;
     // scratch for the raw calls
     void *x_buf = nullptr, *y_buf = nullptr;
     size_t x_cap = 0, y_cap = 0;
@@ -152,8 +156,15 @@ static Context &ctx()
 int device_cu_count() { return ctx().cu; }
 int lib_device() { return ctx().device; }
 
+Account *&thread_account()
+{
+    static thread_local Account *a = nullptr;
+    return a;
+}
+
 void *dev_alloc(size_t bytes)
 {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     Context &c = *g_ctx;
     if (bytes == 0)
         bytes = 256;
@@ -163,6 +174,13 @@ void *dev_alloc(size_t bytes)
                                    " bytes exceeds the HBM budget (" +
                                    std::to_string(c.in_use) + " of " +
                                    std::to_string(c.budget) + " in use)");
+    Account *acct = thread_account();
+    for (Account *a = acct; a; a = a->parent)
+        if (a->in_use + (int64_t)bytes > a->limit)
+            fail(LILAC_ERR_BUDGET, "allocation of " + std::to_string(bytes) +
+                                       " bytes exceeds an account's limit (" +
+                                       std::to_string(a->in_use) + " of " +
+                                       std::to_string(a->limit) + " in use)");
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
@@ -170,8 +188,12 @@ void *dev_alloc(size_t bytes)
         fail(LILAC_ERR_OOM, "hipMalloc of " + std::to_string(bytes) +
                                 " bytes failed: " + hipGetErrorString(e));
     }
-    c.sizes[p] = bytes;
+    c.sizes[p] = Context::Charge{bytes, acct};
     c.in_use += (int64_t)bytes;
+    for (Account *a = acct; a; a = a->parent) {
+        a->in_use += (int64_t)bytes;
+        a->peak = std::max(a->peak, a->in_use);
+    }
     return p;
 }
 
@@ -179,10 +201,13 @@ void dev_free(void *p)
 {
     if (!p || !g_ctx)
         return;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     Context &c = *g_ctx;
     auto it = c.sizes.find(p);
     if (it != c.sizes.end()) {
-        c.in_use -= (int64_t)it->second;
+        c.in_use -= (int64_t)it->second.bytes;
+        for (Account *a = it->second.acct; a; a = a->parent)
+            a->in_use -= (int64_t)it->second.bytes;
         c.sizes.erase(it);
     }
     (void)hipFree(p);  // waits for outstanding work on the device
@@ -793,21 +818,30 @@ static void upload_values(CsrHandle &h, const void *vals, hipStream_t s)
     copy_in(h.d_vals, vals, (size_t)h.nnz * dtype_size(h.dt), s);
 }
 
+int64_t padded_nnz(int64_t nnz)
+{
+    return ((nnz + kPad - 1) / kPad) * kPad + kPad;
+}
+
+// rp/col/vals == the handle's own arrays (adopted): nothing to copy.
 static void construct(CsrHandle &h, int cols_given, const int32_t *rp,
                       const int32_t *col, const void *vals, hipStream_t s)
 {
     Context &c = ctx();
     const size_t vs = dtype_size(h.dt);
-    const int64_t npad = ((h.nnz + kPad - 1) / kPad) * kPad + kPad;
+    const int64_t npad = padded_nnz(h.nnz);
     if (!h.d_row_ptr) {
         h.d_row_ptr = (int32_t *)dev_alloc((size_t)(h.rows + 1) * 4);
         h.d_col = (int32_t *)dev_alloc((size_t)npad * 4);
         h.d_vals = dev_alloc((size_t)npad * vs);
     }
     h.dev_bytes = (int64_t)(h.rows + 1) * 4 + npad * (4 + (int64_t)vs);
-    copy_in(h.d_row_ptr, rp, (size_t)(h.rows + 1) * 4, s);
-    copy_in(h.d_col, col, (size_t)h.nnz * 4, s);
-    upload_values(h, vals, s);
+    if (rp != h.d_row_ptr)
+        copy_in(h.d_row_ptr, rp, (size_t)(h.rows + 1) * 4, s);
+    if (col != h.d_col)
+        copy_in(h.d_col, col, (size_t)h.nnz * 4, s);
+    if (vals != h.d_vals)
+        upload_values(h, vals, s);
     // padding past nnz is read (and discarded) by nothing, but keep it defined
     launch_fill_i32(h.d_col + h.nnz, npad - h.nnz, 0, s);
     launch_fill_bytes_zero((char *)h.d_vals + h.nnz * vs, (npad - h.nnz) * vs, s);
@@ -876,6 +910,31 @@ CsrHandle *create_handle(int rows, int cols, int64_t nnz,
         h->h_row_ptr = rp;
         h->h_col = col;
         h->h_vals = vals;
+    }
+    return h;
+}
+
+CsrHandle *create_handle_adopt(int rows, int cols, int64_t nnz, int32_t *rp,
+                               int32_t *col, void *vals, lilac_dtype dt)
+{
+    auto *h = new CsrHandle();
+    h->d_row_ptr = rp;
+    h->d_col = col;
+    h->d_vals = vals;
+    h->rows = rows;
+    h->nnz = nnz;
+    h->dt = dt;
+    h->cols_given = cols < -1 ? -1 : cols;
+    h->plan = default_plan();
+    try {
+        if (rows < 0 || nnz < 0 || nnz > (int64_t)INT32_MAX - 8192 || !rp || !col || !vals)
+            fail(LILAC_ERR_ARG, "bad adopted arrays");
+        if (dt != LILAC_F64 && dt != LILAC_F32)
+            fail(LILAC_ERR_ARG, "unknown dtype");
+        construct(*h, h->cols_given, rp, col, vals, ctx().stream);
+    } catch (...) {
+        destroy_handle(h);
+        throw;
     }
     return h;
 }
@@ -2288,15 +2347,17 @@ int lilac_spmv_dot(lilac_csr_t hh, const void *x, void *y, const void *w,
     });
 }
 
-int lilac_dot_dev(int64_t n, const double *a, const double *b, double *out,
+int lilac_dot_dev(int64_t n, const void *a, const void *b, void *out, lilac_dtype dtype,
                   void *stream)
 {
     return guard([&] {
         if (n < 0 || !out)
             fail(LILAC_ERR_ARG, "bad argument");
+        if (dtype != LILAC_F64 && dtype != LILAC_F32)
+            fail(LILAC_ERR_ARG, "unknown dtype");
         hipStream_t s = pick_stream(stream);
         if (n == 0) {
-            launch_fill_bytes_zero(out, 8, s);
+            launch_fill_bytes_zero(out, dtype == LILAC_F32 ? 4 : 8, s);
             return;
         }
         if (!a || !b)
@@ -2305,8 +2366,13 @@ int lilac_dot_dev(int64_t n, const double *a, const double *b, double *out,
         const int32_t np = blas1_parts(n);
         // partials in the library's scratch: calls on different streams
         // must not overlap
-        launch_dot_parts(n, a, b, c.dot_part, np, s);
-        launch_sum_parts(c.dot_part, np, out, s);
+        if (dtype == LILAC_F32) {
+            launch_dot_parts_f32(n, (const float *)a, (const float *)b, c.dot_part, np, s);
+            launch_sum_parts_f32(c.dot_part, np, (float *)out, s);
+        } else {
+            launch_dot_parts(n, (const double *)a, (const double *)b, c.dot_part, np, s);
+            launch_sum_parts(c.dot_part, np, (double *)out, s);
+        }
     });
 }
 
@@ -2606,6 +2672,34 @@ int lilac_spmv_jds(int rows, int max_len, const int *perm, const int *nzcnt,
         }
         for (void *d : tmp)
             dev_free(d);
+    });
+}
+
+int lilac_csr_to_jds(lilac_csr_t hh, int *perm, int *nzcnt, int *jd_ptr, int jd_ptr_len,
+                     int *jd_col, void *jd_val, int *max_len, void *stream)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h || !max_len)
+            fail(LILAC_ERR_ARG, "NULL handle or max_len");
+        Context &c = ctx();
+        hipStream_t s = stream ? (hipStream_t)stream : c.stream;
+        refresh(*h, s);
+        const int32_t ml = jds_max_len(*h, c.total, s);
+        *max_len = ml;
+        if (!jd_ptr)
+            return;  // size query
+        if (jd_ptr_len < ml + 1)
+            fail(LILAC_ERR_ARG, "jd_ptr holds fewer than max_len + 1 entries");
+        if (h->rows > 0 && (!perm || !nzcnt))
+            fail(LILAC_ERR_ARG, "NULL perm or nzcnt");
+        if (h->nnz > 0 && (!jd_col || !jd_val))
+            fail(LILAC_ERR_ARG, "NULL jd_col or jd_val");
+        for (const void *p : {(const void *)perm, (const void *)nzcnt, (const void *)jd_ptr,
+                              (const void *)jd_col, (const void *)jd_val})
+            if (p && !is_device_ptr(p))
+                fail(LILAC_ERR_ARG, "JDS outputs must be device memory");
+        jds_convert(*h, ml, perm, nzcnt, jd_ptr, jd_col, jd_val, s);
     });
 }
 

@@ -245,6 +245,8 @@ def test_dot_raw_and_device():
             out = torch.empty(1, dtype=torch.float64, device=DEV)
             L.lilac_dot_dev(n, ad, bd, out)
             assert _host(out)[0] == L.lilac_dot(n, ad, bd)
+            L.lilac_dot_dev(n, ad, bd, out, dtype=L.F64)
+            assert _host(out)[0] == L.lilac_dot(n, ad, bd)
     assert L.lilac_dot(1 << 20, np.ones(1 << 20), np.ones(1 << 20)) == float(1 << 20)
 
 
@@ -259,6 +261,11 @@ def test_dot_f32_raw_host_and_device():
         assert abs(got - ref) <= TOL_F32 * (mag + abs(ref))
         if n:
             assert L.lilac_dot_f32(n, _dev(a), _dev(b)) == got
+        # the device-resident form: float32 result, same single rounding
+        out = torch.full((1,), 7.0, dtype=torch.float32, device=DEV)
+        L.lilac_dot_dev(n, _dev(a) if n else None, _dev(b) if n else None, out)
+        assert _host(out)[0] == np.float32(got)
+        assert abs(float(_host(out)[0]) - ref) <= TOL_F32 * (mag + abs(ref))
     ones = np.ones(1 << 20, dtype=np.float32)
     assert L.lilac_dot_f32(1 << 20, ones, ones) == float(1 << 20)
 
@@ -388,6 +395,11 @@ HOT_MATS = {
     "stencil27": lambda: gen.stencil(12, 27),
     "cols_2p22": lambda: gen.random_rows(5000, 1, 20, seed=10, cols=1 << 22),
     "cols_one": lambda: gen.random_rows(3000, 1, 1, seed=11, cols=1),
+    # 2^20 rows cut into blocks of at most 2048 rows: at least 512 blocks, so
+    # every workgroup of the persistent grid (one per CU) takes two or more
+    # blocks and runs the code that moves from one block to the next
+    "rmat20_by_degree": lambda: gen.relabel_by_degree(
+        gen.rmat_pagerank(20, 1 << 24, seed=14)).astype(np.float64),
 }
 
 
