@@ -364,6 +364,16 @@ class MatrixSpec:
         return random_rows(self.n, 5, 60, seed=self.seed)
 
 
+@dataclasses.dataclass
+class SpdSpec:
+    n: int = 150_000
+    half_per_row: int = 120
+    seed: int = BASE_SEED + 2
+
+    def build(self) -> Csr:
+        return spd_random(self.n, self.half_per_row, self.seed)
+
+
 def batch_specs(count: int = 512, n_lo: int = 1000, n_hi: int = 200_000,
                 seed: int = BASE_SEED + 4) -> List[MatrixSpec]:
     """Sizes log-uniform in [n_lo, n_hi]; kinds cycle through 7-point,

@@ -288,6 +288,11 @@ int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
  * time of one product with the chosen plan.
  */
 int lilac_csr_tune(lilac_csr_t h, double *best_us);
+/* The shape class under which lilac_csr_tune records and looks up plans
+ * (dtype, log2 of rows, twice log2 of the mean row length, row class of
+ * the longest row), as a NUL-terminated string into buf[cap].
+ * LILAC_ERR_ARG if it does not fit. */
+int lilac_csr_tune_class(lilac_csr_t h, char *buf, int cap);
 
 /* ---- 64-bit row offsets ------------------------------------------------ */
 
@@ -413,7 +418,13 @@ typedef struct {
     double wall_s;       /* first arrival -> last completion */
     double req_per_s, solves_per_s;
     double gbytes_per_s; /* credited algorithmic bytes of the work done / wall */
-    int64_t uploads, evictions, ticks, peak_device_bytes;
+    int64_t uploads, evictions, ticks;
+    int64_t peak_device_bytes;    /* highest device bytes the server held (its
+                                     allocator account: matrices, slots,
+                                     tables), since creation or the last reset */
+    int64_t device_bytes;         /* device bytes it holds now */
+    int64_t planned_peak_bytes;   /* highest planned bytes (resident charges +
+                                     upload reserves + slots + tables) */
 } lilac_server_stats;
 
 int lilac_server_create(lilac_server_t *s, const lilac_server_config *cfg);

@@ -88,6 +88,7 @@ _SIGS = {
     "lilac_csr64_info": ([_P, _P, _P, _P, _P], _I),
     "lilac_csr64_destroy": ([_P], _I),
     "lilac_csr_tune": ([_P, _P], _I),
+    "lilac_csr_tune_class": ([_P, ctypes.c_char_p, _I], _I),
     "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
     "lilac_spmv_jds": ([_I, _I, _P, _P, _P, _P, _P, _P, _P], _I),
     "lilac_csr_to_jds": ([_P, _P, _P, _P, _I, _P, _P, _P, _P], _I),
@@ -383,6 +384,11 @@ class Csr:
         out["max_len"] = ml.value
         return out
 
+    def tune_class(self) -> str:
+        buf = ctypes.create_string_buffer(96)
+        _check(lib().lilac_csr_tune_class(self.handle, buf, 96))
+        return buf.value.decode()
+
     def tune(self) -> float:
         us = ctypes.c_double(0.0)
         _check(lib().lilac_csr_tune(self.handle, ctypes.addressof(us)))
@@ -483,7 +489,8 @@ class ServerStats(ctypes.Structure):
                 ("solves_per_s", ctypes.c_double),
                 ("gbytes_per_s", ctypes.c_double), ("uploads", ctypes.c_int64),
                 ("evictions", ctypes.c_int64), ("ticks", ctypes.c_int64),
-                ("peak_device_bytes", ctypes.c_int64)]
+                ("peak_device_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("planned_peak_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liblilac.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip", "jds.hip"]
-CXX_SOURCES = ["marshal.cpp"]
+CXX_SOURCES = ["marshal.cpp", "serve_core.cpp"]
 
 ARCH = os.environ.get("LILAC_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1922,6 +1922,14 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *__restrict__ p,
         p[i] = v;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_f64(double *__restrict__ p, int64_t n,
+                                                     double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_zero_bytes(
     unsigned char *__restrict__ p, int64_t n)
 {
@@ -2184,6 +2192,15 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBlock, 4096)),
                        dim3(kBlock), 0, s, p, n, v);
     check_launch("k_fill_i32");
+}
+
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, p,
+                       n, v);
+    check_launch("k_fill_f64");
 }
 
 void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s)

@@ -185,6 +185,7 @@ struct CsrHandle {
     int32_t rows = 0, cols = 0;
     int32_t cols_given = -1;   // as passed at creation (-1: derived)
     int64_t nnz = 0;
+    int32_t max_len = 0;         // longest row (set when constructed)
     lilac_dtype dt = LILAC_F64;
     unsigned flags = 0;
     // device copies
@@ -276,6 +277,7 @@ int device_cu_count();
 // ---- kernel launchers (kernels.hip) --------------------------------------
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s);
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 void launch_validate(int32_t rows, const int32_t *rp, int64_t nnz,
                      const int32_t *col, int32_t cols_given, int32_t *status,
                      hipStream_t s);
@@ -483,6 +485,8 @@ void spmv_enqueue(const CsrHandle &h, const void *x, void *y, const Epi &epi,
                   const void *w, bool dot, hipStream_t s);
 void run_cg(CsrHandle &h, const double *b, double *x, int iters,
             unsigned flags, hipStream_t s, double *rho_out, int *iters_done);
+// Allocates the handle's CG state now (otherwise done on the first solve).
+void handle_cg_prepare(CsrHandle &h);
 int tile_grid(lilac_dtype dt);   // persistent workgroups for a grouped launch
 
 // ---- CSR -> JDS (jds.hip) ---------------------------------------------------

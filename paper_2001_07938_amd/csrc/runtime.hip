@@ -861,6 +861,7 @@ static void construct(CsrHandle &h, int cols_given, const int32_t *rp,
         fail(LILAC_ERR_CSR, "invalid CSR:" + why);
     }
     h.cols = cols_given >= 0 ? cols_given : st[1] + 1;
+    h.max_len = jds_max_len(h, c.total, s);
     h.line_ratio = -1.0;  // measured again for the new structure
     Plan tuned;
     if (tune_cache_lookup(h, tuned))
@@ -1165,7 +1166,7 @@ static int marshal_mode()
     return 0;
 }
 
-static void *scratch(void *&buf, size_t &cap, size_t bytes)
+static void *grow_buffer(void *&buf, size_t &cap, size_t bytes)
 {
     if (bytes > cap) {
         dev_free(buf);
@@ -1242,12 +1243,12 @@ static void raw_spmv(int rows, const int32_t *rp, const int32_t *col,
     if (h->cols > 0 && !x)
         fail(LILAC_ERR_ARG, "x is NULL");
     if (x && !is_device_ptr(x)) {
-        void *b = scratch(c.x_buf, c.x_cap, (size_t)h->cols * vs);
+        void *b = grow_buffer(c.x_buf, c.x_cap, (size_t)h->cols * vs);
         HIPC(hipMemcpyAsync(b, x, (size_t)h->cols * vs, hipMemcpyHostToDevice, s));
         dx = b;
     }
     const bool y_dev = is_device_ptr(y);
-    void *dy = y_dev ? y : scratch(c.y_buf, c.y_cap, (size_t)rows * vs);
+    void *dy = y_dev ? y : grow_buffer(c.y_buf, c.y_cap, (size_t)rows * vs);
     spmv_enqueue(*h, dx, dy, epi_none(), nullptr, false, s);
     if (!y_dev)
         HIPC(hipMemcpyAsync(y, dy, (size_t)rows * vs, hipMemcpyDeviceToHost, s));
@@ -1345,23 +1346,33 @@ static void cg_prepare(CsrHandle &h)
     h.cg = st;
 }
 
+void handle_cg_prepare(CsrHandle &h) { cg_prepare(h); }
+
 // One whole solve: initialisation, then `iters` iterations of three kernels
 // (product with fused p.q partials; alpha and the x/r update with r.r
 // partials; beta and the direction update).  Scalars never leave the device.
+// r, p, q hold rows doubles, part 2 * kDotParts, sc one CgScalars; the
+// initialisation writes everything later launches read.
+static void cg_enqueue_state(const CsrHandle &h, const double *b, double *x, int iters,
+                             double *r, double *p, double *q, double *part,
+                             CgScalars *sc, hipStream_t s)
+{
+    const int64_t n = h.rows;
+    const int32_t np = blas1_parts(n);
+    const int32_t ndot = h.grid + h.fin_blocks;
+    launch_cg_init(n, b, x, r, p, part, np, sc, s);
+    for (int it = 0; it < iters; ++it) {
+        spmv_enqueue(h, p, q, epi_none(), p, true, s);
+        launch_cg_update(n, sc, p, q, x, r, h.d_dot_part, ndot, part, np, it & 1, s);
+        launch_cg_xpay(n, sc, r, p, part, np, it & 1, s);
+    }
+}
+
 static void cg_enqueue(const CsrHandle &h, const double *b, double *x,
                        int iters, hipStream_t s)
 {
     const CgState &st = *h.cg;
-    const int64_t n = h.rows;
-    const int32_t np = blas1_parts(n);
-    const int32_t ndot = h.grid + h.fin_blocks;
-    launch_cg_init(n, b, x, st.r, st.p, st.part, np, st.sc, s);
-    for (int it = 0; it < iters; ++it) {
-        spmv_enqueue(h, st.p, st.q, epi_none(), st.p, true, s);
-        launch_cg_update(n, st.sc, st.p, st.q, x, st.r, h.d_dot_part, ndot,
-                         st.part, np, it & 1, s);
-        launch_cg_xpay(n, st.sc, st.r, st.p, st.part, np, it & 1, s);
-    }
+    cg_enqueue_state(h, b, x, iters, st.r, st.p, st.q, st.part, st.sc, s);
 }
 
 template <typename Enq>
@@ -1832,24 +1843,21 @@ static void run_batched(int count, const lilac_csr_t *hs, const void *const *xs,
 
 // ================================================================ tuning
 
-// Shape class of a matrix: dtype, log2 of rows, log2 of the mean row length
-// and of the longest-to-mean ratio.  Handles of one class share a plan.
+// Shape class of a matrix: dtype, log2 of rows, twice log2 of the mean row
+// length, and the row class of its longest row under the default bounds
+// (known before the analysis, so a new handle finds its class's plan).
+// Handles of one class share a plan.
 static std::string tune_key(const CsrHandle &h)
 {
     const double mean = h.rows ? (double)h.nnz / h.rows : 0.0;
-    int32_t maxlen = 0;
-    if (!h.bin_off.empty()) {
-        for (int c = NCLASS - 1; c >= 0; --c)
-            if (h.bin_off[c + 1] > h.bin_off[c]) {
-                maxlen = h.plan.upper[c];
-                break;
-            }
-    }
-    (void)maxlen;
+    const Plan d = default_plan();
+    int top = 0;
+    while (top < NCLASS - 1 && h.max_len > d.upper[top])
+        ++top;
     char buf[96];
-    std::snprintf(buf, sizeof(buf), "%s/r%d/m%d", h.dt == LILAC_F32 ? "f32" : "f64",
+    std::snprintf(buf, sizeof(buf), "%s/r%d/m%d/c%d", h.dt == LILAC_F32 ? "f32" : "f64",
                   (int)std::lround(std::log2(std::max(1, h.rows))),
-                  (int)std::lround(2.0 * std::log2(std::max(1.0, mean))));
+                  (int)std::lround(2.0 * std::log2(std::max(1.0, mean))), top);
     return buf;
 }
 
@@ -2700,6 +2708,19 @@ int lilac_csr_to_jds(lilac_csr_t hh, int *perm, int *nzcnt, int *jd_ptr, int jd_
             if (p && !is_device_ptr(p))
                 fail(LILAC_ERR_ARG, "JDS outputs must be device memory");
         jds_convert(*h, ml, perm, nzcnt, jd_ptr, jd_col, jd_val, s);
+    });
+}
+
+int lilac_csr_tune_class(lilac_csr_t hh, char *buf, int cap)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h || !buf || cap < 1)
+            fail(LILAC_ERR_ARG, "NULL handle or buffer");
+        const std::string k = tune_key(*h);
+        if ((int)k.size() >= cap)
+            fail(LILAC_ERR_ARG, "buffer too small");
+        std::memcpy(buf, k.c_str(), k.size() + 1);
     });
 }
 

@@ -121,6 +121,8 @@ class Core {
     bool step();
     // Waits (real time) until a request or an upload result arrives.
     void wait_for_work(int64_t max_ns);
+    // Wakes a scheduler blocked in wait_for_work.
+    void wake();
     // Fails what has not started, finishes what runs.
     void shutdown();
     // Marks the server failed after an executor error: every outstanding
@@ -172,6 +174,7 @@ class Core {
     void complete(int tick);
     void collect_uploads();
     void take_incoming();
+    void bump_peak();
 
     Executor &ex_;
     Limits lim_;
@@ -201,6 +204,7 @@ class Core {
     int64_t t_first_ = 0, t_last_ = 0;
     std::string err_;
     bool dead_ = false;
+    int64_t peak_pub_ = 0;   // peak_ as the client side sees it
     std::deque<Done> up_done_;
 };
 

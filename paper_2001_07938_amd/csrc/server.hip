@@ -1,18 +1,23 @@
 // Request server: continuous batching of SpMV and CG-solve requests over a
 // pool of device-resident matrices.
 //
-// A scheduler thread runs "ticks".  Each tick admits waiting requests whose
-// matrix is resident (while slots and the HBM budget allow), then issues ONE
-// grouped product over every active request (y = A x for SpMV requests,
-// q = A p for the next iteration of every active CG request) followed by
-// three batched kernels that advance every CG by one iteration.  Requests
-// that arrive while a tick runs join at the next tick; a CG request leaves
-// after its last iteration, an SpMV request after its tick.  Uploads of
-// matrices that are not resident run on a separate thread and stream, so
-// they overlap with the ticks; least recently used idle matrices are evicted
-// when the pool or the budget is full.  Every per-request reduction has a
-// shape fixed by that request's matrix (its own tile list, its own number of
-// CG workgroups), so a result does not depend on what else is in the batch.
+// The scheduling (admission against the HBM budget, the resident pool and
+// its LRU-2 eviction, request slots, batching into ticks, statistics) is the
+// device-free serve::Core (serve_core.h).  This file is its executor on
+// the GPU:
+//  - uploads run on two threads with a stream each: the CSR arrays go from
+//    pinned host memory straight into the device arrays the matrix handle
+//    then takes over, and the handle's analysis and layout build follow;
+//  - every device byte a matrix holds is charged to an allocator account of
+//    its own whose limit is the upload's reserve, under the server's account
+//    whose limit is the budget, so the budget is a hard bound, the reserve
+//    is checked, and what a resident matrix holds is known exactly;
+//  - a tick is ONE grouped product over every active request (y = A x for
+//    SpMV requests, q = A p for the next iteration of every active CG
+//    request; row-class tiles, column panels and band blocks each in one
+//    launch), then three batched kernels that advance every CG by one
+//    iteration.  Each request's reductions have shapes fixed by its own
+//    matrix, so a result does not depend on what it was batched with.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -20,10 +25,10 @@
 #include <cstring>
 #include <deque>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "lilac_internal.h"
+#include "serve_core.h"
 
 namespace lilac {
 namespace {
@@ -37,103 +42,277 @@ int64_t now_ns()
         .count();
 }
 
+constexpr int kUploadThreads = 2;
+
 struct SMatrix {
     int rows = 0, cols = 0;
     int64_t nnz = 0;
-    const int32_t *rp = nullptr, *col = nullptr;
+    const int32_t *rp = nullptr, *col = nullptr;   // pinned host copy
     const double *vals = nullptr;
-    CsrHandle *h = nullptr;
-    enum State { OFF, UPLOADING, READY } st = OFF;
-    int64_t bytes = 0;         // device bytes while resident
-    uint64_t last_use = 0;
-    int refs = 0;              // admitted requests using it
-    double *vin = nullptr, *vout = nullptr;  // trace-mode vectors
-    int64_t spmv_bytes = 0;    // credited bytes of one product
-    void *pin = nullptr;       // pinned host copy holding rp, col, vals
+    void *pin = nullptr;
+    CsrHandle *h = nullptr;                 // set by the upload thread
+    double *vin = nullptr;                  // trace-mode operand (all ones)
+    Account acct;                           // every device byte it holds
+    int64_t nchunks = 0;                    // of the resident handle
 };
 
-// Per-slot device workspace of an admitted request.
+// Per-slot device workspace of an admitted request: CG vectors, its own
+// output vector for trace-mode requests, partials, chunk sums.
 struct Slot {
-    int64_t cap_n = 0, cap_chunks = 0;
-    double *r = nullptr, *p = nullptr, *q = nullptr;
+    int64_t cap_chunks = 0;
+    double *r = nullptr, *p = nullptr, *q = nullptr, *x = nullptr;
     double *pq = nullptr, *rr = nullptr;  // kBlock and 2*kBlock partials
     int32_t *done = nullptr;
     double *chunk = nullptr;
-    int64_t bytes = 0;
 };
 
-struct Req {
-    uint64_t ticket = 0;
-    int kind = 0, mid = 0, iters = 0;
-    const double *in = nullptr;
-    double *out = nullptr;
-    int64_t t_arr = 0;
-    int iter = 0;          // CG iterations already enqueued
-    int slot = -1;
-    bool failed = false;
-};
-
-struct Tick {
+// Tables of one tick, in pinned memory and on the device.  Sized once for
+// max_active requests.
+struct TickBuf {
     hipEvent_t ev = nullptr;
-    std::vector<Req *> finishing;   // requests whose last work is in it
-    bool pending = false;
-    // pinned staging and device copies of the tick's tables
     char *host = nullptr, *dev = nullptr;
     size_t cap = 0;
 };
 
+size_t per_request_table_bytes()
+{
+    return sizeof(MatDesc) + 4 + 2 * sizeof(CgSeg) + sizeof(PanelDesc) +
+           sizeof(PanelIO) + 4 + sizeof(BandDesc) + sizeof(PanelIO) + 4;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Server;
+
+class HipExec : public serve::Executor {
+  public:
+    explicit HipExec(Server *s) : S(s) {}
+    int64_t now_ns() override { return lilac::now_ns(); }
+    int64_t upload_reserve(int mid) override;
+    void start_upload(int mid) override;
+    void evict(int mid) override;
+    int64_t slot_need(int slot, int mid) override;
+    void prepare_slot(int slot, int mid) override;
+    void release_slot(int slot) override;
+    void launch_tick(int tick, const std::vector<serve::Request *> &reqs) override;
+    void wait_tick(int tick) override;
+    void run_one(serve::Request *r) override;
+
+  private:
+    Server *S;
+};
+
 struct Server {
-    lilac_server_config cfg;
-    hipStream_t stream = nullptr, up_stream = nullptr;
-    std::vector<SMatrix> mats;
-    // client side
-    std::mutex mu;
-    std::condition_variable cv, done_cv;
-    std::deque<Req *> incoming;
-    std::unordered_map<uint64_t, int> status;  // 0 pending, 1 done, -1 failed
-    uint64_t next_ticket = 1;
-    // scheduler side
-    std::thread sched, uploader;
-    std::atomic<bool> stop{false};
-    std::deque<Req *> waiting;
-    std::vector<Req *> active;
-    std::vector<Slot> slots;
-    std::vector<int> free_slots;
-    int64_t used = 0, peak = 0;
-    uint64_t use_clock = 0;
-    int resident = 0;
-    Tick ticks[2];
-    int tick_no = 0;
+    lilac_server_config cfg{};
     bool fifo = false;
-    // uploads
+    int max_rows = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t up_stream[kUploadThreads] = {};
+    std::vector<SMatrix> mats;
+    std::vector<Slot> slots;
+    TickBuf ticks[2];
+    Account acct;                  // the server's own: limit = budget
+    HipExec exec{this};
+    serve::Core *core = nullptr;
+    std::thread sched;
+    std::thread uploader[kUploadThreads];
+    std::atomic<bool> stop{false};
     std::mutex up_mu;
     std::condition_variable up_cv;
     std::deque<int> up_q;
-    std::vector<std::pair<int, CsrHandle *>> up_done;
-    std::vector<int> up_failed;
-    // statistics (under mu)
-    std::vector<double> lat_us;
-    int64_t n_spmv = 0, n_cg = 0, n_failed = 0, n_uploads = 0, n_evict = 0,
-            n_ticks = 0;
-    double bytes_done = 0.0;
-    int64_t t_first = 0, t_last = 0;
-    std::string err;
-    int max_rows = 0;
-    bool dead = false;   // the scheduler stopped on an error
+    std::atomic<bool> started{false};
+    std::mutex start_mu;
 };
 
-int64_t matrix_bytes(const SMatrix &m)
+// ------------------------------------------------------------- accounting
+
+// Bound on the device bytes an upload of a float64 matrix holds at any
+// moment: the CSR arrays (padded), the row-class analysis and its
+// temporaries, the larger of the column-panel and band copies with their
+// build temporaries, the trace operand, and the 256-byte rounding of each
+// allocation.  Upload threads run under an account with this limit, so a
+// build that needed more would fail loudly instead of passing the budget.
+int64_t upload_bound(const SMatrix &m, bool cg_state)
 {
-    const int64_t npad = ((m.nnz + kPad - 1) / kPad) * kPad + kPad;
-    return (int64_t)(m.rows + 1) * 4 + npad * 12 + (int64_t)m.rows * 4 +
-           (int64_t)(m.rows + m.cols) * 8 + (1 << 20);
+    const int64_t rows = m.rows, nnz = m.nnz;
+    const int64_t npad = padded_nnz(nnz);
+    int64_t b = 0;
+    b += (rows + 1) * 4 + npad * 12;                       // CSR
+    b += rows * 28 + (nnz / 2048 + 1) * 24 + (1 << 20);    // classes, tiles, chunks, temps
+    b += (nnz + kPad) * 12 + 256 * (rows + 257) + (2 << 20);  // panel or band copy + build
+    b += (int64_t)std::max(1, m.cols) * 8;                 // trace operand
+    if (cg_state)
+        b += rows * 24 + 2 * 1024 * 8 + 256;               // CG state of the plain path
+    b += 64 * 256;                                         // allocation rounding
+    return b;
 }
 
-void free_slot_mem(Slot &sl)
+int64_t slot_bytes_for(const Server *S, int64_t chunks)
 {
+    const int64_t n = std::max(1, S->max_rows);
+    return 4 * (int64_t)round256((size_t)n * 8) + (int64_t)round256(kBlock * 8) +
+           (int64_t)round256(2 * kBlock * 8) + 256 +
+           (chunks > 0 ? (int64_t)round256((size_t)chunks * 8) : 0);
+}
+
+// ------------------------------------------------------------- uploads
+
+void upload_loop(Server *S, int t)
+{
+    if (hipSetDevice(lib_device()) != hipSuccess)
+        return;
+    hipStream_t us = S->up_stream[t];
+    while (true) {
+        int id = -1;
+        {
+            std::unique_lock<std::mutex> lk(S->up_mu);
+            S->up_cv.wait(lk, [&] { return !S->up_q.empty() || S->stop.load(); });
+            if (S->stop.load())
+                return;
+            id = S->up_q.front();
+            S->up_q.pop_front();
+        }
+        SMatrix &m = S->mats[(size_t)id];
+        const int64_t npad = padded_nnz(m.nnz);
+        int32_t *d_rp = nullptr, *d_col = nullptr;
+        double *d_vals = nullptr;
+        CsrHandle *h = nullptr;
+        double *vin = nullptr;
+        bool ok = true;
+        std::string why;
+        thread_account() = &m.acct;
+        try {
+            {
+                std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+                d_rp = (int32_t *)dev_alloc((size_t)(m.rows + 1) * 4);
+                d_col = (int32_t *)dev_alloc((size_t)npad * 4);
+                d_vals = (double *)dev_alloc((size_t)npad * 8);
+            }
+            // the copies run without the library lock (the scheduler may
+            // need it meanwhile); the arrays become the handle's own
+            HIPC(hipMemcpyAsync(d_rp, m.rp, (size_t)(m.rows + 1) * 4,
+                                hipMemcpyHostToDevice, us));
+            if (m.nnz) {
+                HIPC(hipMemcpyAsync(d_col, m.col, (size_t)m.nnz * 4,
+                                    hipMemcpyHostToDevice, us));
+                HIPC(hipMemcpyAsync(d_vals, m.vals, (size_t)m.nnz * 8,
+                                    hipMemcpyHostToDevice, us));
+            }
+            HIPC(hipStreamSynchronize(us));
+            std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+            int32_t *a = d_rp, *c = d_col;
+            double *v = d_vals;
+            d_rp = d_col = nullptr;
+            d_vals = nullptr;
+            h = create_handle_adopt(m.rows, m.cols, m.nnz, a, c, v, LILAC_F64);
+            if (S->fifo && m.rows == m.cols && m.rows > 0)
+                handle_cg_prepare(*h);   // the plain path's CG state, counted here
+            vin = (double *)dev_alloc((size_t)std::max(1, m.cols) * 8);
+            launch_fill_f64(vin, std::max(1, m.cols), 1.0, us);
+            HIPC(hipStreamSynchronize(us));
+        } catch (const Error &e) {
+            ok = false;
+            why = e.msg;
+            std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+            dev_free(d_rp);
+            dev_free(d_col);
+            dev_free(d_vals);
+            dev_free(vin);
+            vin = nullptr;
+            if (h)
+                destroy_handle(h);
+            h = nullptr;
+        }
+        thread_account() = nullptr;
+        int64_t held = 0;
+        {
+            std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+            m.h = h;
+            m.vin = vin;
+            m.nchunks = h ? h->nchunks : 0;
+            held = m.acct.in_use;
+            m.acct.limit = INT64_MAX;   // the reserve no longer applies
+        }
+        S->core->upload_done(id, ok, held, why);
+    }
+}
+
+// ------------------------------------------------------------- executor
+
+int64_t HipExec::upload_reserve(int mid)
+{
+    return upload_bound(S->mats[(size_t)mid], S->fifo);
+}
+
+void HipExec::start_upload(int mid)
+{
+    SMatrix &m = S->mats[(size_t)mid];
+    {
+        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+        m.acct.limit = upload_bound(m, S->fifo);
+        m.acct.peak = m.acct.in_use;
+    }
+    std::lock_guard<std::mutex> lk(S->up_mu);
+    S->up_q.push_back(mid);
+    S->up_cv.notify_one();
+}
+
+void HipExec::evict(int mid)
+{
+    SMatrix &m = S->mats[(size_t)mid];
+    std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+    destroy_handle(m.h);
+    dev_free(m.vin);
+    m.h = nullptr;
+    m.vin = nullptr;
+    if (m.acct.in_use != 0)
+        fail(LILAC_ERR_DEVICE, "evicted matrix still holds device memory");
+}
+
+int64_t HipExec::slot_need(int slot, int mid)
+{
+    const Slot *sl = slot < (int)S->slots.size() ? &S->slots[(size_t)slot] : nullptr;
+    const int64_t chunks =
+        std::max<int64_t>(sl ? sl->cap_chunks : 0, S->mats[(size_t)mid].nchunks);
+    return slot_bytes_for(S, chunks);
+}
+
+void HipExec::prepare_slot(int slot, int mid)
+{
+    while ((int)S->slots.size() <= slot)
+        S->slots.push_back(Slot());
+    Slot &sl = S->slots[(size_t)slot];
+    const int64_t n = std::max(1, S->max_rows);
+    std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+    if (!sl.r) {
+        sl.r = (double *)dev_alloc((size_t)n * 8);
+        sl.p = (double *)dev_alloc((size_t)n * 8);
+        sl.q = (double *)dev_alloc((size_t)n * 8);
+        sl.x = (double *)dev_alloc((size_t)n * 8);
+        sl.pq = (double *)dev_alloc(kBlock * 8);
+        sl.rr = (double *)dev_alloc(2 * kBlock * 8);
+        sl.done = (int32_t *)dev_alloc(256);
+    }
+    const int64_t nc = S->mats[(size_t)mid].nchunks;
+    if (sl.cap_chunks < nc) {
+        dev_free(sl.chunk);
+        sl.chunk = nullptr;
+        sl.cap_chunks = 0;
+        sl.chunk = (double *)dev_alloc((size_t)nc * 8);
+        sl.cap_chunks = nc;
+    }
+}
+
+void HipExec::release_slot(int slot)
+{
+    if (slot >= (int)S->slots.size())
+        return;
+    Slot &sl = S->slots[(size_t)slot];
+    std::lock_guard<std::recursive_mutex> lk(lib_mutex());
     dev_free(sl.r);
     dev_free(sl.p);
     dev_free(sl.q);
+    dev_free(sl.x);
     dev_free(sl.pq);
     dev_free(sl.rr);
     dev_free(sl.done);
@@ -141,311 +320,36 @@ void free_slot_mem(Slot &sl)
     sl = Slot();
 }
 
-// ------------------------------------------------------------- uploads
-
-void upload_loop(Server *S)
-{
-    if (hipSetDevice(lib_device()) != hipSuccess)
-        return;
-    while (!S->stop.load()) {
-        int id = -1;
-        {
-            std::unique_lock<std::mutex> lk(S->up_mu);
-            S->up_cv.wait_for(lk, std::chrono::milliseconds(5),
-                              [&] { return !S->up_q.empty() || S->stop.load(); });
-            if (S->stop.load())
-                return;
-            if (S->up_q.empty())
-                continue;
-            id = S->up_q.front();
-            S->up_q.pop_front();
-        }
-        SMatrix &m = S->mats[id];
-        CsrHandle *h = nullptr;
-        // the arrays go up from pinned host memory into staging buffers
-        // without the library lock (the scheduler may need it meanwhile, to
-        // evict); the lock is taken only to build the handle from them
-        int32_t *d_rp = nullptr, *d_col = nullptr;
-        double *d_vals = nullptr;
-        const size_t b_rp = (size_t)(m.rows + 1) * 4, b_col = (size_t)m.nnz * 4,
-                     b_vals = (size_t)m.nnz * 8;
-        try {
-            {
-                std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-                d_rp = (int32_t *)dev_alloc(b_rp);
-                d_col = (int32_t *)dev_alloc(std::max<size_t>(b_col, 4));
-                d_vals = (double *)dev_alloc(std::max<size_t>(b_vals, 8));
-            }
-            HIPC(hipMemcpyAsync(d_rp, m.rp, b_rp, hipMemcpyHostToDevice, S->up_stream));
-            if (m.nnz) {
-                HIPC(hipMemcpyAsync(d_col, m.col, b_col, hipMemcpyHostToDevice, S->up_stream));
-                HIPC(hipMemcpyAsync(d_vals, m.vals, b_vals, hipMemcpyHostToDevice,
-                                    S->up_stream));
-            }
-            HIPC(hipStreamSynchronize(S->up_stream));
-            std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-            h = create_handle(m.rows, m.cols, m.nnz, d_rp, d_col, d_vals, LILAC_F64, 0,
-                              true);
-            dev_free(d_rp);
-            dev_free(d_col);
-            dev_free(d_vals);
-            d_rp = d_col = nullptr;
-            d_vals = nullptr;
-            m.vin = (double *)dev_alloc((size_t)std::max(1, m.cols) * 8);
-            m.vout = (double *)dev_alloc((size_t)std::max(1, m.rows) * 8);
-            // trace-mode operands: x (or b) = 1
-            std::vector<double> ones((size_t)std::max(1, m.cols), 1.0);
-            HIPC(hipMemcpyAsync(m.vin, ones.data(), ones.size() * 8,
-                                hipMemcpyHostToDevice, S->up_stream));
-            HIPC(hipStreamSynchronize(S->up_stream));
-        } catch (const Error &e) {
-            {
-                std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-                dev_free(d_rp);
-                dev_free(d_col);
-                dev_free(d_vals);
-            }
-            std::lock_guard<std::mutex> lk(S->up_mu);
-            S->up_failed.push_back(id);
-            S->err = e.msg;
-            continue;
-        }
-        std::lock_guard<std::mutex> lk(S->up_mu);
-        S->up_done.emplace_back(id, h);
-    }
-}
-
-// ------------------------------------------------------------- scheduler
-
-bool evict_one(Server *S)
-{
-    int best = -1;
-    for (int i = 0; i < (int)S->mats.size(); ++i) {
-        const SMatrix &m = S->mats[i];
-        if (m.st == SMatrix::READY && m.refs == 0 &&
-            (best < 0 || m.last_use < S->mats[best].last_use))
-            best = i;
-    }
-    if (best < 0)
-        return false;
-    SMatrix &m = S->mats[best];
-    {
-        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-        destroy_handle(m.h);
-        dev_free(m.vin);
-        dev_free(m.vout);
-    }
-    m.h = nullptr;
-    m.vin = m.vout = nullptr;
-    m.st = SMatrix::OFF;
-    S->used -= m.bytes;
-    m.bytes = 0;
-    S->resident -= 1;
-    S->n_evict += 1;
-    return true;
-}
-
-void finish(Server *S, Req *r, int64_t t)
-{
-    SMatrix &m = S->mats[r->mid];
-    m.refs -= 1;
-    if (r->slot >= 0)
-        S->free_slots.push_back(r->slot);
-    std::lock_guard<std::mutex> lk(S->mu);
-    if (r->failed) {
-        S->status[r->ticket] = -1;
-        S->n_failed += 1;
-    } else {
-        S->status[r->ticket] = 1;
-        S->lat_us.push_back((t - r->t_arr) * 1e-3);
-        if (r->kind == LILAC_REQ_CG) {
-            S->n_cg += 1;
-            S->bytes_done += (double)r->iters * (m.spmv_bytes + 9.0 * m.rows * 8);
-        } else {
-            S->n_spmv += 1;
-            S->bytes_done += (double)m.spmv_bytes;
-        }
-        if (!S->t_first)
-            S->t_first = r->t_arr;
-        S->t_last = std::max(S->t_last, t);
-    }
-    S->done_cv.notify_all();
-    delete r;
-}
-
-void complete_tick(Server *S, Tick &tk)
-{
-    if (!tk.pending)
-        return;
-    HIPC(hipEventSynchronize(tk.ev));
-    const int64_t t = now_ns();
-    for (Req *r : tk.finishing)
-        finish(S, r, t);
-    tk.finishing.clear();
-    tk.pending = false;
-}
-
-// A workspace slot for request r.  Slots are sized for the largest
-// registered matrix, so any free slot fits; chunk partials grow on demand.
-bool get_slot(Server *S, Req *r)
-{
-    const SMatrix &m = S->mats[r->mid];
-    const int64_t nc = m.h->nchunks;
-    if (S->free_slots.empty()) {
-        if ((int)S->slots.size() >= S->cfg.max_active)
-            return false;
-        const int64_t n = S->max_rows;
-        const int64_t need = n * 24 + 3 * kBlock * 8 + 256 + 4096;
-        if (S->used + need > S->cfg.hbm_budget)
-            return false;
-        Slot sl;
-        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-        sl.cap_n = n;
-        sl.r = (double *)dev_alloc((size_t)std::max<int64_t>(n, 1) * 8);
-        sl.p = (double *)dev_alloc((size_t)std::max<int64_t>(n, 1) * 8);
-        sl.q = (double *)dev_alloc((size_t)std::max<int64_t>(n, 1) * 8);
-        sl.pq = (double *)dev_alloc(kBlock * 8);
-        sl.rr = (double *)dev_alloc(2 * kBlock * 8);
-        sl.done = (int32_t *)dev_alloc(256);
-        sl.bytes = need;
-        S->used += need;
-        S->peak = std::max(S->peak, S->used);
-        S->slots.push_back(sl);
-        S->free_slots.push_back((int)S->slots.size() - 1);
-    }
-    const int si = S->free_slots.back();
-    Slot &sl = S->slots[si];
-    if (sl.cap_chunks < nc) {
-        if (S->used + nc * 8 > S->cfg.hbm_budget)
-            return false;
-        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-        dev_free(sl.chunk);
-        sl.chunk = (double *)dev_alloc((size_t)nc * 8);
-        S->used += (nc - sl.cap_chunks) * 8;
-        sl.bytes += (nc - sl.cap_chunks) * 8;
-        sl.cap_chunks = nc;
-        S->peak = std::max(S->peak, S->used);
-    }
-    r->slot = si;
-    S->free_slots.pop_back();
-    return true;
-}
-
-void collect_uploads(Server *S)
-{
-    std::vector<std::pair<int, CsrHandle *>> done;
-    std::vector<int> failed;
-    {
-        std::lock_guard<std::mutex> lk(S->up_mu);
-        done.swap(S->up_done);
-        failed.swap(S->up_failed);
-    }
-    for (auto &d : done) {
-        SMatrix &m = S->mats[d.first];
-        m.h = d.second;
-        m.st = SMatrix::READY;
-        m.spmv_bytes = m.nnz * 12 + (int64_t)(m.rows + 1) * 4 +
-                       (int64_t)(m.cols + m.rows) * 8;
-    }
-    for (int id : failed) {
-        SMatrix &m = S->mats[id];
-        m.st = SMatrix::OFF;
-        S->used -= m.bytes;
-        m.bytes = 0;
-        S->resident -= 1;
-        // fail every waiting request on this matrix
-        for (auto it = S->waiting.begin(); it != S->waiting.end();) {
-            if ((*it)->mid == id) {
-                (*it)->failed = true;
-                m.refs += 1;
-                finish(S, *it, now_ns());
-                it = S->waiting.erase(it);
-            } else {
-                ++it;
-            }
-        }
-    }
-}
-
-// Start an upload if the budget and the pool allow (evicting idle matrices).
-void request_upload(Server *S, int id)
-{
-    SMatrix &m = S->mats[id];
-    const int64_t need = matrix_bytes(m);
-    if (need > S->cfg.hbm_budget) {
-        m.st = SMatrix::UPLOADING;   // will fail through the failure path
-        S->used += 0;
-        std::lock_guard<std::mutex> lk(S->up_mu);
-        S->up_failed.push_back(id);
-        S->err = "matrix larger than the server's HBM budget";
-        S->resident += 1;
-        return;
-    }
-    while ((S->used + need > S->cfg.hbm_budget ||
-            S->resident >= S->cfg.pool_capacity) &&
-           evict_one(S)) {
-    }
-    if (S->used + need > S->cfg.hbm_budget || S->resident >= S->cfg.pool_capacity)
-        return;  // try again when something becomes idle
-    m.st = SMatrix::UPLOADING;
-    m.bytes = need;
-    S->used += need;
-    S->peak = std::max(S->peak, S->used);
-    S->resident += 1;
-    S->n_uploads += 1;
-    std::lock_guard<std::mutex> lk(S->up_mu);
-    S->up_q.push_back(id);
-    S->up_cv.notify_one();
-}
-
-// Grows the pinned and device table buffers of a tick.
-void tick_reserve(Tick &tk, size_t bytes)
-{
-    if (bytes <= tk.cap)
-        return;
-    size_t cap = std::max<size_t>(bytes, 2 * tk.cap);
-    cap = std::max<size_t>(cap, 1 << 16);
-    if (tk.host)
-        (void)hipHostFree(tk.host);
-    if (tk.dev) {
-        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-        dev_free(tk.dev);
-    }
-    HIPC(hipHostMalloc((void **)&tk.host, cap, hipHostMallocDefault));
-    {
-        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-        tk.dev = (char *)dev_alloc(cap);
-    }
-    tk.cap = cap;
-}
+void HipExec::wait_tick(int tick) { HIPC(hipEventSynchronize(S->ticks[tick].ev)); }
 
 // One batched tick over every active request.
-void run_tick(Server *S)
+void HipExec::launch_tick(int tick, const std::vector<serve::Request *> &reqs)
 {
-    Tick &tk = S->ticks[S->tick_no & 1];
-    complete_tick(S, tk);  // its buffers are about to be reused
+    TickBuf &tk = S->ticks[tick];
     std::vector<MatDesc> descs;
     std::vector<int32_t> prefix(1, 0);
-    std::vector<int32_t> items;
     std::vector<CgSeg> init, step;
-    std::vector<Req *> own;
+    std::vector<serve::Request *> own, split;
     int32_t init_blocks = 0, step_blocks = 0;
-    for (Req *r : S->active) {
-        SMatrix &m = S->mats[r->mid];
-        Slot &sl = S->slots[r->slot];
-        const int j = (int)descs.size();
-        const double *in = r->in ? r->in : m.vin;
-        double *out = r->out ? r->out : m.vout;
+    for (serve::Request *r : reqs) {
+        SMatrix &m = S->mats[(size_t)r->mid];
+        Slot &sl = S->slots[(size_t)r->slot];
+        const double *in = r->in ? (const double *)r->in : m.vin;
+        double *out = r->out ? (double *)r->out : sl.x;
         if (own_layout(*m.h)) {
             // matrices in a layout of their own run their own product kernel
             own.push_back(r);
-        } else if (r->kind == LILAC_REQ_SPMV) {
-            descs.push_back(make_desc(*m.h, in, out, nullptr, sl.chunk));
         } else {
-            descs.push_back(make_desc(*m.h, sl.p, sl.q, nullptr, sl.chunk));
+            if (r->kind == serve::kSpmv)
+                descs.push_back(make_desc(*m.h, in, out, nullptr, sl.chunk));
+            else
+                descs.push_back(make_desc(*m.h, sl.p, sl.q, nullptr, sl.chunk));
+            prefix.push_back(prefix.back() + m.h->ntiles);
+            if (m.h->nsplit > 0)
+                split.push_back(r);
         }
-        if (r->kind == LILAC_REQ_CG) {
-            CgSeg sg;
+        if (r->kind == serve::kCg) {
+            CgSeg sg{};
             sg.b = in;
             sg.x = out;
             sg.r = sl.r;
@@ -467,37 +371,31 @@ void run_tick(Server *S)
             step_blocks += sg.nb;
             step.push_back(sg);
         }
-        if (own_layout(*m.h))
-            continue;
-        prefix.push_back(prefix.back() + m.h->ntiles);
-        for (int32_t k = 0; k < m.h->nsplit; ++k) {
-            items.push_back(j);
-            items.push_back(k);
-        }
     }
-    // column-panel products of the tick: one grouped launch
+    // column-panel and band products of the tick: one grouped launch each,
+    // matrices with the most non-zeros per block first so that a launch
+    // ends on short blocks
     std::vector<PanelDesc> pdesc;
     std::vector<PanelIO> pio;
     std::vector<int32_t> pprefix(1, 0);
     std::vector<BandDesc> bdesc;
     std::vector<PanelIO> bio;
     std::vector<int32_t> bprefix(1, 0);
-    std::vector<Req *> own_hot;
-    // matrices with the most non-zeros per block first, so that a grouped
-    // launch ends on short blocks
-    std::vector<Req *> heavy(own.begin(), own.end());
-    auto per_block = [&](const Req *r) {
-        const CsrHandle &h = *S->mats[r->mid].h;
+    std::vector<serve::Request *> own_hot;
+    auto per_block = [&](const serve::Request *r) {
+        const CsrHandle &h = *S->mats[(size_t)r->mid].h;
         const int32_t nb = h.use_panels ? h.pan.nblk : h.use_band ? h.band.nblk : 1;
         return (double)h.nnz / (double)std::max(1, nb);
     };
-    std::stable_sort(heavy.begin(), heavy.end(),
-                     [&](const Req *a, const Req *b) { return per_block(a) > per_block(b); });
-    for (Req *r : heavy) {
-        SMatrix &m = S->mats[r->mid];
-        Slot &sl = S->slots[r->slot];
-        const PanelIO io = (r->kind == LILAC_REQ_SPMV)
-                               ? PanelIO{r->in ? r->in : m.vin, r->out ? r->out : m.vout}
+    std::stable_sort(own.begin(), own.end(), [&](const serve::Request *a,
+                                                 const serve::Request *b) {
+        return per_block(a) > per_block(b);
+    });
+    for (serve::Request *r : own) {
+        SMatrix &m = S->mats[(size_t)r->mid];
+        Slot &sl = S->slots[(size_t)r->slot];
+        const PanelIO io = (r->kind == serve::kSpmv)
+                               ? PanelIO{r->in ? r->in : m.vin, r->out ? r->out : sl.x}
                                : PanelIO{sl.p, sl.q};
         if (m.h->use_panels) {
             pdesc.push_back(m.h->pan);
@@ -513,7 +411,6 @@ void run_tick(Server *S)
     }
     const size_t b_desc = descs.size() * sizeof(MatDesc);
     const size_t b_pre = ((prefix.size() * 4 + 15) / 16) * 16;
-    const size_t b_items = ((items.size() * 4 + 15) / 16) * 16;
     const size_t b_init = init.size() * sizeof(CgSeg);
     const size_t b_step = step.size() * sizeof(CgSeg);
     const size_t b_pdesc = pdesc.size() * sizeof(PanelDesc);
@@ -522,18 +419,20 @@ void run_tick(Server *S)
     const size_t b_bdesc = bdesc.size() * sizeof(BandDesc);
     const size_t b_bio = bio.size() * sizeof(PanelIO);
     const size_t b_bpre = ((bprefix.size() * 4 + 15) / 16) * 16;
-    tick_reserve(tk, b_desc + b_pre + b_items + b_init + b_step + b_pdesc + b_pio +
-                         b_ppre + b_bdesc + b_bio + b_bpre + 64);
+    const size_t total = b_desc + b_pre + b_init + b_step + b_pdesc + b_pio + b_ppre +
+                         b_bdesc + b_bio + b_bpre;
+    if (total > tk.cap)
+        fail(LILAC_ERR_DEVICE, "tick tables larger than their buffer");
     size_t off = 0;
     auto put = [&](const void *src, size_t n, size_t padded) {
-        std::memcpy(tk.host + off, src, n);
+        if (n)
+            std::memcpy(tk.host + off, src, n);
         const size_t at = off;
         off += padded;
         return at;
     };
     const size_t o_desc = put(descs.data(), b_desc, b_desc);
     const size_t o_pre = put(prefix.data(), prefix.size() * 4, b_pre);
-    const size_t o_items = put(items.data(), items.size() * 4, b_items);
     const size_t o_init = put(init.data(), b_init, b_init);
     const size_t o_step = put(step.data(), b_step, b_step);
     const size_t o_pdesc = put(pdesc.data(), b_pdesc, b_pdesc);
@@ -542,213 +441,202 @@ void run_tick(Server *S)
     const size_t o_bdesc = put(bdesc.data(), b_bdesc, b_bdesc);
     const size_t o_bio = put(bio.data(), b_bio, b_bio);
     const size_t o_bpre = put(bprefix.data(), bprefix.size() * 4, b_bpre);
-    HIPC(hipMemcpyAsync(tk.dev, tk.host, off, hipMemcpyHostToDevice, S->stream));
+    hipStream_t s = S->stream;
+    HIPC(hipMemcpyAsync(tk.dev, tk.host, off, hipMemcpyHostToDevice, s));
     const MatDesc *d_desc = (const MatDesc *)(tk.dev + o_desc);
     if (!init.empty())
         launch_cgb_init((const CgSeg *)(tk.dev + o_init), (int32_t)init.size(),
-                        init_blocks, S->stream);
+                        init_blocks, s);
     launch_spmv_segments(LILAC_F64, d_desc, (const int32_t *)(tk.dev + o_pre),
-                         (int32_t)descs.size(), prefix.back(), tile_grid(LILAC_F64),
-                         S->stream);
+                         (int32_t)descs.size(), prefix.back(), tile_grid(LILAC_F64), s);
     launch_spmv_panels_grouped(LILAC_F64, (const PanelDesc *)(tk.dev + o_pdesc),
                                (const PanelIO *)(tk.dev + o_pio),
                                (const int32_t *)(tk.dev + o_ppre), (int32_t)pdesc.size(),
-                               pprefix.back(), S->stream);
+                               pprefix.back(), s);
     launch_spmv_band_grouped(LILAC_F64, (const BandDesc *)(tk.dev + o_bdesc),
                              (const PanelIO *)(tk.dev + o_bio),
                              (const int32_t *)(tk.dev + o_bpre), (int32_t)bdesc.size(),
-                             bprefix.back(), S->stream);
-    for (Req *r : own_hot) {
-        SMatrix &m = S->mats[r->mid];
-        Slot &sl = S->slots[r->slot];
-        if (r->kind == LILAC_REQ_SPMV)
-            spmv_enqueue(*m.h, r->in ? r->in : m.vin, r->out ? r->out : m.vout,
-                         Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, S->stream);
+                             bprefix.back(), s);
+    for (serve::Request *r : own_hot) {
+        SMatrix &m = S->mats[(size_t)r->mid];
+        Slot &sl = S->slots[(size_t)r->slot];
+        if (r->kind == serve::kSpmv)
+            spmv_enqueue(*m.h, r->in ? r->in : m.vin, r->out ? r->out : sl.x,
+                         Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, s);
         else
-            spmv_enqueue(*m.h, sl.p, sl.q, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr,
-                         false, S->stream);
+            spmv_enqueue(*m.h, sl.p, sl.q, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, s);
     }
-    if (!items.empty()) {
-        MatDesc none{};
-        launch_split_finalize(LILAC_F64, (const int32_t *)(tk.dev + o_items),
-                              (int32_t)(items.size() / 2), none, d_desc,
-                              Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, S->stream);
+    // split rows: each request's chunk sums added up in chunk order, as the
+    // single-matrix product does
+    for (serve::Request *r : split) {
+        SMatrix &m = S->mats[(size_t)r->mid];
+        Slot &sl = S->slots[(size_t)r->slot];
+        const MatDesc d = (r->kind == serve::kSpmv)
+                              ? make_desc(*m.h, r->in ? r->in : m.vin,
+                                          r->out ? r->out : sl.x, nullptr, sl.chunk)
+                              : make_desc(*m.h, sl.p, sl.q, nullptr, sl.chunk);
+        launch_split_finalize(LILAC_F64, nullptr, m.h->nsplit, d, nullptr,
+                              Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, s);
     }
     if (!step.empty()) {
         const CgSeg *d_step = (const CgSeg *)(tk.dev + o_step);
-        launch_cgb_pq(d_step, (int32_t)step.size(), step_blocks, S->stream);
-        launch_cgb_update(d_step, (int32_t)step.size(), step_blocks, S->stream);
-        launch_cgb_xpay(d_step, (int32_t)step.size(), step_blocks, S->stream);
+        launch_cgb_pq(d_step, (int32_t)step.size(), step_blocks, s);
+        launch_cgb_update(d_step, (int32_t)step.size(), step_blocks, s);
+        launch_cgb_xpay(d_step, (int32_t)step.size(), step_blocks, s);
     }
-    HIPC(hipEventRecord(tk.ev, S->stream));
-    tk.pending = true;
-    S->n_ticks += 1;
-    // requests whose last step is in this tick leave the active set now;
-    // their resources are released when the tick completes
-    std::vector<Req *> still;
-    for (Req *r : S->active) {
-        if (r->kind == LILAC_REQ_CG) {
-            r->iter += 1;
-            if (r->iter < r->iters) {
-                still.push_back(r);
-                continue;
-            }
-        }
-        tk.finishing.push_back(r);
-    }
-    S->active.swap(still);
-    S->tick_no += 1;
+    HIPC(hipEventRecord(tk.ev, s));
 }
 
-// The plain path: one request at a time with the single-matrix calls.
-void run_fifo_one(Server *S, Req *r)
+// The plain path: the whole request alone with the single-matrix calls.
+void HipExec::run_one(serve::Request *r)
 {
-    SMatrix &m = S->mats[r->mid];
-    const double *in = r->in ? r->in : m.vin;
-    double *out = r->out ? r->out : m.vout;
-    if (r->kind == LILAC_REQ_SPMV) {
-        spmv_enqueue(*m.h, in, out, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr,
-                     false, S->stream);
+    SMatrix &m = S->mats[(size_t)r->mid];
+    Slot &sl = S->slots[(size_t)r->slot];
+    const double *in = r->in ? (const double *)r->in : m.vin;
+    double *out = r->out ? (double *)r->out : sl.x;
+    if (r->kind == serve::kSpmv) {
+        spmv_enqueue(*m.h, in, out, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, S->stream);
     } else {
-        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-        run_cg(*m.h, in, out, r->iters, LILAC_CG_GRAPH, S->stream, nullptr,
-               nullptr);
+        // the CG state was made at upload, under the matrix's account
+        thread_account() = &m.acct;
+        try {
+            std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+            run_cg(*m.h, in, out, r->iters, LILAC_CG_GRAPH, S->stream, nullptr, nullptr);
+        } catch (...) {
+            thread_account() = &S->acct;
+            throw;
+        }
+        thread_account() = &S->acct;
     }
     HIPC(hipStreamSynchronize(S->stream));
-    finish(S, r, now_ns());
 }
 
-void schedule_loop(Server *S)
-{
-    HIPC(hipSetDevice(lib_device()));
-    while (true) {
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            while (!S->incoming.empty()) {
-                S->waiting.push_back(S->incoming.front());
-                S->incoming.pop_front();
-            }
-        }
-        collect_uploads(S);
-        if (S->stop.load()) {
-            // shutting down: what has not started fails, what runs finishes
-            for (Req *r : S->waiting) {
-                r->failed = true;
-                S->mats[r->mid].refs += 1;
-                finish(S, r, now_ns());
-            }
-            S->waiting.clear();
-            if (S->active.empty()) {
-                complete_tick(S, S->ticks[0]);
-                complete_tick(S, S->ticks[1]);
-                break;
-            }
-        }
-        // admission, in arrival order; a request whose matrix is not yet
-        // resident does not hold up the ones behind it
-        for (auto it = S->waiting.begin(); it != S->waiting.end();) {
-            Req *r = *it;
-            SMatrix &m = S->mats[r->mid];
-            if (m.st == SMatrix::OFF) {
-                request_upload(S, r->mid);
-                ++it;
-                continue;
-            }
-            if (m.st != SMatrix::READY) {
-                ++it;
-                continue;
-            }
-            if (S->fifo) {
-                it = S->waiting.erase(it);
-                m.refs += 1;
-                m.last_use = ++S->use_clock;
-                run_fifo_one(S, r);
-                break;
-            }
-            if ((int)S->active.size() >= S->cfg.max_active)
-                break;
-            m.refs += 1;  // keep it resident while we look for a slot
-            if (!get_slot(S, r)) {
-                m.refs -= 1;
-                break;
-            }
-            m.last_use = ++S->use_clock;
-            S->active.push_back(r);
-            it = S->waiting.erase(it);
-        }
-        if (!S->active.empty()) {
-            run_tick(S);
-            // keep one tick in flight: finish the previous one now
-            complete_tick(S, S->ticks[S->tick_no & 1]);
-            continue;
-        }
-        complete_tick(S, S->ticks[0]);
-        complete_tick(S, S->ticks[1]);
-        std::unique_lock<std::mutex> lk(S->mu);
-        S->cv.wait_for(lk, std::chrono::microseconds(200),
-                       [&] { return !S->incoming.empty() || S->stop.load(); });
-    }
-}
+// ------------------------------------------------------------- threads
 
 void scheduler_main(Server *S)
 {
-    try {
-        schedule_loop(S);
-    } catch (const Error &e) {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->err = e.msg;
-        S->dead = true;
-        // fail everything still queued so waiters return
-        for (Req *r : S->waiting)
-            S->status[r->ticket] = -1;
-        for (Req *r : S->active)
-            S->status[r->ticket] = -1;
-        for (Req *r : S->incoming)
-            S->status[r->ticket] = -1;
-        S->done_cv.notify_all();
+    if (hipSetDevice(lib_device()) != hipSuccess) {
+        S->core->die("hipSetDevice failed in the scheduler");
+        return;
     }
+    thread_account() = &S->acct;
+    try {
+        while (!S->stop.load()) {
+            if (!S->core->step())
+                S->core->wait_for_work(200000);
+        }
+        S->core->shutdown();
+    } catch (const Error &e) {
+        S->core->die(e.msg);
+    } catch (const std::exception &e) {
+        S->core->die(e.what());
+    }
+    thread_account() = nullptr;
 }
 
 void fill_stats(Server *S, lilac_server_stats *o)
 {
-    std::lock_guard<std::mutex> lk(S->mu);
+    const serve::Stats st = S->core->stats();
     std::memset(o, 0, sizeof(*o));
-    o->completed = (int64_t)S->lat_us.size();
-    o->spmv_done = S->n_spmv;
-    o->cg_done = S->n_cg;
-    o->failed = S->n_failed;
-    o->uploads = S->n_uploads;
-    o->evictions = S->n_evict;
-    o->ticks = S->n_ticks;
-    o->peak_device_bytes = S->peak;
-    if (!S->lat_us.empty()) {
-        std::vector<double> v = S->lat_us;
-        auto pct = [&](double p) {
-            const size_t k = std::min(v.size() - 1, (size_t)(p * (v.size() - 1) + 0.5));
-            std::nth_element(v.begin(), v.begin() + k, v.end());
-            return v[k];
-        };
-        o->p50_us = pct(0.50);
-        o->p99_us = pct(0.99);
-        double s = 0.0, mx = 0.0;
-        for (double x : S->lat_us) {
-            s += x;
-            mx = std::max(mx, x);
+    o->completed = st.completed;
+    o->spmv_done = st.spmv_done;
+    o->cg_done = st.cg_done;
+    o->failed = st.failed;
+    o->p50_us = st.p50_us;
+    o->p99_us = st.p99_us;
+    o->mean_us = st.mean_us;
+    o->max_us = st.max_us;
+    o->wall_s = st.wall_s;
+    o->req_per_s = st.req_per_s;
+    o->solves_per_s = st.solves_per_s;
+    o->gbytes_per_s = st.gbytes_per_s;
+    o->uploads = st.uploads;
+    o->evictions = st.evictions;
+    o->ticks = st.ticks;
+    o->planned_peak_bytes = st.planned_peak;
+    std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+    o->peak_device_bytes = S->acct.peak;
+    o->device_bytes = S->acct.in_use;
+}
+
+void free_server(Server *S)
+{
+    std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+    for (auto &m : S->mats) {
+        if (m.h)
+            destroy_handle(m.h);
+        dev_free(m.vin);
+        if (m.pin)
+            (void)hipHostFree(m.pin);
+    }
+    for (auto &sl : S->slots) {
+        dev_free(sl.r);
+        dev_free(sl.p);
+        dev_free(sl.q);
+        dev_free(sl.x);
+        dev_free(sl.pq);
+        dev_free(sl.rr);
+        dev_free(sl.done);
+        dev_free(sl.chunk);
+    }
+    for (auto &t : S->ticks) {
+        if (t.host)
+            (void)hipHostFree(t.host);
+        dev_free(t.dev);
+        if (t.ev)
+            (void)hipEventDestroy(t.ev);
+    }
+    for (auto &us : S->up_stream)
+        if (us)
+            (void)hipStreamDestroy(us);
+    if (S->stream)
+        (void)hipStreamDestroy(S->stream);
+    delete S->core;
+    delete S;
+}
+
+// Starts the threads at the first request (matrices are all registered).
+void start(Server *S)
+{
+    std::lock_guard<std::mutex> slk(S->start_mu);
+    if (S->started.load())
+        return;
+    serve::Limits lim;
+    lim.budget = S->cfg.hbm_budget;
+    lim.max_active = S->cfg.max_active;
+    lim.pool_capacity = S->cfg.pool_capacity;
+    lim.fifo = S->fifo;
+    {
+        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+        thread_account() = &S->acct;
+        try {
+            const size_t cap =
+                round256(64 + (size_t)S->cfg.max_active * (per_request_table_bytes() + 64));
+            for (auto &t : S->ticks) {
+                HIPC(hipHostMalloc((void **)&t.host, cap, hipHostMallocDefault));
+                t.dev = (char *)dev_alloc(cap);
+                t.cap = cap;
+            }
+        } catch (...) {
+            thread_account() = nullptr;
+            throw;
         }
-        o->mean_us = s / (double)S->lat_us.size();
-        o->max_us = mx;
+        thread_account() = nullptr;
+        lim.overhead = S->acct.in_use;
     }
-    const double wall = (S->t_last - S->t_first) * 1e-9;
-    o->wall_s = wall;
-    if (wall > 0) {
-        o->req_per_s = o->completed / wall;
-        o->solves_per_s = S->n_cg / wall;
-        o->gbytes_per_s = S->bytes_done / wall / 1e9;
+    S->core = new serve::Core(S->exec, lim);
+    for (auto &m : S->mats) {
+        const int64_t sp = m.nnz * 12 + (int64_t)(m.rows + 1) * 4 +
+                           (int64_t)(m.cols + m.rows) * 8;
+        S->core->add_matrix(sp, sp + 9 * (int64_t)m.rows * 8);
     }
+    S->sched = std::thread(scheduler_main, S);
+    for (int t = 0; t < kUploadThreads; ++t)
+        S->uploader[t] = std::thread(upload_loop, S, t);
+    S->started.store(true);
 }
 
 }  // namespace
-
 }  // namespace lilac
 
 using namespace lilac;
@@ -788,12 +676,17 @@ int lilac_server_create(lilac_server_t *out, const lilac_server_config *cfg)
         S->cfg.pool_capacity = (cfg && cfg->pool_capacity > 0) ? cfg->pool_capacity : 64;
         S->cfg.fifo = cfg ? cfg->fifo : 0;
         S->fifo = S->cfg.fifo != 0;
-        HIPC(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
-        HIPC(hipStreamCreateWithFlags(&S->up_stream, hipStreamNonBlocking));
-        for (auto &t : S->ticks)
-            HIPC(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));
-        S->sched = std::thread(scheduler_main, S);
-        S->uploader = std::thread(upload_loop, S);
+        S->acct.limit = S->cfg.hbm_budget;
+        try {
+            HIPC(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+            for (auto &us : S->up_stream)
+                HIPC(hipStreamCreateWithFlags(&us, hipStreamNonBlocking));
+            for (auto &t : S->ticks)
+                HIPC(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));
+        } catch (...) {
+            free_server(S);
+            throw;
+        }
         *out = (lilac_server_t)S;
     });
 }
@@ -806,13 +699,13 @@ int lilac_server_add_matrix(lilac_server_t hs, int rows, int cols, int64_t nnz,
     return sguard([&] {
         if (!S || !id || rows < 0 || nnz < 0 || !row_ptr || (nnz && (!col_idx || !vals)))
             fail(LILAC_ERR_ARG, "bad argument");
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (!S->waiting.empty() || !S->active.empty() || !S->incoming.empty())
+        if (S->started.load())
             fail(LILAC_ERR_STATE, "add matrices before submitting requests");
         SMatrix m;
         m.rows = rows;
         m.cols = cols >= 0 ? cols : rows;
         m.nnz = nnz;
+        m.acct.parent = &S->acct;
         // a pinned copy: uploads then run at DMA speed, and the caller's
         // arrays are free once this returns
         const size_t b_rp = (size_t)(rows + 1) * 4, b_col = (size_t)nnz * 4;
@@ -844,28 +737,22 @@ int lilac_server_submit(lilac_server_t hs, const lilac_request *r, uint64_t *tic
             fail(LILAC_ERR_ARG, "unknown matrix id");
         if (r->kind != LILAC_REQ_SPMV && r->kind != LILAC_REQ_CG)
             fail(LILAC_ERR_ARG, "unknown request kind");
-        if (r->kind == LILAC_REQ_CG && (r->iters <= 0 ||
-                                        S->mats[r->matrix].rows != S->mats[r->matrix].cols))
+        const SMatrix &m = S->mats[(size_t)r->matrix];
+        if (r->kind == LILAC_REQ_CG && (r->iters <= 0 || m.rows != m.cols))
             fail(LILAC_ERR_ARG, "CG needs iters > 0 and a square matrix");
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (S->dead)
-                fail(LILAC_ERR_STATE, "server stopped after an error: " + S->err);
-        }
-        auto *q = new Req();
+        start(S);
+        if (S->core->dead())
+            fail(LILAC_ERR_STATE, "server stopped after an error: " + S->core->error());
+        auto *q = new serve::Request();
         q->kind = r->kind;
         q->mid = r->matrix;
         q->iters = r->iters;
         q->in = r->in;
         q->out = r->out;
         q->t_arr = r->arrival_ns > 0 ? r->arrival_ns : now_ns();
-        std::lock_guard<std::mutex> lk(S->mu);
-        q->ticket = S->next_ticket++;
-        S->status[q->ticket] = 0;
-        S->incoming.push_back(q);
-        S->cv.notify_one();
+        const uint64_t t = S->core->submit(q);
         if (ticket)
-            *ticket = q->ticket;
+            *ticket = t;
     });
 }
 
@@ -875,11 +762,10 @@ int lilac_server_poll(lilac_server_t hs, uint64_t ticket, int *done)
     return sguard([&] {
         if (!S || !done)
             fail(LILAC_ERR_ARG, "bad argument");
-        std::lock_guard<std::mutex> lk(S->mu);
-        auto it = S->status.find(ticket);
-        if (it == S->status.end())
+        const int st = S->core ? S->core->poll(ticket) : -2;
+        if (st == -2)
             fail(LILAC_ERR_ARG, "unknown ticket");
-        *done = it->second;
+        *done = st;
     });
 }
 
@@ -889,13 +775,11 @@ int lilac_server_wait(lilac_server_t hs, uint64_t ticket)
     return sguard([&] {
         if (!S)
             fail(LILAC_ERR_ARG, "bad argument");
-        std::unique_lock<std::mutex> lk(S->mu);
-        auto it = S->status.find(ticket);
-        if (it == S->status.end())
+        const int st = S->core ? S->core->wait(ticket) : -2;
+        if (st == -2)
             fail(LILAC_ERR_ARG, "unknown ticket");
-        S->done_cv.wait(lk, [&] { return S->status[ticket] != 0; });
-        if (S->status[ticket] < 0)
-            fail(LILAC_ERR_STATE, "request failed: " + S->err);
+        if (st < 0)
+            fail(LILAC_ERR_STATE, "request failed: " + S->core->error());
     });
 }
 
@@ -915,6 +799,7 @@ int lilac_server_stats_get(lilac_server_t hs, lilac_server_stats *out)
     return sguard([&] {
         if (!S || !out)
             fail(LILAC_ERR_ARG, "bad argument");
+        start(S);
         fill_stats(S, out);
     });
 }
@@ -925,11 +810,10 @@ int lilac_server_reset_stats(lilac_server_t hs)
     return sguard([&] {
         if (!S)
             fail(LILAC_ERR_ARG, "bad argument");
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->lat_us.clear();
-        S->n_spmv = S->n_cg = S->n_failed = S->n_uploads = S->n_evict = S->n_ticks = 0;
-        S->bytes_done = 0.0;
-        S->t_first = S->t_last = 0;
+        start(S);
+        S->core->reset_stats();
+        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+        S->acct.peak = S->acct.in_use;
     });
 }
 
@@ -943,9 +827,14 @@ int lilac_server_run_trace(lilac_server_t hs, int n, const int64_t *arrival_ns,
             fail(LILAC_ERR_ARG, "bad argument");
         for (int i = 0; i < n; ++i)
             if (matrix[i] < 0 || matrix[i] >= (int)S->mats.size() ||
-                (kind[i] != LILAC_REQ_SPMV && kind[i] != LILAC_REQ_CG))
+                (kind[i] != LILAC_REQ_SPMV && kind[i] != LILAC_REQ_CG) ||
+                (kind[i] == LILAC_REQ_CG &&
+                 S->mats[(size_t)matrix[i]].rows != S->mats[(size_t)matrix[i]].cols))
                 fail(LILAC_ERR_ARG, "bad request in trace");
-        lilac_server_reset_stats(hs);
+        start(S);
+        if (S->core->dead())
+            fail(LILAC_ERR_STATE, "server stopped after an error: " + S->core->error());
+        S->core->reset_stats();
         std::vector<uint64_t> tickets((size_t)n);
         const int64_t t0 = now_ns() + 1000000;  // start 1 ms from now
         for (int i = 0; i < n; ++i) {
@@ -955,28 +844,18 @@ int lilac_server_run_trace(lilac_server_t hs, int n, const int64_t *arrival_ns,
                 std::this_thread::sleep_for(std::chrono::nanoseconds(due - t - 100000));
             while ((t = now_ns()) < due) {
             }
-            auto *q = new Req();
+            auto *q = new serve::Request();
             q->kind = kind[i];
             q->mid = matrix[i];
             q->iters = cg_iters;
             q->t_arr = due;
-            // trace mode: the matrix's own vectors (attached at admission)
-            q->in = nullptr;
-            q->out = nullptr;
-            std::lock_guard<std::mutex> lk(S->mu);
-            q->ticket = S->next_ticket++;
-            S->status[q->ticket] = 0;
-            S->incoming.push_back(q);
-            tickets[(size_t)i] = q->ticket;
-            S->cv.notify_one();
+            // trace mode: the server's operand and the slot's own output
+            tickets[(size_t)i] = S->core->submit(q);
         }
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            for (uint64_t tkt : tickets)
-                S->done_cv.wait(lk, [&] { return S->status[tkt] != 0; });
-            for (uint64_t tkt : tickets)
-                S->status.erase(tkt);
-        }
+        for (uint64_t tkt : tickets)
+            S->core->wait(tkt);
+        for (uint64_t tkt : tickets)
+            S->core->forget(tkt);
         if (out)
             fill_stats(S, out);
     });
@@ -989,39 +868,25 @@ int lilac_server_destroy(lilac_server_t hs)
         if (!S)
             return;
         S->stop.store(true);
-        S->cv.notify_all();
-        S->up_cv.notify_all();
-        if (S->sched.joinable())
-            S->sched.join();
-        if (S->uploader.joinable())
-            S->uploader.join();
+        if (S->started.load()) {
+            {
+                std::lock_guard<std::mutex> lk(S->up_mu);
+                S->up_cv.notify_all();
+            }
+            S->core->wake();
+            if (S->sched.joinable())
+                S->sched.join();
+            for (auto &u : S->uploader) {
+                {
+                    std::lock_guard<std::mutex> lk(S->up_mu);
+                    S->up_cv.notify_all();
+                }
+                if (u.joinable())
+                    u.join();
+            }
+        }
         (void)hipStreamSynchronize(S->stream);
-        std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-        for (auto &d : S->up_done)   // uploads that finished after the stop
-            destroy_handle(d.second);
-        for (auto &m : S->mats) {
-            if (m.h)
-                destroy_handle(m.h);
-            dev_free(m.vin);
-            dev_free(m.vout);
-            if (m.pin)
-                (void)hipHostFree(m.pin);
-        }
-        for (auto &sl : S->slots)
-            free_slot_mem(sl);
-        for (auto &t : S->ticks) {
-            if (t.host)
-                (void)hipHostFree(t.host);
-            dev_free(t.dev);
-            (void)hipEventDestroy(t.ev);
-        }
-        for (auto *r : S->waiting)
-            delete r;
-        for (auto *r : S->incoming)
-            delete r;
-        (void)hipStreamDestroy(S->stream);
-        (void)hipStreamDestroy(S->up_stream);
-        delete S;
+        free_server(S);
     });
 }
 

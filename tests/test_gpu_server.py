@@ -144,3 +144,55 @@ def test_trace_replay_small():
     assert st["cg_done"] == int(kind.sum())
     assert st["p99_us"] >= st["p50_us"] > 0 and st["req_per_s"] > 0
     S.destroy()
+
+
+def test_budget_pressure_peak_within_budget():
+    """A pool whose resident copies need more than a 1 GiB budget: uploads
+    wait for idle matrices to be evicted, the server's real device bytes
+    (its allocator account: matrices, slots, tables) never pass the budget,
+    and every result equals the same request run alone and the oracle."""
+    budget = 1 << 30
+    mats = [gen.spd_random(60000, 100, seed=11 + i) for i in range(4)]
+    mats += [gen.stencil(40, 27), gen.stencil(36, 7),
+             gen.random_rows(200000, 5, 60, seed=15), gen.random_rows(120000, 5, 60, seed=16)]
+    spd = [True] * 6 + [False] * 2
+    S = L.Server(hbm_budget=budget)
+    ids = [S.add_matrix(A) for A in mats]
+    iters = 15
+    reqs = []
+    for A, mid, s in zip(mats, ids, spd):
+        reqs.append((L.REQ_SPMV, mid, A, gen.vector(A.cols, 400 + mid)))
+        if s:
+            reqs.append((L.REQ_CG, mid, A, gen.vector(A.rows, 500 + mid)))
+    alone = _run(S, reqs, iters, together=False)
+    order = list(range(len(reqs)))
+    np.random.default_rng(7).shuffle(order)
+    mixed = _run(S, [reqs[i] for i in order], iters, together=True)
+    st = S.stats()
+    assert st["failed"] == 0 and st["completed"] == 2 * len(reqs)
+    assert st["evictions"] > 0
+    assert 0 < st["peak_device_bytes"] <= budget, st
+    assert st["planned_peak_bytes"] <= budget, st
+    for k, i in enumerate(order):
+        assert np.array_equal(mixed[k], alone[i]), i
+    for (kind, mid, A, v), y in zip(reqs, alone):
+        if kind == L.REQ_SPMV:
+            check_spmv(A, v, y, TOL_F64)
+        else:
+            x_or, _, _ = oracle.cg(A.row_ptr, A.col_idx, A.vals, v, iters)
+            assert np.max(np.abs(y - x_or)) <= 1e-10 * np.max(np.abs(x_or))
+    S.destroy()
+
+
+def test_trace_mode_cg_outputs_do_not_share():
+    """Trace-mode requests (no caller vectors) write into their own slot's
+    vector: two CG requests on one matrix in flight together both run
+    (regression: they once shared one output vector)."""
+    A = gen.spd_random(20000, 30, seed=21)
+    S = L.Server()
+    mid = S.add_matrix(A)
+    st = S.run_trace(np.array([0, 1000, 2000, 3000]), np.array([1, 1, 1, 0]),
+                     np.array([mid] * 4), 40)
+    assert st["completed"] == 4 and st["failed"] == 0 and st["cg_done"] == 3
+    assert st["peak_device_bytes"] > 0
+    S.destroy()
