@@ -258,6 +258,25 @@ int lilac_cg(lilac_csr_t h, const double *b, double *x, int iters,
              unsigned flags, void *stream, double *rho_out, int *iters_done);
 
 /*
+ * The same conjugate gradient as lilac_cg (eager, identical kernels and
+ * reduction shapes, so x is bitwise what lilac_cg without LILAC_CG_GRAPH
+ * gives), for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  It
+ * allocates nothing: the solver state (r, p, q, partial sums, scalars) lives
+ * in one fixed device array of the library, about 24 MiB per GPU, held from
+ * the library's set-up until the process ends, which limits the matrix to
+ * at most 1048576 rows (LILAC_ERR_ARG beyond).  The handle must be up to
+ * date: after lilac_csr_invalidate it is refused with LILAC_ERR_STATE until
+ * a call that may allocate (lilac_spmv, lilac_cg ...) has re-uploaded the
+ * matrix (lilac_csr_update_values uploads at once).  b and x are device arrays of
+ * rows doubles.  Every call on one GPU shares that array, so calls that
+ * overlap on one GPU (other streams, other threads, other handles) race and
+ * must be ordered by the caller; each call initialises all of the state it
+ * reads.  Async on `stream` (NULL: HIP's null stream).
+ */
+int lilac_cg_noalloc(lilac_csr_t h, const double *b, double *x, int iters, void *stream);
+
+/*
  * PageRank power iteration on a pull-direction F32 handle (rows are
  * destinations, vals[k] = 1/outdeg of the source), the repeated product of
  * the paper's PageRank graph kernel (section "Results", graph kernels):

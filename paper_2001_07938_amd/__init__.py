@@ -92,6 +92,7 @@ _SIGS = {
     "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
     "lilac_spmv_jds": ([_I, _I, _P, _P, _P, _P, _P, _P, _P], _I),
     "lilac_csr_to_jds": ([_P, _P, _P, _P, _I, _P, _P, _P, _P], _I),
+    "lilac_cg_noalloc": ([_P, _P, _P, _I, _P], _I),
 }
 
 _lib = None
@@ -347,6 +348,12 @@ class Csr:
                               ctypes.addressof(rho) if want_result else None,
                               ctypes.addressof(it) if want_result else None))
         return (rho.value, it.value) if want_result else None
+
+    def cg_noalloc(self, b, x, iters: int, stream=None):
+        """CG with the solver state in the library's fixed device array (no
+        allocation); async."""
+        _check(lib().lilac_cg_noalloc(self.handle, _ptr(b), _ptr(x), iters,
+                                      _stream(stream)))
 
     def pagerank(self, damping: float, iters: int, x, stream=None):
         _check(lib().lilac_pagerank(self.handle, float(damping), iters, _ptr(x),

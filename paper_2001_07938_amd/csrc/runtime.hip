@@ -108,6 +108,8 @@ static void at_exit_hook()
     marshal_reset();
 }
 
+static char *scratch_on_current_device();
+
 static Context &init_ctx(int device)
 {
     if (g_ctx)
@@ -132,6 +134,7 @@ static Context &init_ctx(int device)
     c->cu = prop.multiProcessorCount;
     HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPC(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    (void)scratch_on_current_device();  // the fixed CG state's address
     if (const char *b = std::getenv("LILAC_HBM_BUDGET"))
         c->budget = parse_bytes(b);
     g_ctx = c;
@@ -1375,6 +1378,48 @@ static void cg_enqueue(const CsrHandle &h, const double *b, double *x,
     cg_enqueue_state(h, b, x, iters, st.r, st.p, st.q, st.part, st.sc, s);
 }
 
+// ------------------------------------------------ CG without allocation
+//
+// For callers that cannot allocate device memory (work under HIP graph
+// capture, tight serving loops): the CG state (r, p, q, the r.r partials
+// and the scalars) lives in one fixed device array instead of the handle's
+// state, which is allocated on first use.  The array holds the state of a
+// matrix of at most kNoAllocRows rows; every GPU the library runs on keeps
+// its own copy until the process ends.  In host code `scratch` is only a
+// stand-in for the symbol: its device address, per device, comes from
+// hipGetSymbolAddress and only that address is handed to kernels.
+constexpr int64_t kNoAllocRows = 1 << 20;
+constexpr size_t kNoAllocPart = 2 * kDotParts;
+constexpr size_t kNoAllocBytes =
+    3 * (size_t)kNoAllocRows * 8 + kNoAllocPart * 8 + sizeof(CgScalars);
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+static char *scratch_on_current_device()
+{
+    int dev = -1;
+    HIPC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        fail(LILAC_ERR_DEVICE, "device index beyond the fixed-state table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            fail(LILAC_ERR_DEVICE, std::string("hipGetSymbolAddress of the fixed CG "
+                                               "state failed: ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 template <typename Enq>
 static void capture(hipGraph_t &graph, hipGraphExec_t &exec, Enq enq)
 {
@@ -2392,6 +2437,41 @@ int lilac_cg(lilac_csr_t hh, const double *b, double *x, int iters,
         if (!h)
             fail(LILAC_ERR_ARG, "NULL handle");
         run_cg(*h, b, x, iters, flags, pick_stream(stream), rho_out, iters_done);
+    });
+}
+
+int lilac_cg_noalloc(lilac_csr_t hh, const double *b, double *x, int iters, void *stream)
+{
+    return guard([&] {
+        CsrHandle *h = (CsrHandle *)hh;
+        if (!h)
+            fail(LILAC_ERR_ARG, "NULL handle");
+        if (h->dt != LILAC_F64)
+            fail(LILAC_ERR_UNSUPPORTED, "CG needs a float64 handle");
+        if (h->rows != h->cols)
+            fail(LILAC_ERR_ARG, "CG needs a square matrix");
+        if (iters < 0)
+            fail(LILAC_ERR_ARG, "iters must be >= 0");
+        if ((int64_t)h->rows > kNoAllocRows)
+            fail(LILAC_ERR_ARG, "matrix has " + std::to_string(h->rows) +
+                                    " rows; the fixed CG state holds at most " +
+                                    std::to_string(kNoAllocRows));
+        if (h->dirty_struct || h->dirty_vals)
+            fail(LILAC_ERR_STATE, "handle has pending updates; bring it up to date "
+                                  "with a call that may allocate first");
+        if (h->rows == 0)
+            return;
+        if (!b || !x)
+            fail(LILAC_ERR_ARG, "b or x is NULL");
+        if (!is_device_ptr(b) || !is_device_ptr(x))
+            fail(LILAC_ERR_ARG, "b and x must be device arrays");
+        char *base = scratch_on_current_device();
+        double *r = (double *)base;
+        double *p = r + kNoAllocRows;
+        double *q = p + kNoAllocRows;
+        double *part = q + kNoAllocRows;
+        CgScalars *sc = (CgScalars *)(part + kNoAllocPart);
+        cg_enqueue_state(*h, b, x, iters, r, p, q, part, sc, (hipStream_t)stream);
     });
 }
 
