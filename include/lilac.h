@@ -313,6 +313,21 @@ int lilac_csr_tune(lilac_csr_t h, double *best_us);
  * LILAC_ERR_ARG if it does not fit. */
 int lilac_csr_tune_class(lilac_csr_t h, char *buf, int cap);
 
+/* ---- measurement -------------------------------------------------------- */
+/*
+ * The device's streaming ceiling, written for this library rather than
+ * borrowed: reads `bytes` of src once with non-temporal 16-byte loads (eight
+ * per thread in flight), and with dst != NULL also stores them there (a
+ * copy).  groups_per_cu workgroups of 256 threads per compute unit, each
+ * streaming one contiguous range.  Benchmarks time it beside the products
+ * to quote their bandwidth against what the part delivers as well as
+ * against its nominal peak.  src, dst: device, 16-byte aligned; bytes a
+ * multiple of 16.  Async on `stream` (NULL: HIP's null stream).
+ * Errors: LILAC_ERR_ARG.
+ */
+int lilac_hbm_stream(const void *src, void *dst, int64_t bytes, int groups_per_cu,
+                     void *stream);
+
 /* ---- 64-bit row offsets ------------------------------------------------ */
 
 /*

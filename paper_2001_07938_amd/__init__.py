@@ -19,7 +19,7 @@ import torch  # noqa: F401  (shares its HIP runtime with the library)
 __all__ = [
     "LilacError", "lib", "lilac_spmv_csr", "lilac_spmv_csr_f32", "lilac_dot",
     "lilac_invalidate", "lilac_release_all", "lilac_init", "lilac_finalize",
-    "lilac_dot_dev", "lilac_spmv_batched", "Csr", "Csr64", "F64", "F32",
+    "lilac_dot_dev", "lilac_spmv_batched", "lilac_hbm_stream", "Csr", "Csr64", "F64", "F32",
     "KEEP_HOST", "CG_GRAPH", "NCLASS", "HEADER_FUNCTIONS",
 ]
 
@@ -89,6 +89,7 @@ _SIGS = {
     "lilac_csr64_destroy": ([_P], _I),
     "lilac_csr_tune": ([_P, _P], _I),
     "lilac_csr_tune_class": ([_P, ctypes.c_char_p, _I], _I),
+    "lilac_hbm_stream": ([_P, _P, _I64, _I, _P], _I),
     "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
     "lilac_spmv_jds": ([_I, _I, _P, _P, _P, _P, _P, _P, _P], _I),
     "lilac_csr_to_jds": ([_P, _P, _P, _P, _I, _P, _P, _P, _P], _I),
@@ -224,6 +225,12 @@ def lilac_dot_dev(n: int, a, b, out, dtype: int = None, stream=None):
     if dtype is None:
         dtype = F32 if _elem_size(out) == 4 else F64
     _check(lib().lilac_dot_dev(n, _ptr(a), _ptr(b), _ptr(out), dtype, _stream(stream)))
+
+
+def lilac_hbm_stream(src, nbytes: int, dst=None, groups_per_cu: int = 8, stream=None):
+    """Streams nbytes of device memory (read, or copy into dst)."""
+    _check(lib().lilac_hbm_stream(_ptr(src), _ptr(dst), nbytes, groups_per_cu,
+                                  _stream(stream)))
 
 
 def lilac_invalidate(ptr):

@@ -1979,6 +1979,43 @@ __global__ __launch_bounds__(1024) void k_sum_parts(
         *out = (TOut)t;
 }
 
+// HBM stream ceiling: every 16-byte piece of src read once with
+// non-temporal loads, U pieces per thread in flight; with dst, each piece is
+// also stored there (a copy).  The read-only form folds the data into a
+// value that is stored only if it equals a constant nothing in practice
+// produces, so the loads stay.  Workgroup g streams the contiguous range of
+// pieces [g * per, (g + 1) * per).
+template <int U, bool COPY>
+__global__ __launch_bounds__(kBlock) void k_stream(const i32x4 *__restrict__ src,
+                                                   i32x4 *__restrict__ dst, int64_t n,
+                                                   int64_t per, uint32_t *__restrict__ sink)
+{
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = min(n, lo + per);
+    int32_t fold = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += (int64_t)U * kBlock) {
+        i32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = i + (int64_t)u * kBlock;
+            v[u] = (k < hi) ? ld_stream(src + k) : i32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = i + (int64_t)u * kBlock;
+            if (COPY) {
+                if (k < hi)
+                    __builtin_nontemporal_store(
+                        v[u], (__attribute__((address_space(1))) i32x4 *)(dst + k));
+            } else {
+                fold ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+            }
+        }
+    }
+    if (!COPY && fold == (int32_t)0x9E3779B9)
+        sink[0] = (uint32_t)fold;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy(int64_t n,
                                                  const T *__restrict__ src,
@@ -2730,6 +2767,22 @@ void launch_sum_parts_f32(const double *part, int32_t nparts, float *out,
     hipLaunchKernelGGL(k_sum_parts<float>, dim3(1), dim3(1024), 0, s, part, nparts,
                        out);
     check_launch("k_sum_parts");
+}
+
+void launch_stream(const void *src, void *dst, int64_t bytes, int32_t groups,
+                   uint32_t *sink, hipStream_t s)
+{
+    const int64_t n = bytes / 16;
+    if (n <= 0)
+        return;
+    const int64_t per = (n + groups - 1) / groups;
+    if (dst)
+        hipLaunchKernelGGL((k_stream<4, true>), dim3(groups), dim3(kBlock), 0, s,
+                           (const i32x4 *)src, (i32x4 *)dst, n, per, sink);
+    else
+        hipLaunchKernelGGL((k_stream<8, false>), dim3(groups), dim3(kBlock), 0, s,
+                           (const i32x4 *)src, (i32x4 *)nullptr, n, per, sink);
+    check_launch("k_stream");
 }
 
 void launch_copy_f64(int64_t n, const double *src, double *dst, hipStream_t s)

@@ -278,6 +278,9 @@ int device_cu_count();
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_bytes_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+// HBM stream ceiling (read, or copy when dst is set) over bytes/16 pieces.
+void launch_stream(const void *src, void *dst, int64_t bytes, int32_t groups,
+                   uint32_t *sink, hipStream_t s);
 void launch_validate(int32_t rows, const int32_t *rp, int64_t nnz,
                      const int32_t *col, int32_t cols_given, int32_t *status,
                      hipStream_t s);

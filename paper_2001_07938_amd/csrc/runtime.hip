@@ -2791,6 +2791,22 @@ int lilac_csr_to_jds(lilac_csr_t hh, int *perm, int *nzcnt, int *jd_ptr, int jd_
     });
 }
 
+int lilac_hbm_stream(const void *src, void *dst, int64_t bytes, int groups_per_cu,
+                     void *stream)
+{
+    return guard([&] {
+        if (!src || bytes < 0 || (bytes & 15) || (((uintptr_t)src | (uintptr_t)dst) & 15))
+            fail(LILAC_ERR_ARG, "src (and dst) must be 16-byte aligned, bytes a multiple of 16");
+        if (groups_per_cu < 1 || groups_per_cu > 64)
+            fail(LILAC_ERR_ARG, "groups_per_cu must be in [1, 64]");
+        if (!is_device_ptr(src) || (dst && !is_device_ptr(dst)))
+            fail(LILAC_ERR_ARG, "src and dst must be device memory");
+        Context &c = ctx();
+        launch_stream(src, dst, bytes, c.cu * groups_per_cu, (uint32_t *)c.total,
+                      pick_stream(stream));
+    });
+}
+
 int lilac_csr_tune_class(lilac_csr_t hh, char *buf, int cap)
 {
     return guard([&] {

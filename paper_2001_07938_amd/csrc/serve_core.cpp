@@ -31,11 +31,13 @@ Core::~Core()
         delete r;
     for (Request *r : incoming_)
         delete r;
-    for (Request *r : active_)
-        delete r;
-    for (auto &f : finishing_)
-        for (Request *r : f)
+    for (auto &act : active_)
+        for (Request *r : act)
             delete r;
+    for (auto &lane : finishing_)
+        for (auto &f : lane)
+            for (Request *r : f)
+                delete r;
 }
 
 int Core::add_matrix(int64_t spmv_bytes, int64_t cg_iter_bytes)
@@ -397,24 +399,34 @@ void Core::finish(Request *r, int64_t t)
     delete r;
 }
 
-void Core::complete(int tick)
+void Core::complete(int lane, int tick)
 {
-    if (!pending_[tick])
+    if (!pending_[lane][tick])
         return;
-    ex_.wait_tick(tick);
+    ex_.wait_tick(lane, tick);
     const int64_t t = ex_.now_ns();
-    for (Request *r : finishing_[tick])
+    for (Request *r : finishing_[lane][tick])
         finish(r, t);
-    finishing_[tick].clear();
-    pending_[tick] = false;
+    finishing_[lane][tick].clear();
+    pending_[lane][tick] = false;
 }
 
-void Core::launch_and_rotate()
+// Launches the lane's next tick if its tick buffer is free (a lane keeps at
+// most two ticks on the device, so the next one is queued behind the
+// running one).
+bool Core::launch(int lane)
 {
-    const int tk = tick_no_ & 1;
-    complete(tk);   // its buffers are about to be reused
-    ex_.launch_tick(tk, active_);
-    pending_[tk] = true;
+    std::vector<Request *> &act = active_[lane];
+    if (act.empty())
+        return false;
+    const int tk = tick_no_[lane] & 1;
+    if (pending_[lane][tk]) {
+        if (!ex_.tick_done(lane, tk))
+            return false;
+        complete(lane, tk);
+    }
+    ex_.launch_tick(lane, tk, act);
+    pending_[lane][tk] = true;
     {
         std::lock_guard<std::mutex> lk(mu_);
         n_ticks_ += 1;
@@ -422,7 +434,7 @@ void Core::launch_and_rotate()
     // requests whose last step is in this tick leave the active set now;
     // they finish when the tick does
     std::vector<Request *> still;
-    for (Request *r : active_) {
+    for (Request *r : act) {
         if (r->kind == kCg) {
             r->iter += 1;
             if (r->iter < r->iters) {
@@ -430,12 +442,19 @@ void Core::launch_and_rotate()
                 continue;
             }
         }
-        finishing_[tk].push_back(r);
+        finishing_[lane][tk].push_back(r);
     }
-    active_.swap(still);
-    tick_no_ += 1;
-    // one tick stays in flight: the previous one is finished now
-    complete(tick_no_ & 1);
+    act.swap(still);
+    tick_no_[lane] += 1;
+    return true;
+}
+
+bool Core::busy() const
+{
+    for (int l = 0; l < kLanes; ++l)
+        if (pending_[l][0] || pending_[l][1])
+            return true;
+    return false;
 }
 
 bool Core::step()
@@ -443,6 +462,13 @@ bool Core::step()
     take_incoming();
     collect_uploads();
     bool worked = false;
+    // ticks that are over give their requests back
+    for (int l = 0; l < kLanes; ++l)
+        for (int t = 0; t < 2; ++t)
+            if (pending_[l][t] && ex_.tick_done(l, t)) {
+                complete(l, t);
+                worked = true;
+            }
     // admission in arrival order; a request whose matrix is not resident
     // does not hold up the ones behind it
     for (auto it = waiting_.begin(); it != waiting_.end();) {
@@ -478,7 +504,7 @@ bool Core::step()
             finish(r, ex_.now_ns());
             return true;  // one request per round
         }
-        if ((int)active_.size() >= lim_.max_active)
+        if (active() >= lim_.max_active)
             break;
         if (!get_slot(r))
             break;
@@ -486,19 +512,13 @@ bool Core::step()
         m.queued -= 1;
         m.prev_use = m.last_use;
         m.last_use = ++use_clock_;
-        active_.push_back(r);
+        active_[ex_.lane_of(r->mid)].push_back(r);
         it = waiting_.erase(it);
         worked = true;
     }
-    if (!active_.empty()) {
-        launch_and_rotate();
-        return true;
-    }
-    if (pending_[0] || pending_[1]) {
-        complete(0);
-        complete(1);
-        return true;
-    }
+    for (int l = 0; l < kLanes; ++l)
+        if (launch(l))
+            worked = true;
     return worked;
 }
 
@@ -528,10 +548,14 @@ void Core::shutdown()
         finish(r, ex_.now_ns());
     }
     waiting_.clear();
-    while (!active_.empty())
-        launch_and_rotate();
-    complete(0);
-    complete(1);
+    for (int l = 0; l < kLanes; ++l) {
+        while (!active_[l].empty()) {
+            if (!launch(l))
+                complete(l, tick_no_[l] & 1);   // wait for the buffer, then launch
+        }
+        complete(l, 0);
+        complete(l, 1);
+    }
 }
 
 void Core::die(const std::string &msg)

@@ -13,6 +13,11 @@
 // device once and reused until it has to go) applied to a stream of
 // independent requests instead of one program's call sites.
 //
+// Requests run in two lanes, each with its own ticks (on its own device
+// stream in the library): matrices whose one product is long go to the
+// heavy lane, the rest to the light lane, so that a short request never
+// waits out the long product of another request's tick.
+//
 // Threads: one scheduler thread calls step(); any thread may call submit,
 // poll, wait, stats; executor threads report finished uploads through
 // upload_done.  Scheduler-only state is touched by step() alone.
@@ -33,6 +38,7 @@ namespace serve {
 
 constexpr int kSpmv = 0;
 constexpr int kCg = 1;
+constexpr int kLanes = 2;   // 0: light, 1: heavy
 
 struct Request {
     uint64_t ticket = 0;
@@ -80,11 +86,16 @@ class Executor {
     virtual void prepare_slot(int slot, int mid) = 0;
     // Frees an unused slot's memory.  Blocking.
     virtual void release_slot(int slot) = 0;
-    // Enqueues one batched step over `reqs`: the product of every SpMV
-    // request and one iteration of every CG request (iteration r->iter).
-    virtual void launch_tick(int tick, const std::vector<Request *> &reqs) = 0;
-    // Blocks until tick `tick` has finished on the device.
-    virtual void wait_tick(int tick) = 0;
+    // Lane of a matrix's requests (0 light, 1 heavy).
+    virtual int lane_of(int mid) = 0;
+    // Enqueues one batched step of a lane over `reqs`: the product of every
+    // SpMV request and one iteration of every CG request (iteration
+    // r->iter).  A lane has two tick buffers (tick 0 and 1), used in turn.
+    virtual void launch_tick(int lane, int tick, const std::vector<Request *> &reqs) = 0;
+    // Whether a launched tick has finished on the device (non-blocking).
+    virtual bool tick_done(int lane, int tick) = 0;
+    // Blocks until it has.
+    virtual void wait_tick(int lane, int tick) = 0;
     // The plain path: runs the whole request alone.  Blocking.
     virtual void run_one(Request *r) = 0;
 };
@@ -116,9 +127,12 @@ class Core {
 
     // ---- scheduler thread ----
     // One scheduling round: take new requests and finished uploads, admit,
-    // launch a tick (finishing the previous one).  Returns false when there
-    // was nothing to do.
+    // finish the ticks that are done, launch a tick in every lane that has
+    // active requests and a free tick buffer.  Returns false when there was
+    // nothing to do.
     bool step();
+    // Whether a tick is still running (the scheduler should poll again soon).
+    bool busy() const;
     // Waits (real time) until a request or an upload result arrives.
     void wait_for_work(int64_t max_ns);
     // Wakes a scheduler blocked in wait_for_work.
@@ -133,7 +147,7 @@ class Core {
     int64_t planned_bytes() const { return charged_; }
     int64_t planned_peak() const { return peak_; }
     int resident() const { return resident_; }
-    int active() const { return (int)active_.size(); }
+    int active() const { return (int)(active_[0].size() + active_[1].size()); }
     int waiting() const { return (int)waiting_.size(); }
     int uploading() const;
     bool is_resident(int mid) const;
@@ -170,8 +184,8 @@ class Core {
     bool get_slot(Request *r);
     void finish(Request *r, int64_t t);
     void fail_waiting_on(int mid, const std::string &why);
-    void launch_and_rotate();
-    void complete(int tick);
+    bool launch(int lane);
+    void complete(int lane, int tick);
     void collect_uploads();
     void take_incoming();
     void bump_peak();
@@ -182,10 +196,10 @@ class Core {
     std::vector<Slot> slots_;
     std::vector<int> free_slots_;
     std::deque<Request *> waiting_;
-    std::vector<Request *> active_;
-    std::vector<Request *> finishing_[2];
-    bool pending_[2] = {false, false};
-    int tick_no_ = 0;
+    std::vector<Request *> active_[kLanes];
+    std::vector<Request *> finishing_[kLanes][2];
+    bool pending_[kLanes][2] = {{false, false}, {false, false}};
+    int tick_no_[kLanes] = {0, 0};
     int64_t charged_ = 0, peak_ = 0;
     int resident_ = 0;
     uint64_t use_clock_ = 0;

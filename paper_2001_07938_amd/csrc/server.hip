@@ -12,7 +12,11 @@
 //    its own whose limit is the upload's reserve, under the server's account
 //    whose limit is the budget, so the budget is a hard bound, the reserve
 //    is checked, and what a resident matrix holds is known exactly;
-//  - a tick is ONE grouped product over every active request (y = A x for
+//  - requests run in two lanes with a stream each: matrices of at least
+//    kHeavyNnz non-zeros (one product alone takes tens of microseconds) in
+//    the heavy lane, the others in the light lane, so a short request never
+//    waits out a long product in its tick;
+//  - a tick is ONE grouped product over every active request of a lane (y = A x for
 //    SpMV requests, q = A p for the next iteration of every active CG
 //    request; row-class tiles, column panels and band blocks each in one
 //    launch), then three batched kernels that advance every CG by one
@@ -43,6 +47,7 @@ int64_t now_ns()
 }
 
 constexpr int kUploadThreads = 2;
+constexpr int64_t kHeavyNnz = 1 << 23;
 
 struct SMatrix {
     int rows = 0, cols = 0;
@@ -94,8 +99,10 @@ class HipExec : public serve::Executor {
     int64_t slot_need(int slot, int mid) override;
     void prepare_slot(int slot, int mid) override;
     void release_slot(int slot) override;
-    void launch_tick(int tick, const std::vector<serve::Request *> &reqs) override;
-    void wait_tick(int tick) override;
+    int lane_of(int mid) override;
+    void launch_tick(int lane, int tick, const std::vector<serve::Request *> &reqs) override;
+    bool tick_done(int lane, int tick) override;
+    void wait_tick(int lane, int tick) override;
     void run_one(serve::Request *r) override;
 
   private:
@@ -106,11 +113,11 @@ struct Server {
     lilac_server_config cfg{};
     bool fifo = false;
     int max_rows = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream[serve::kLanes] = {};
     hipStream_t up_stream[kUploadThreads] = {};
     std::vector<SMatrix> mats;
     std::vector<Slot> slots;
-    TickBuf ticks[2];
+    TickBuf ticks[serve::kLanes][2];
     Account acct;                  // the server's own: limit = budget
     HipExec exec{this};
     serve::Core *core = nullptr;
@@ -320,12 +327,26 @@ void HipExec::release_slot(int slot)
     sl = Slot();
 }
 
-void HipExec::wait_tick(int tick) { HIPC(hipEventSynchronize(S->ticks[tick].ev)); }
+int HipExec::lane_of(int mid) { return S->mats[(size_t)mid].nnz >= kHeavyNnz ? 1 : 0; }
 
-// One batched tick over every active request.
-void HipExec::launch_tick(int tick, const std::vector<serve::Request *> &reqs)
+bool HipExec::tick_done(int lane, int tick)
 {
-    TickBuf &tk = S->ticks[tick];
+    const hipError_t e = hipEventQuery(S->ticks[lane][tick].ev);
+    if (e == hipErrorNotReady)
+        return false;
+    HIPC(e);
+    return true;
+}
+
+void HipExec::wait_tick(int lane, int tick)
+{
+    HIPC(hipEventSynchronize(S->ticks[lane][tick].ev));
+}
+
+// One batched tick over every active request of a lane.
+void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *> &reqs)
+{
+    TickBuf &tk = S->ticks[lane][tick];
     std::vector<MatDesc> descs;
     std::vector<int32_t> prefix(1, 0);
     std::vector<CgSeg> init, step;
@@ -441,7 +462,7 @@ void HipExec::launch_tick(int tick, const std::vector<serve::Request *> &reqs)
     const size_t o_bdesc = put(bdesc.data(), b_bdesc, b_bdesc);
     const size_t o_bio = put(bio.data(), b_bio, b_bio);
     const size_t o_bpre = put(bprefix.data(), bprefix.size() * 4, b_bpre);
-    hipStream_t s = S->stream;
+    hipStream_t s = S->stream[lane];
     HIPC(hipMemcpyAsync(tk.dev, tk.host, off, hipMemcpyHostToDevice, s));
     const MatDesc *d_desc = (const MatDesc *)(tk.dev + o_desc);
     if (!init.empty())
@@ -495,20 +516,20 @@ void HipExec::run_one(serve::Request *r)
     const double *in = r->in ? (const double *)r->in : m.vin;
     double *out = r->out ? (double *)r->out : sl.x;
     if (r->kind == serve::kSpmv) {
-        spmv_enqueue(*m.h, in, out, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, S->stream);
+        spmv_enqueue(*m.h, in, out, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, S->stream[0]);
     } else {
         // the CG state was made at upload, under the matrix's account
         thread_account() = &m.acct;
         try {
             std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-            run_cg(*m.h, in, out, r->iters, LILAC_CG_GRAPH, S->stream, nullptr, nullptr);
+            run_cg(*m.h, in, out, r->iters, LILAC_CG_GRAPH, S->stream[0], nullptr, nullptr);
         } catch (...) {
             thread_account() = &S->acct;
             throw;
         }
         thread_account() = &S->acct;
     }
-    HIPC(hipStreamSynchronize(S->stream));
+    HIPC(hipStreamSynchronize(S->stream[0]));
 }
 
 // ------------------------------------------------------------- threads
@@ -522,8 +543,10 @@ void scheduler_main(Server *S)
     thread_account() = &S->acct;
     try {
         while (!S->stop.load()) {
+            // with a tick on the device, look again soon (ticks end without
+            // waking the scheduler); otherwise sleep until work arrives
             if (!S->core->step())
-                S->core->wait_for_work(200000);
+                S->core->wait_for_work(S->core->busy() ? 20000 : 200000);
         }
         S->core->shutdown();
     } catch (const Error &e) {
@@ -579,18 +602,20 @@ void free_server(Server *S)
         dev_free(sl.done);
         dev_free(sl.chunk);
     }
-    for (auto &t : S->ticks) {
-        if (t.host)
-            (void)hipHostFree(t.host);
-        dev_free(t.dev);
-        if (t.ev)
-            (void)hipEventDestroy(t.ev);
-    }
+    for (auto &lane : S->ticks)
+        for (auto &t : lane) {
+            if (t.host)
+                (void)hipHostFree(t.host);
+            dev_free(t.dev);
+            if (t.ev)
+                (void)hipEventDestroy(t.ev);
+        }
     for (auto &us : S->up_stream)
         if (us)
             (void)hipStreamDestroy(us);
-    if (S->stream)
-        (void)hipStreamDestroy(S->stream);
+    for (auto &st : S->stream)
+        if (st)
+            (void)hipStreamDestroy(st);
     delete S->core;
     delete S;
 }
@@ -612,11 +637,12 @@ void start(Server *S)
         try {
             const size_t cap =
                 round256(64 + (size_t)S->cfg.max_active * (per_request_table_bytes() + 64));
-            for (auto &t : S->ticks) {
-                HIPC(hipHostMalloc((void **)&t.host, cap, hipHostMallocDefault));
-                t.dev = (char *)dev_alloc(cap);
-                t.cap = cap;
-            }
+            for (auto &lane : S->ticks)
+                for (auto &t : lane) {
+                    HIPC(hipHostMalloc((void **)&t.host, cap, hipHostMallocDefault));
+                    t.dev = (char *)dev_alloc(cap);
+                    t.cap = cap;
+                }
         } catch (...) {
             thread_account() = nullptr;
             throw;
@@ -678,11 +704,13 @@ int lilac_server_create(lilac_server_t *out, const lilac_server_config *cfg)
         S->fifo = S->cfg.fifo != 0;
         S->acct.limit = S->cfg.hbm_budget;
         try {
-            HIPC(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+            for (auto &st : S->stream)
+                HIPC(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
             for (auto &us : S->up_stream)
                 HIPC(hipStreamCreateWithFlags(&us, hipStreamNonBlocking));
-            for (auto &t : S->ticks)
-                HIPC(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));
+            for (auto &lane : S->ticks)
+                for (auto &t : lane)
+                    HIPC(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));
         } catch (...) {
             free_server(S);
             throw;
@@ -885,7 +913,9 @@ int lilac_server_destroy(lilac_server_t hs)
                     u.join();
             }
         }
-        (void)hipStreamSynchronize(S->stream);
+        for (auto &st : S->stream)
+            if (st)
+                (void)hipStreamSynchronize(st);
         free_server(S);
     });
 }

@@ -42,6 +42,7 @@ struct MatModel {
     int64_t final = 0;     // bytes the resident copy holds
     int64_t up_ns = 0;     // upload time
     int64_t work_ns = 0;   // one product (or one CG iteration) in a tick
+    int lane = 0;          // 0 light, 1 heavy
 };
 
 class SimExec : public Executor {
@@ -60,9 +61,9 @@ class SimExec : public Executor {
     std::vector<bool> uploading;
     std::vector<int64_t> slot_held;
     std::multimap<int64_t, int> up_events;   // completion time -> matrix
-    int64_t gpu_free_at = 0;                 // ticks run one after another
-    int64_t tick_end[2] = {0, 0};
-    std::set<int> tick_mats[2];              // matrices a pending tick reads
+    int64_t gpu_free_at[kLanes] = {0, 0};    // a lane's ticks run one after another
+    int64_t tick_end[kLanes][2] = {{0, 0}, {0, 0}};
+    std::set<int> tick_mats[kLanes][2];      // matrices a pending tick reads
     std::vector<int> evicted;
     int max_in_tick = 0, ticks = 0, fifo_runs = 0;
     bool violated = false;
@@ -110,9 +111,10 @@ class SimExec : public Executor {
     {
         if (!held[(size_t)mid])
             bad("eviction of a matrix that is not resident");
-        for (int k = 0; k < 2; ++k)
-            if (tick_end[k] > t && tick_mats[k].count(mid))
-                bad("eviction of a matrix a running tick reads");
+        for (int l = 0; l < kLanes; ++l)
+            for (int k = 0; k < 2; ++k)
+                if (tick_end[l][k] > t && tick_mats[l][k].count(mid))
+                    bad("eviction of a matrix a running tick reads");
         used -= held[(size_t)mid];
         held[(size_t)mid] = 0;
         evicted.push_back(mid);
@@ -130,29 +132,44 @@ class SimExec : public Executor {
         used -= slot_held[(size_t)slot];
         slot_held[(size_t)slot] = 0;
     }
-    void launch_tick(int tick, const std::vector<Request *> &reqs) override
+    int lane_of(int mid) override { return m[(size_t)mid].lane; }
+    void launch_tick(int lane, int tick, const std::vector<Request *> &reqs) override
     {
+        if (tick_end[lane][tick] > t)
+            bad("tick buffer reused while its tick runs");
         int64_t d = 2000;
-        tick_mats[tick].clear();
+        tick_mats[lane][tick].clear();
         for (Request *r : reqs) {
             if (!held[(size_t)r->mid])
                 bad("tick reads a matrix that is not resident");
             if (r->slot < 0 || r->slot >= (int)slot_held.size() || !slot_held[(size_t)r->slot])
                 bad("request without slot memory");
+            if (m[(size_t)r->mid].lane != lane)
+                bad("request in the wrong lane");
             d += m[(size_t)r->mid].work_ns;
-            tick_mats[tick].insert(r->mid);
+            tick_mats[lane][tick].insert(r->mid);
         }
-        gpu_free_at = std::max(gpu_free_at, t) + d;
-        tick_end[tick] = gpu_free_at;
+        gpu_free_at[lane] = std::max(gpu_free_at[lane], t) + d;
+        tick_end[lane][tick] = gpu_free_at[lane];
         max_in_tick = std::max(max_in_tick, (int)reqs.size());
         ticks += 1;
     }
-    void wait_tick(int tick) override
+    bool tick_done(int lane, int tick) override { return tick_end[lane][tick] <= t; }
+    void wait_tick(int lane, int tick) override
     {
-        if (tick_end[tick] > t) {
-            deliver(tick_end[tick]);
-            t = tick_end[tick];
+        if (tick_end[lane][tick] > t) {
+            deliver(tick_end[lane][tick]);
+            t = tick_end[lane][tick];
         }
+    }
+    int64_t next_tick_end() const
+    {
+        int64_t e = INT64_MAX;
+        for (int l = 0; l < kLanes; ++l)
+            for (int k = 0; k < 2; ++k)
+                if (tick_end[l][k] > t)
+                    e = std::min(e, tick_end[l][k]);
+        return e;
     }
     void run_one(Request *r) override
     {
@@ -194,6 +211,7 @@ static std::vector<uint64_t> simulate(Core &core, SimExec &ex, std::vector<Arriv
             tn = arr[next].t;
         if (!ex.up_events.empty())
             tn = std::min(tn, ex.up_events.begin()->first);
+        tn = std::min(tn, ex.next_tick_end());
         if (tn == INT64_MAX)
             break;
         ex.t = std::max(ex.t, tn);
@@ -378,7 +396,7 @@ static void test_random_traces()
         for (int i = 0; i < nm; ++i) {
             const int64_t fin = 20000 + (int64_t)(rng() % 200000);
             mm.push_back(MatModel{fin + fin / 4, fin, 1000 + fin / 10,
-                                  200 + (int64_t)(rng() % 5000)});
+                                  200 + (int64_t)(rng() % 5000), (int)(rng() % 2)});
         }
         const int64_t budget = 1000 + 900000 + (int64_t)(rng() % 400000);
         SimExec ex(mm, budget, 3000);
@@ -485,8 +503,10 @@ class ThreadExec : public Executor {
     int64_t slot_need(int, int) override { return 100; }
     void prepare_slot(int, int) override { add(100); }
     void release_slot(int) override { used -= 100; }
-    void launch_tick(int, const std::vector<Request *> &) override {}
-    void wait_tick(int) override { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
+    int lane_of(int mid) override { return mid % 2; }
+    void launch_tick(int, int, const std::vector<Request *> &) override {}
+    bool tick_done(int, int) override { return true; }
+    void wait_tick(int, int) override { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
     void run_one(Request *) override {}
 };
 
@@ -504,7 +524,7 @@ static void test_threads()
     std::thread sched([&] {
         while (!stop.load())
             if (!core.step())
-                core.wait_for_work(100000);
+                core.wait_for_work(core.busy() ? 20000 : 100000);
         core.shutdown();
     });
     std::vector<std::thread> clients;
@@ -535,6 +555,33 @@ static void test_threads()
     CHECK(ex.peak.load() <= budget);
 }
 
+// Two lanes: short requests do not wait out the long ticks of a heavy
+// solve; they finish while it still runs, and the heavy lane's ticks are
+// never slowed by them.
+static void test_lanes_keep_short_requests_short()
+{
+    std::vector<MatModel> mm = {MatModel{1000, 1000, 1000, 100000, 1},
+                                MatModel{1000, 1000, 1000, 1000, 0},
+                                MatModel{1000, 1000, 1000, 1000, 0}};
+    SimExec ex(mm, 1 << 30, 100);
+    Core core(ex, limits(1 << 30, 16, 4));
+    ex.core = &core;
+    add_all(core, 3);
+    std::vector<Arrival> a = {{0, kCg, 0, 30}};
+    for (int i = 0; i < 20; ++i)
+        a.push_back({200000 + i * 50000, i % 3 == 0 ? kCg : kSpmv, 1 + i % 2, 5});
+    auto tk = simulate(core, ex, a);
+    CHECK(!ex.violated);
+    for (uint64_t t : tk)
+        CHECK(core.poll(t) == 1);
+    const Stats st = core.stats();
+    // the heavy solve alone: 30 ticks of ~102 us; each short request a few
+    // light ticks of ~3 us.  Without lanes a short one would take at least
+    // one heavy tick per step.
+    CHECK(st.max_us >= 30 * 100.0);
+    CHECK(st.p50_us < 100.0);
+}
+
 int main()
 {
     test_budget_exhaustion();
@@ -544,6 +591,7 @@ int main()
     test_too_large_fails();
     test_slots_released_for_uploads();
     test_fifo();
+    test_lanes_keep_short_requests_short();
     test_random_traces();
     test_threads();
     if (g_fail) {
