@@ -183,16 +183,24 @@ def run_cg(args, torch, L, gen, extras_only=False):
     inf = h.info()
     kernel_name = ("k_spmv_panels<double, false>" if inf.layout == L.LAYOUT_PANELS
                    else "k_spmv_tiles<double, false, false>")
-    # a plain copy of known size (256 MiB read + 256 MiB written): the
-    # calibration for the hardware byte counters, and the measured copy
-    # ceiling quoted beside the nominal peak
-    ca = torch.empty(32 << 20, dtype=torch.float64, device="cuda")
+    # the library's own stream kernels: a 256 MiB copy (read + write; also
+    # the calibration of the hardware byte counters) and a 1 GiB read, the
+    # measured ceilings quoted beside the nominal peak
+    nb = 256 << 20
+    ca = torch.empty(nb, dtype=torch.uint8, device="cuda")
     cb = torch.empty_like(ca)
-    cb.copy_(ca)
+    L.lilac_hbm_stream(ca, nb, dst=cb)
     torch.cuda.synchronize()
-    copy_ms = time_events(lambda: cb.copy_(ca), 20, stream)
-    copy_gbs = 2 * ca.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    copy_ms = time_events(lambda: L.lilac_hbm_stream(ca, nb, dst=cb), 20, stream)
+    copy_gbs = 2 * nb / (copy_ms * 1e-3) / 1e9
     del ca, cb
+    rb = 1 << 30
+    big = torch.empty(rb, dtype=torch.uint8, device="cuda")
+    for _ in range(5):
+        L.lilac_hbm_stream(big, rb)
+    read_ms = time_events(lambda: L.lilac_hbm_stream(big, rb), 20, stream)
+    read_gbs = rb / (read_ms * 1e-3) / 1e9
+    del big
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s",
         "ms_per_step": round(dt * 1e3, 4),
@@ -204,6 +212,8 @@ def run_cg(args, torch, L, gen, extras_only=False):
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(kernel_name, "cg_spd150k"),
                      "kernel": kernel_name, "npanels": inf.npanels,
+                     "read_ceiling": round(read_gbs, 1),
+                     "frac_of_read_ceiling": round(achieved / read_gbs, 4),
                      "copy_ceiling": round(copy_gbs, 1),
                      "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
                      "bytes_per_launch": kb, "avg_us": round(ms * 1e3, 2)},
@@ -290,10 +300,10 @@ def build_matrices(specs):
 
 
 def run_batched(args, torch, L, gen):
-    """512 matrices in one grouped call, with the library's default plans and
-    with plans from the autotuner (one representative of each shape class
-    tuned first; every later handle of that class starts from its plan),
-    against 512 single calls."""
+    """512 matrices in one grouped call: with the library's default plans,
+    then tuned by the batch autotuner and measured on fresh handles that
+    start from the tuned plans (the value reported), against 512 single
+    calls."""
     specs = gen.batch_specs()
     t0 = time.perf_counter()
     mats = build_matrices(specs)
@@ -323,18 +333,15 @@ def run_batched(args, torch, L, gen):
             h.spmv(x, y)
     singles()
     ms_s = time_events(singles, 3, stream)
-    # the autotuner on one matrix per shape class (the largest of the class)
+    # the batch autotuner: layouts chosen class by class on the batched call
+    # itself; the plans go to the tuning cache, and new handles of the same
+    # matrices start from them
     t0 = time.perf_counter()
-    classes = {}
-    for i, h in enumerate(hs):
-        k = h.tune_class()
-        if k not in classes or mats[i].nnz > mats[classes[k]].nnz:
-            classes[k] = i
-    for k, i in classes.items():
-        hs[i].tune()
+    tuned_est = L.lilac_spmv_batched_tune(hs, xs, ys)
+    tune_s = time.perf_counter() - t0
+    classes = len({h.tune_class() for h in hs})
     for h in hs:
         h.destroy()
-    tune_s = time.perf_counter() - t0
     hs = [L.Csr.from_gen(A) for A in mats]   # each starts from its class's plan
     ms_tuned = measure(hs)
     layouts = {}
@@ -344,14 +351,15 @@ def run_batched(args, torch, L, gen):
     for h in hs:
         h.destroy()
     del mats
-    ms_g = min(ms_default, ms_tuned)
+    ms_g = ms_tuned
     return {"workload": "batched512", "nnz": nnz, "bytes": total_b,
             "ms_grouped": round(ms_g, 3),
             "GBps_grouped": round(total_b / (ms_g * 1e-3) / 1e9, 1),
             "frac_of_8TBps": round(total_b / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "ms_grouped_default_plans": round(ms_default, 3),
             "ms_grouped_tuned_plans": round(ms_tuned, 3),
-            "tuned_classes": len(classes), "tuning_s": round(tune_s, 2),
+            "ms_tuner_estimate": round(tuned_est, 3),
+            "tuned_classes": classes, "tuning_s": round(tune_s, 2),
             "layouts_tuned": {str(k): v for k, v in sorted(layouts.items())},
             "ms_512_single_calls": round(ms_s, 3),
             "GBps_single_calls": round(total_b / (ms_s * 1e-3) / 1e9, 1),
@@ -435,7 +443,8 @@ def run_marshal(args, torch, L, gen):
     """The paper's marshaling comparison on MI355X: the paper-shaped call
     with host arrays, the matrix cached on the device after the first call
     (only x up and y down per call) against re-uploading and re-analysing it
-    on every call (LILAC_MARSHAL=naive)."""
+    on every call (LILAC_MARSHAL=naive): the CG matrix spd150k, and the
+    PageRank loop on R-MAT 2^22."""
     A = gen.spd_random()
     x = gen.vector(A.cols, 3)
     y = np.empty(A.rows)
@@ -454,6 +463,32 @@ def run_marshal(args, torch, L, gen):
     os.environ.pop("LILAC_MARSHAL", None)
     out["naive_over_persistent"] = round(out["ms_per_call_naive"] /
                                          out["ms_per_call_persistent"], 1)
+    # the PageRank loop of the paper's graph kernels: 20 power steps, each a
+    # paper-shaped float32 product on host arrays (x up, y down per call)
+    # plus the damping on the host, with the matrix cached after the first
+    # call or re-uploaded by every call
+    G = gen.rmat_pagerank()
+    n = G.rows
+    d = np.float32(0.85)
+    pr = {"workload": "marshal_pagerank_rmat22", "nnz": G.nnz, "steps": 20}
+    for mode, steps in (("persistent", 20), ("naive", 3)):
+        if mode == "naive":
+            os.environ["LILAC_MARSHAL"] = "naive"
+        else:
+            os.environ.pop("LILAC_MARSHAL", None)
+        xh = np.full(n, 1.0 / n, dtype=np.float32)
+        yh = np.empty(n, dtype=np.float32)
+        L.lilac_spmv_csr_f32(n, G.row_ptr, G.col_idx, G.vals, xh, yh)   # first call
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            L.lilac_spmv_csr_f32(n, G.row_ptr, G.col_idx, G.vals, xh, yh)
+            xh = d * yh + np.float32((1.0 - d) / n)
+        pr[f"ms_per_step_{mode}"] = round((time.perf_counter() - t0) / steps * 1e3, 3)
+        L.lilac_release_all()
+    os.environ.pop("LILAC_MARSHAL", None)
+    pr["naive_over_persistent"] = round(pr["ms_per_step_naive"] /
+                                        pr["ms_per_step_persistent"], 1)
+    out["pagerank"] = pr
     return out
 
 

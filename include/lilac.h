@@ -246,12 +246,17 @@ int lilac_dot_dev(int64_t n, const void *a, const void *b, void *out, lilac_dtyp
  * `iters` iterations of
  *   q = A p; alpha = rho/(p.q); x += alpha p; r -= alpha q;
  *   rho' = r.r; beta = rho'/rho; p = r + beta p
- * stopping early (x kept) only if rho or p.q becomes exactly 0.  b and x are
- * device arrays of rows doubles.  With LILAC_CG_GRAPH the whole solve runs as
- * one captured HIP graph (scalars stay on the device, no host round trip);
- * the graph is cached per (handle, b, x, iters).  rho_out / iters_done are
- * host pointers (may be NULL; if given the call waits for the result).
- * Async otherwise.
+ * stopping early (x kept) only if rho or p.q becomes exactly 0.  The
+ * iterations are computed in the arrangement of Chronopoulos and Gear
+ * (1989), the same iterates in exact arithmetic: the product is w = A r and
+ * s = A p is updated alongside p, so both inner products of an iteration
+ * are known together and an iteration is one product (with r.w fused into
+ * it) and one vector kernel.  b and x are device arrays of rows doubles.
+ * With LILAC_CG_GRAPH the whole solve runs as one captured HIP graph
+ * (scalars stay on the device, no host round trip); the graph is cached per
+ * (handle, b, x, iters).  rho_out / iters_done are host pointers (may be
+ * NULL; if given the call waits for the result): r.r of the final residual
+ * (or at the early stop) and the iterations done.  Async otherwise.
  */
 #define LILAC_CG_GRAPH 1u
 int lilac_cg(lilac_csr_t h, const double *b, double *x, int iters,
@@ -262,8 +267,8 @@ int lilac_cg(lilac_csr_t h, const double *b, double *x, int iters,
  * reduction shapes, so x is bitwise what lilac_cg without LILAC_CG_GRAPH
  * gives), for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation.  It
- * allocates nothing: the solver state (r, p, q, partial sums, scalars) lives
- * in one fixed device array of the library, about 24 MiB per GPU, held from
+ * allocates nothing: the solver state (r, p, s, w, partial sums, scalars)
+ * lives in one fixed device array of the library, 32 MiB per GPU, held from
  * the library's set-up until the process ends, which limits the matrix to
  * at most 1048576 rows (LILAC_ERR_ARG beyond).  The handle must be up to
  * date: after lilac_csr_invalidate it is refused with LILAC_ERR_STATE until
@@ -307,6 +312,21 @@ int lilac_spmv_batched(int count, const lilac_csr_t *hs, const void *const *xs,
  * time of one product with the chosen plan.
  */
 int lilac_csr_tune(lilac_csr_t h, double *best_us);
+/*
+ * Autotuner for a batch (the choice of storage per matrix of section
+ * "Necessity of Flexible Backends", made by timing): the handles are
+ * grouped by shape class (lilac_csr_tune_class); class by class, most
+ * non-zeros first, each layout a grouped launch takes (row-class tiles,
+ * column panels, band) is tried on all matrices of the class and kept when
+ * the whole lilac_spmv_batched call on (hs, xs, ys) gets at least 1%
+ * faster.  The handles keep the chosen plans, and each class's plan goes
+ * to the tuning cache (and the LILAC_TUNE_CACHE file), so handles created
+ * later start from it.  The vectors are overwritten by the trial calls.
+ * best_ms (may be NULL) receives the time of one batched call with the
+ * chosen plans.  Blocking.  Errors: LILAC_ERR_ARG.
+ */
+int lilac_spmv_batched_tune(int count, const lilac_csr_t *hs, const void *const *xs,
+                            void *const *ys, double *best_ms);
 /* The shape class under which lilac_csr_tune records and looks up plans
  * (dtype, log2 of rows, twice log2 of the mean row length, row class of
  * the longest row), as a NUL-terminated string into buf[cap].

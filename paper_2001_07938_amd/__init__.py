@@ -19,7 +19,7 @@ import torch  # noqa: F401  (shares its HIP runtime with the library)
 __all__ = [
     "LilacError", "lib", "lilac_spmv_csr", "lilac_spmv_csr_f32", "lilac_dot",
     "lilac_invalidate", "lilac_release_all", "lilac_init", "lilac_finalize",
-    "lilac_dot_dev", "lilac_spmv_batched", "lilac_hbm_stream", "Csr", "Csr64", "F64", "F32",
+    "lilac_dot_dev", "lilac_spmv_batched", "lilac_spmv_batched_tune", "lilac_hbm_stream", "Csr", "Csr64", "F64", "F32",
     "KEEP_HOST", "CG_GRAPH", "NCLASS", "HEADER_FUNCTIONS",
 ]
 
@@ -90,6 +90,7 @@ _SIGS = {
     "lilac_csr_tune": ([_P, _P], _I),
     "lilac_csr_tune_class": ([_P, ctypes.c_char_p, _I], _I),
     "lilac_hbm_stream": ([_P, _P, _I64, _I, _P], _I),
+    "lilac_spmv_batched_tune": ([_I, _P, _P, _P, _P], _I),
     "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
     "lilac_spmv_jds": ([_I, _I, _P, _P, _P, _P, _P, _P, _P], _I),
     "lilac_csr_to_jds": ([_P, _P, _P, _P, _I, _P, _P, _P, _P], _I),
@@ -257,6 +258,19 @@ def lilac_spmv_batched(handles: Sequence["Csr"], xs, ys, stream=None):
     Y = (ctypes.c_void_p * n)(*[_ptr(y) for y in ys])
     _check(lib().lilac_spmv_batched(n, ctypes.cast(H, _P), ctypes.cast(X, _P),
                                     ctypes.cast(Y, _P), _stream(stream)))
+
+
+def lilac_spmv_batched_tune(handles: Sequence["Csr"], xs, ys) -> float:
+    """Tunes the batch's layouts class by class on the batched call itself;
+    returns the time (ms) of one batched call with the chosen plans."""
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*[h.handle for h in handles])
+    X = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+    Y = (ctypes.c_void_p * n)(*[_ptr(y) for y in ys])
+    ms = ctypes.c_double(0.0)
+    _check(lib().lilac_spmv_batched_tune(n, ctypes.cast(H, _P), ctypes.cast(X, _P),
+                                         ctypes.cast(Y, _P), ctypes.addressof(ms)))
+    return ms.value
 
 
 # ------------------------------------------------------------ handle

@@ -2037,11 +2037,22 @@ __device__ __forceinline__ double sum_parts_256(const double *__restrict__ part,
     return block_sum<kWaves>(acc, lds);
 }
 
-// CG start: x = 0, r = b, p = b, partial sums of b.b into rr (parity 0).
+// Conjugate gradient in the arrangement of Chronopoulos and Gear (1989):
+// the same iterates as the textbook loop in exact arithmetic, with both
+// inner products of an iteration (r.r and r.Ar) available together, so an
+// iteration is one product w = A r (with the partials of w.r fused into it)
+// and one vector kernel.  Recurrences (s = A p kept alongside p):
+//   gamma = r.r, delta = w.r, beta = gamma / gamma_old (0 at first),
+//   p.Ap = delta - beta * gamma / alpha_old, alpha = gamma / p.Ap,
+//   p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s.
+// The scalars of iteration k go to slot k & 1 of gamma[] and alpha[], so an
+// iteration reads the previous slot while it writes its own.
+
+// Start: x = 0, r = b, p = s = 0, partial sums of b.b into rr (parity 0).
 __global__ __launch_bounds__(kBlock) void k_cg_init(
     int64_t n, const double *__restrict__ b, double *__restrict__ x,
-    double *__restrict__ r, double *__restrict__ p, double *__restrict__ rr,
-    CgScalars *__restrict__ sc)
+    double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv,
+    double *__restrict__ rr, CgScalars *__restrict__ sc)
 {
     __shared__ double lds[kWaves];
     double acc = 0.0;
@@ -2050,7 +2061,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(
         const double bi = b[i];
         x[i] = 0.0;
         r[i] = bi;
-        p[i] = bi;
+        p[i] = 0.0;
+        sv[i] = 0.0;
         acc = fma(bi, bi, acc);
     }
     const double t = block_sum<kWaves>(acc, lds);
@@ -2058,9 +2070,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(
         rr[blockIdx.x] = t;
         if (blockIdx.x == 0) {
             sc->rho = 0.0;
-            sc->pq = 0.0;
-            sc->alpha = 0.0;
-            sc->beta = 0.0;
+            sc->gamma[0] = sc->gamma[1] = 1.0;
+            sc->alpha[0] = sc->alpha[1] = 1.0;
             sc->done = 0;
             sc->iters = 0;
         }
@@ -2089,55 +2100,67 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *lds)
     b = tb;
 }
 
-// Iteration k, after q = A p (with p.q partials in dot_part):
-//   rho = sum rr[k&1], pq = sum dot_part; stop (x kept) if either is 0;
-//   alpha = rho/pq; x += alpha p; r -= alpha q; partials of r.r into rr[~k&1].
-// Every workgroup forms rho, pq and alpha itself, in the same order.  The
-// thread's first elements are read before the sums, so their loads overlap.
-__global__ __launch_bounds__(kBlock) void k_cg_update(
-    int64_t n, CgScalars *__restrict__ sc, const double *__restrict__ p,
-    const double *__restrict__ q, double *__restrict__ x,
+// Iteration k (slot par = k & 1), after w = A r with the w.r partials in
+// dot_part: every workgroup forms gamma, delta, beta and alpha itself, in
+// the same order; the solve stops (x kept) when gamma or p.Ap is exactly 0.
+// Each thread's first elements are read before the sums, so their loads
+// overlap; the partials of the new r.r go to rr[par ^ 1].
+__global__ __launch_bounds__(kBlock) void k_cg_step(
+    int64_t n, CgScalars *__restrict__ sc, const double *__restrict__ w,
+    double *__restrict__ p, double *__restrict__ sv, double *__restrict__ x,
     double *__restrict__ r, const double *__restrict__ dot_part, int32_t ndot,
-    double *__restrict__ rr, int32_t nparts, int32_t par)
+    double *__restrict__ rr, int32_t nparts, int32_t k)
 {
     __shared__ double lds[2 * kWaves];
+    const int32_t par = k & 1;
     const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t step = (int64_t)gridDim.x * kBlock;
-    double p0 = 0.0, q0 = 0.0, x0 = 0.0, r0 = 0.0;
+    double w0 = 0.0, p0 = 0.0, s0 = 0.0, x0 = 0.0, r0 = 0.0;
     if (i0 < n) {
+        w0 = w[i0];
         p0 = p[i0];
-        q0 = q[i0];
+        s0 = sv[i0];
         x0 = x[i0];
         r0 = r[i0];
     }
     const int32_t done = sc->done;
-    double rho = 0.0, pq = 0.0;
+    const double g_old = sc->gamma[par ^ 1], a_old = sc->alpha[par ^ 1];
+    double g = 0.0, d = 0.0;
     for (int32_t i = threadIdx.x; i < nparts; i += kBlock)
-        rho += rr[par * kDotParts + i];
+        g += rr[par * kDotParts + i];
     for (int32_t i = threadIdx.x; i < ndot; i += kBlock)
-        pq += dot_part[i];
+        d += dot_part[i];
     if (done)
         return;
-    block_sum2(rho, pq, lds);
-    if (rho == 0.0 || pq == 0.0) {
+    block_sum2(g, d, lds);
+    const double beta = (k > 0) ? g / g_old : 0.0;
+    const double pap = d - beta * g / a_old;
+    if (g == 0.0 || pap == 0.0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->done = 1;
-            sc->rho = rho;
-            sc->pq = pq;
+            sc->rho = g;
         }
         return;
     }
-    const double alpha = rho / pq;
+    const double alpha = g / pap;
     double acc = 0.0;
     if (i0 < n) {
-        x[i0] = fma(alpha, p0, x0);
-        const double ri = fma(-alpha, q0, r0);
+        const double pi = fma(beta, p0, r0);
+        const double si = fma(beta, s0, w0);
+        p[i0] = pi;
+        sv[i0] = si;
+        x[i0] = fma(alpha, pi, x0);
+        const double ri = fma(-alpha, si, r0);
         r[i0] = ri;
         acc = ri * ri;
     }
     for (int64_t i = i0 + step; i < n; i += step) {
-        x[i] = fma(alpha, p[i], x[i]);
-        const double ri = fma(-alpha, q[i], r[i]);
+        const double pi = fma(beta, p[i], r[i]);
+        const double si = fma(beta, sv[i], w[i]);
+        p[i] = pi;
+        sv[i] = si;
+        x[i] = fma(alpha, pi, x[i]);
+        const double ri = fma(-alpha, si, r[i]);
         r[i] = ri;
         acc = fma(ri, ri, acc);
     }
@@ -2145,45 +2168,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
     if (threadIdx.x == 0) {
         rr[(par ^ 1) * kDotParts + blockIdx.x] = t;
         if (blockIdx.x == 0) {
-            sc->pq = pq;
-            sc->alpha = alpha;
+            sc->gamma[par] = g;
+            sc->alpha[par] = alpha;
+            sc->iters = k + 1;
         }
     }
 }
 
-// beta = rho'/rho (rho' = sum rr[~k&1]); p = r + beta p.
-__global__ __launch_bounds__(kBlock) void k_cg_xpay(
-    int64_t n, CgScalars *__restrict__ sc, const double *__restrict__ r,
-    double *__restrict__ p, const double *__restrict__ rr, int32_t nparts,
-    int32_t par)
+// After the last iteration: rho = r.r of the final residual (partials in
+// rr[par]), unless the solve stopped early (rho was set then).
+__global__ __launch_bounds__(1024) void k_cg_final(CgScalars *__restrict__ sc,
+                                                   const double *__restrict__ rr,
+                                                   int32_t nparts, int32_t par)
 {
-    __shared__ double lds[2 * kWaves];
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    double r0 = 0.0, p0 = 0.0;
-    if (i0 < n) {
-        r0 = r[i0];
-        p0 = p[i0];
-    }
-    const int32_t done = sc->done;
-    double rho = 0.0, rho_new = 0.0;
-    for (int32_t i = threadIdx.x; i < nparts; i += kBlock) {
-        rho += rr[par * kDotParts + i];
-        rho_new += rr[(par ^ 1) * kDotParts + i];
-    }
-    if (done)
-        return;
-    block_sum2(rho, rho_new, lds);
-    const double beta = rho_new / rho;
-    if (i0 < n)
-        p[i0] = fma(beta, p0, r0);
-    for (int64_t i = i0 + step; i < n; i += step)
-        p[i] = fma(beta, p[i], r[i]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->rho = rho_new;
-        sc->beta = beta;
-        sc->iters += 1;
-    }
+    __shared__ double lds[16];
+    const double t = sum_parts_1024(rr + par * kDotParts, nparts, lds);
+    if (threadIdx.x == 0 && !sc->done)
+        sc->rho = t;
 }
 
 inline int32_t grid_for(int64_t n, int32_t per_block, int32_t cap)
@@ -2803,31 +2804,28 @@ void launch_copy_f32(int64_t n, const float *src, float *dst, hipStream_t s)
     check_launch("k_copy");
 }
 
-void launch_cg_init(int64_t n, const double *b, double *x, double *r,
-                    double *p, double *rr, int32_t nparts, CgScalars *sc,
-                    hipStream_t s)
+void launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p,
+                    double *sv, double *rr, int32_t nparts, CgScalars *sc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_init, dim3(nparts), dim3(kBlock), 0, s, n, b, x, r,
-                       p, rr, sc);
+    hipLaunchKernelGGL(k_cg_init, dim3(nparts), dim3(kBlock), 0, s, n, b, x, r, p, sv, rr,
+                       sc);
     check_launch("k_cg_init");
 }
 
-void launch_cg_update(int64_t n, CgScalars *sc, const double *p,
-                      const double *q, double *x, double *r,
-                      const double *dot_part, int32_t ndot, double *rr,
-                      int32_t nparts, int32_t par, hipStream_t s)
+void launch_cg_step(int64_t n, CgScalars *sc, const double *w, double *p, double *sv,
+                    double *x, double *r, const double *dot_part, int32_t ndot, double *rr,
+                    int32_t nparts, int32_t k, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_update, dim3(nparts), dim3(kBlock), 0, s, n, sc, p,
-                       q, x, r, dot_part, ndot, rr, nparts, par);
-    check_launch("k_cg_update");
+    hipLaunchKernelGGL(k_cg_step, dim3(nparts), dim3(kBlock), 0, s, n, sc, w, p, sv, x, r,
+                       dot_part, ndot, rr, nparts, k);
+    check_launch("k_cg_step");
 }
 
-void launch_cg_xpay(int64_t n, CgScalars *sc, const double *r, double *p,
-                    const double *rr, int32_t nparts, int32_t par, hipStream_t s)
+void launch_cg_final(CgScalars *sc, const double *rr, int32_t nparts, int32_t par,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_xpay, dim3(nparts), dim3(kBlock), 0, s, n, sc, r, p,
-                       rr, nparts, par);
-    check_launch("k_cg_xpay");
+    hipLaunchKernelGGL(k_cg_final, dim3(1), dim3(1024), 0, s, sc, rr, nparts, par);
+    check_launch("k_cg_final");
 }
 
 }  // namespace lilac

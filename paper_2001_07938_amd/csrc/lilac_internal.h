@@ -443,23 +443,22 @@ void launch_copy_f32(int64_t n, const float *src, float *dst, hipStream_t s);
 
 // CG building blocks (device scalars in `CgScalars`)
 struct CgScalars {
-    double rho, pq, alpha, beta;
+    double rho;                 // r.r (of the final residual, or at the stop)
+    double gamma[2], alpha[2];  // r.r and alpha of the last two iterations
     int32_t done, iters;
-    int32_t pad[2];
 };
-// CG iteration k is three launches: the product q = A p with fused p.q
-// partials, then these two; rr holds r.r partials for two parities
-// (kDotParts each), so no scalar is written by one workgroup while others
+// A conjugate gradient solve is k_cg_init, then per iteration the product
+// w = A r with the w.r partials fused into it and k_cg_step, then
+// k_cg_final (see kernels.hip).  rr holds r.r partials for two parities
+// (kDotParts each), so no partial is written by one workgroup while others
 // read it.
-void launch_cg_init(int64_t n, const double *b, double *x, double *r,
-                    double *p, double *rr, int32_t nparts, CgScalars *sc,
-                    hipStream_t s);
-void launch_cg_update(int64_t n, CgScalars *sc, const double *p,
-                      const double *q, double *x, double *r,
-                      const double *dot_part, int32_t ndot, double *rr,
-                      int32_t nparts, int32_t par, hipStream_t s);
-void launch_cg_xpay(int64_t n, CgScalars *sc, const double *r, double *p,
-                    const double *rr, int32_t nparts, int32_t par, hipStream_t s);
+void launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p,
+                    double *sv, double *rr, int32_t nparts, CgScalars *sc, hipStream_t s);
+void launch_cg_step(int64_t n, CgScalars *sc, const double *w, double *p, double *sv,
+                    double *x, double *r, const double *dot_part, int32_t ndot, double *rr,
+                    int32_t nparts, int32_t k, hipStream_t s);
+void launch_cg_final(CgScalars *sc, const double *rr, int32_t nparts, int32_t par,
+                     hipStream_t s);
 int32_t blas1_parts(int64_t n);
 // Workgroups of the tile kernel resident per compute unit.
 int occupancy_tiles(lilac_dtype dt);

@@ -945,7 +945,7 @@ CsrHandle *create_handle_adopt(int rows, int cols, int64_t nnz, int32_t *rp,
 
 struct CgState {
     int64_t n = 0;
-    double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+    double *r = nullptr, *p = nullptr, *sv = nullptr, *w = nullptr, *part = nullptr;
     CgScalars *sc = nullptr;
     struct G {
         const double *b;
@@ -1012,7 +1012,8 @@ void destroy_handle(CsrHandle *h)
     if (h->cg) {
         dev_free(h->cg->r);
         dev_free(h->cg->p);
-        dev_free(h->cg->q);
+        dev_free(h->cg->sv);
+        dev_free(h->cg->w);
         dev_free(h->cg->part);
         dev_free(h->cg->sc);
         delete h->cg;
@@ -1335,13 +1336,15 @@ static void cg_prepare(CsrHandle &h)
     try {
         st->r = (double *)dev_alloc((size_t)h.rows * 8);
         st->p = (double *)dev_alloc((size_t)h.rows * 8);
-        st->q = (double *)dev_alloc((size_t)h.rows * 8);
+        st->sv = (double *)dev_alloc((size_t)h.rows * 8);
+        st->w = (double *)dev_alloc((size_t)h.rows * 8);
         st->part = (double *)dev_alloc((size_t)2 * kDotParts * 8);
         st->sc = (CgScalars *)dev_alloc(sizeof(CgScalars));
     } catch (...) {
         dev_free(st->r);
         dev_free(st->p);
-        dev_free(st->q);
+        dev_free(st->sv);
+        dev_free(st->w);
         dev_free(st->part);
         delete st;
         throw;
@@ -1351,37 +1354,38 @@ static void cg_prepare(CsrHandle &h)
 
 void handle_cg_prepare(CsrHandle &h) { cg_prepare(h); }
 
-// One whole solve: initialisation, then `iters` iterations of three kernels
-// (product with fused p.q partials; alpha and the x/r update with r.r
-// partials; beta and the direction update).  Scalars never leave the device.
-// r, p, q hold rows doubles, part 2 * kDotParts, sc one CgScalars; the
-// initialisation writes everything later launches read.
+// One whole solve: initialisation, then `iters` iterations of two kernels
+// (the product w = A r with the w.r partials fused into it; the scalars and
+// the p, s, x, r updates with the next r.r partials), then the final r.r.
+// Scalars never leave the device.  r, p, sv (s = A p), w hold rows doubles,
+// part 2 * kDotParts, sc one CgScalars; the initialisation writes
+// everything later launches read.
 static void cg_enqueue_state(const CsrHandle &h, const double *b, double *x, int iters,
-                             double *r, double *p, double *q, double *part,
+                             double *r, double *p, double *sv, double *w, double *part,
                              CgScalars *sc, hipStream_t s)
 {
     const int64_t n = h.rows;
     const int32_t np = blas1_parts(n);
     const int32_t ndot = h.grid + h.fin_blocks;
-    launch_cg_init(n, b, x, r, p, part, np, sc, s);
+    launch_cg_init(n, b, x, r, p, sv, part, np, sc, s);
     for (int it = 0; it < iters; ++it) {
-        spmv_enqueue(h, p, q, epi_none(), p, true, s);
-        launch_cg_update(n, sc, p, q, x, r, h.d_dot_part, ndot, part, np, it & 1, s);
-        launch_cg_xpay(n, sc, r, p, part, np, it & 1, s);
+        spmv_enqueue(h, r, w, epi_none(), r, true, s);
+        launch_cg_step(n, sc, w, p, sv, x, r, h.d_dot_part, ndot, part, np, it, s);
     }
+    launch_cg_final(sc, part, np, iters & 1, s);
 }
 
 static void cg_enqueue(const CsrHandle &h, const double *b, double *x,
                        int iters, hipStream_t s)
 {
     const CgState &st = *h.cg;
-    cg_enqueue_state(h, b, x, iters, st.r, st.p, st.q, st.part, st.sc, s);
+    cg_enqueue_state(h, b, x, iters, st.r, st.p, st.sv, st.w, st.part, st.sc, s);
 }
 
 // ------------------------------------------------ CG without allocation
 //
 // For callers that cannot allocate device memory (work under HIP graph
-// capture, tight serving loops): the CG state (r, p, q, the r.r partials
+// capture, tight serving loops): the CG state (r, p, s, w, the r.r partials
 // and the scalars) lives in one fixed device array instead of the handle's
 // state, which is allocated on first use.  The array holds the state of a
 // matrix of at most kNoAllocRows rows; every GPU the library runs on keeps
@@ -1391,7 +1395,7 @@ static void cg_enqueue(const CsrHandle &h, const double *b, double *x,
 constexpr int64_t kNoAllocRows = 1 << 20;
 constexpr size_t kNoAllocPart = 2 * kDotParts;
 constexpr size_t kNoAllocBytes =
-    3 * (size_t)kNoAllocRows * 8 + kNoAllocPart * 8 + sizeof(CgScalars);
+    4 * (size_t)kNoAllocRows * 8 + kNoAllocPart * 8 + sizeof(CgScalars);
 static __device__ __align__(256) char scratch[kNoAllocBytes];
 
 constexpr int kMaxDevices = 64;
@@ -1990,7 +1994,8 @@ bool tune_cache_lookup(const CsrHandle &h, Plan &out)
 {
     if (g_tune.empty())
         return false;
-    // the key needs the row count and mean length only, available here
+    // the key needs the row count, the mean and the longest row length,
+    // all known before the analysis
     auto it = g_tune.find(tune_key(h));
     if (it == g_tune.end())
         return false;
@@ -2107,6 +2112,121 @@ static double tune_handle(CsrHandle &h)
     g_tune[tune_key(h)] = best;
     tune_cache_save();
     return best_us;
+}
+
+// ============================================================ batch tuner
+
+// One batched call's time (ms): the median of three runs of `reps` calls.
+static double time_batch(int count, const lilac_csr_t *hs, const void *const *xs,
+                         void *const *ys, int reps)
+{
+    Context &c = ctx();
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    double t[3];
+    try {
+        run_batched(count, hs, xs, ys, c.stream);
+        for (double &ti : t) {
+            HIPC(hipEventRecord(e0, c.stream));
+            for (int i = 0; i < reps; ++i)
+                run_batched(count, hs, xs, ys, c.stream);
+            HIPC(hipEventRecord(e1, c.stream));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            ti = ms / reps;
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::sort(t, t + 3);
+    return t[1];
+}
+
+// Layout a handle's product uses now.
+static int32_t effective_layout(const CsrHandle &h)
+{
+    return h.use_panels ? LAYOUT_PANELS : h.use_band ? LAYOUT_BAND
+                                                     : h.use_hot ? LAYOUT_HOT : LAYOUT_ROWS;
+}
+
+// Autotuner for a batch: the matrices are grouped by shape class; class by
+// class (most non-zeros first), each layout the grouped launch can take
+// (row-class tiles, column panels, band) is tried on every matrix of the
+// class and kept if the whole batched call gets at least 1% faster.  The
+// chosen plan of each class goes to the tuning cache, so handles of that
+// class created later start from it.  Timing the batch itself matters:
+// a layout that is fastest for a matrix alone can slow the grouped launch
+// down (for instance fewer row blocks than compute units alone, but just
+// right among hundreds of others).
+static double tune_batch(int count, const lilac_csr_t *hs, const void *const *xs,
+                         void *const *ys)
+{
+    Context &c = ctx();
+    std::map<std::string, std::vector<int>> cls;
+    for (int j = 0; j < count; ++j) {
+        CsrHandle *h = (CsrHandle *)hs[j];
+        refresh(*h, c.stream);
+        cls[tune_key(*h)].push_back(j);
+    }
+    std::vector<std::pair<int64_t, std::string>> order;
+    for (auto &kv : cls) {
+        int64_t nnz = 0;
+        for (int j : kv.second)
+            nnz += ((const CsrHandle *)hs[j])->nnz;
+        order.emplace_back(nnz, kv.first);
+    }
+    std::sort(order.begin(), order.end(), std::greater<std::pair<int64_t, std::string>>());
+    auto apply = [&](const std::vector<int> &members, const std::vector<Plan> &plans) {
+        for (size_t k = 0; k < members.size(); ++k) {
+            CsrHandle &h = *(CsrHandle *)hs[members[k]];
+            drop_graphs(h);
+            forget_handle_in_groups(&h);
+            h.dev_bytes -= analysis_bytes(h);
+            h.plan = plans[k];
+            analyse(h, c.stream);
+            h.dev_bytes += analysis_bytes(h);
+        }
+    };
+    // the clocks settle under sustained load before anything is compared
+    for (int i = 0; i < 20; ++i)
+        run_batched(count, hs, xs, ys, c.stream);
+    double best = time_batch(count, hs, xs, ys, 5);
+    for (auto &o : order) {
+        const std::vector<int> &members = cls[o.second];
+        std::vector<Plan> cur;
+        std::vector<int32_t> lay;
+        for (int j : members) {
+            cur.push_back(((const CsrHandle *)hs[j])->plan);
+            lay.push_back(effective_layout(*(const CsrHandle *)hs[j]));
+        }
+        for (int32_t cand : {LAYOUT_ROWS, LAYOUT_PANELS, LAYOUT_BAND}) {
+            std::vector<Plan> trial = cur;
+            for (Plan &p : trial)
+                p.layout = cand;
+            apply(members, trial);
+            bool changed = false;
+            for (size_t k = 0; k < members.size(); ++k)
+                changed |= effective_layout(*(const CsrHandle *)hs[members[k]]) != lay[k];
+            const double t = changed ? time_batch(count, hs, xs, ys, 5) : 1e300;
+            if (t < 0.99 * best) {
+                best = t;
+                cur = trial;
+                for (size_t k = 0; k < members.size(); ++k)
+                    lay[k] = effective_layout(*(const CsrHandle *)hs[members[k]]);
+            } else {
+                apply(members, cur);
+            }
+        }
+        g_tune[o.second] = cur.front();
+    }
+    tune_cache_save();
+    return best;
 }
 
 // ================================================================== C ABI
@@ -2468,10 +2588,11 @@ int lilac_cg_noalloc(lilac_csr_t hh, const double *b, double *x, int iters, void
         char *base = scratch_on_current_device();
         double *r = (double *)base;
         double *p = r + kNoAllocRows;
-        double *q = p + kNoAllocRows;
-        double *part = q + kNoAllocRows;
+        double *sv = p + kNoAllocRows;
+        double *w = sv + kNoAllocRows;
+        double *part = w + kNoAllocRows;
         CgScalars *sc = (CgScalars *)(part + kNoAllocPart);
-        cg_enqueue_state(*h, b, x, iters, r, p, q, part, sc, (hipStream_t)stream);
+        cg_enqueue_state(*h, b, x, iters, r, p, sv, w, part, sc, (hipStream_t)stream);
     });
 }
 
@@ -2804,6 +2925,21 @@ int lilac_hbm_stream(const void *src, void *dst, int64_t bytes, int groups_per_c
         Context &c = ctx();
         launch_stream(src, dst, bytes, c.cu * groups_per_cu, (uint32_t *)c.total,
                       pick_stream(stream));
+    });
+}
+
+int lilac_spmv_batched_tune(int count, const lilac_csr_t *hs, const void *const *xs,
+                            void *const *ys, double *best_ms)
+{
+    return guard([&] {
+        if (count < 0 || (count > 0 && (!hs || !xs || !ys)))
+            fail(LILAC_ERR_ARG, "bad batch");
+        for (int j = 0; j < count; ++j)
+            if (!hs[j])
+                fail(LILAC_ERR_ARG, "NULL handle");
+        const double ms = count ? tune_batch(count, hs, xs, ys) : 0.0;
+        if (best_ms)
+            *best_ms = ms;
     });
 }
 

@@ -149,7 +149,7 @@ int64_t upload_bound(const SMatrix &m, bool cg_state)
     b += (nnz + kPad) * 12 + 256 * (rows + 257) + (2 << 20);  // panel or band copy + build
     b += (int64_t)std::max(1, m.cols) * 8;                 // trace operand
     if (cg_state)
-        b += rows * 24 + 2 * 1024 * 8 + 256;               // CG state of the plain path
+        b += rows * 32 + 2 * 1024 * 8 + 256;               // CG state of the plain path
     b += 64 * 256;                                         // allocation rounding
     return b;
 }

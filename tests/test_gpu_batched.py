@@ -148,3 +148,34 @@ def test_full_size_batched512():
         check_spmv(A, xh, y.cpu().numpy(), TOL_F64)
     for h in hs:
         h.destroy()
+
+
+def test_batch_tuner_results_and_cache():
+    """The batch autotuner changes layouts only; every matrix still equals
+    its single call bitwise and the oracle within tolerance, and handles
+    created afterwards start from the tuned plan of their class."""
+    mats = _batch(60, 17, n_hi=60000)
+    hs = [L.Csr.from_gen(A) for A in mats]
+    xs_h = [gen.vector(max(A.cols, 1), 300 + i) for i, A in enumerate(mats)]
+    xs = [_dev(x) for x in xs_h]
+    ys = [torch.empty(max(A.rows, 1), dtype=torch.float64, device=DEV) for A in mats]
+    ms = L.lilac_spmv_batched_tune(hs, xs, ys)
+    assert ms > 0
+    lay = [h.info().layout for h in hs]
+    L.lilac_spmv_batched(hs, xs, ys)
+    torch.cuda.synchronize()
+    for i, (h, A, x, y) in enumerate(zip(hs, mats, xs, ys)):
+        y1 = torch.empty_like(y)
+        h.spmv(x, y1)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y1)
+        if A.rows:
+            check_spmv(A, xs_h[i], y.cpu().numpy()[:A.rows], TOL_F64)
+    # a fresh handle of each matrix gets its class's tuned plan
+    for A, h, l0 in zip(mats, hs, lay):
+        h2 = L.Csr.from_gen(A)
+        assert h2.tune_class() == h.tune_class()
+        assert h2.info().layout == l0, (A.name, h.tune_class())
+        h2.destroy()
+    for h in hs:
+        h.destroy()
