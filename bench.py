@@ -408,7 +408,10 @@ def run_serve(args, torch, L, gen):
                   "solves_per_s": round(st["solves_per_s"], 1),
                   "GBps": round(st["gbytes_per_s"], 1), "uploads": st["uploads"],
                   "evictions": st["evictions"], "ticks": st["ticks"],
-                  "peak_device_GB": round(st["peak_device_bytes"] / 1e9, 3)}
+                  "peak_device_GB": round(st["peak_device_bytes"] / 1e9, 3),
+                  "mean_wait_ms": round(st["mean_wait_us"] / 1e3, 3),
+                  "mean_run_ms": round(st["mean_run_us"] / 1e3, 3),
+                  "waited_upload": st["waited_upload"]}
             log(f"[serve] {pt}")
             out["points"].append(pt)
         S.destroy()

@@ -479,6 +479,10 @@ typedef struct {
     int64_t device_bytes;         /* device bytes it holds now */
     int64_t planned_peak_bytes;   /* highest planned bytes (resident charges +
                                      upload reserves + slots + tables) */
+    double mean_wait_us;          /* arrival -> admission (upload, slot, queue) */
+    double mean_run_us;           /* admission -> completion */
+    int64_t waited_upload;        /* requests whose matrix was not resident
+                                     when they arrived */
 } lilac_server_stats;
 
 int lilac_server_create(lilac_server_t *s, const lilac_server_config *cfg);

@@ -518,7 +518,9 @@ class ServerStats(ctypes.Structure):
                 ("gbytes_per_s", ctypes.c_double), ("uploads", ctypes.c_int64),
                 ("evictions", ctypes.c_int64), ("ticks", ctypes.c_int64),
                 ("peak_device_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("planned_peak_bytes", ctypes.c_int64)]
+                ("planned_peak_bytes", ctypes.c_int64),
+                ("mean_wait_us", ctypes.c_double), ("mean_run_us", ctypes.c_double),
+                ("waited_upload", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

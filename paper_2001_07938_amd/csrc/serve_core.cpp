@@ -104,6 +104,7 @@ Stats Core::stats()
     o.evictions = n_evict_;
     o.ticks = n_ticks_;
     o.planned_peak = peak_pub_;
+    o.waited_upload = n_waited_upload_;
     if (!lat_us_.empty()) {
         std::vector<double> v = lat_us_;
         auto pct = [&](double p) {
@@ -120,6 +121,8 @@ Stats Core::stats()
         }
         o.mean_us = s / (double)lat_us_.size();
         o.max_us = mx;
+        o.mean_wait_us = wait_sum_us_ / (double)lat_us_.size();
+        o.mean_run_us = run_sum_us_ / (double)lat_us_.size();
     }
     const double wall = (double)(t_last_ - t_first_) * 1e-9;
     o.wall_s = wall;
@@ -135,6 +138,8 @@ void Core::reset_stats()
 {
     std::lock_guard<std::mutex> lk(mu_);
     lat_us_.clear();
+    wait_sum_us_ = run_sum_us_ = 0.0;
+    n_waited_upload_ = 0;
     n_spmv_ = n_cg_ = n_failed_ = n_uploads_ = n_evict_ = n_ticks_ = 0;
     bytes_done_ = 0.0;
     t_first_ = t_last_ = 0;
@@ -181,9 +186,16 @@ void Core::take_incoming()
         std::lock_guard<std::mutex> lk(mu_);
         in.swap(incoming_);
     }
+    int64_t cold = 0;
     for (Request *r : in) {
-        mats_[(size_t)r->mid].queued += 1;
+        Mat &m = mats_[(size_t)r->mid];
+        cold += m.st != READY;
+        m.queued += 1;
         waiting_.push_back(r);
+    }
+    if (cold) {
+        std::lock_guard<std::mutex> lk(mu_);
+        n_waited_upload_ += cold;
     }
 }
 
@@ -383,6 +395,8 @@ void Core::finish(Request *r, int64_t t)
         } else {
             status_[r->ticket] = 1;
             lat_us_.push_back((double)(t - r->t_arr) * 1e-3);
+            wait_sum_us_ += (double)(r->t_adm - r->t_arr) * 1e-3;
+            run_sum_us_ += (double)(t - r->t_adm) * 1e-3;
             if (r->kind == kCg) {
                 n_cg_ += 1;
                 bytes_done_ += (double)r->iters * (double)m.cg_iter_bytes;
@@ -500,6 +514,7 @@ bool Core::step()
             m.refs += 1;
             m.prev_use = m.last_use;
             m.last_use = ++use_clock_;
+            r->t_adm = ex_.now_ns();
             ex_.run_one(r);
             finish(r, ex_.now_ns());
             return true;  // one request per round
@@ -512,6 +527,7 @@ bool Core::step()
         m.queued -= 1;
         m.prev_use = m.last_use;
         m.last_use = ++use_clock_;
+        r->t_adm = ex_.now_ns();
         active_[ex_.lane_of(r->mid)].push_back(r);
         it = waiting_.erase(it);
         worked = true;

@@ -48,6 +48,7 @@ struct Request {
     const void *in = nullptr;   // device x (SpMV) or b (CG); null: the server's own
     void *out = nullptr;        // device y (SpMV) or x (CG); null: the slot's own
     int64_t t_arr = 0;          // arrival, executor clock (ns)
+    int64_t t_adm = 0;          // admission (set by the core)
     int iter = 0;               // CG iterations launched so far
     int slot = -1;
     bool failed = false;
@@ -67,6 +68,9 @@ struct Stats {
     double wall_s = 0, req_per_s = 0, solves_per_s = 0, gbytes_per_s = 0;
     int64_t uploads = 0, evictions = 0, ticks = 0;
     int64_t planned_peak = 0;  // highest planned device bytes (charges + reserves)
+    double mean_wait_us = 0;   // arrival -> admission (upload, slot, queue)
+    double mean_run_us = 0;    // admission -> completion
+    int64_t waited_upload = 0; // requests that found their matrix not resident
 };
 
 class Executor {
@@ -212,6 +216,8 @@ class Core {
     std::unordered_map<uint64_t, int> status_;
     uint64_t next_ticket_ = 1;
     std::vector<double> lat_us_;
+    double wait_sum_us_ = 0.0, run_sum_us_ = 0.0;
+    int64_t n_waited_upload_ = 0;
     int64_t n_spmv_ = 0, n_cg_ = 0, n_failed_ = 0, n_uploads_ = 0, n_evict_ = 0,
             n_ticks_ = 0;
     double bytes_done_ = 0.0;

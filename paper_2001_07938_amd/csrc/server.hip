@@ -577,6 +577,9 @@ void fill_stats(Server *S, lilac_server_stats *o)
     o->evictions = st.evictions;
     o->ticks = st.ticks;
     o->planned_peak_bytes = st.planned_peak;
+    o->mean_wait_us = st.mean_wait_us;
+    o->mean_run_us = st.mean_run_us;
+    o->waited_upload = st.waited_upload;
     std::lock_guard<std::recursive_mutex> lk(lib_mutex());
     o->peak_device_bytes = S->acct.peak;
     o->device_bytes = S->acct.in_use;
