@@ -367,11 +367,15 @@ def run_batched(args, torch, L, gen):
 
 
 def run_serve(args, torch, L, gen):
-    """Poisson request stream over a pool of 64 resident float64 matrices
-    (4 of the CG type, 60 of the batched type) plus 16 more that have to be
-    uploaded on demand; 80% SpMV / 20% 50-iteration CG (CG only on the SPD
-    matrices); lambda swept; the same trace also run through the plain
-    one-request-at-a-time path at the lower rates."""
+    """Poisson request stream over 80 float64 matrices: 64 pool matrices (4
+    of the CG type, 60 of the batched type) that take 90% of the requests,
+    and 16 more named by the other 10%, first uploaded on demand; 80% SpMV /
+    20% 50-iteration CG (CG only on the SPD matrices); lambda swept.  The
+    main points use the server's default limits (the HBM budget alone bounds
+    the resident set, which then holds all 80); the `pool64` points cap it
+    at 64 matrices, so every request for a non-resident matrix costs an
+    upload and an eviction.  The same traces also run through the plain
+    one-request-at-a-time path."""
     import gen as G
     specs = [G.SpdSpec(seed=gen.BASE_SEED + 50 + i) for i in range(4)]
     bspecs = gen.batch_specs(76, seed=gen.BASE_SEED + 60)
@@ -388,20 +392,22 @@ def run_serve(args, torch, L, gen):
         kind = np.where(spd[m], tr.kind, 0)
         return tr.arrival_ns, kind, m
 
-    out = {"workload": "serve_pool64", "cg_iters": 50, "points": []}
-    for fifo in (False, True):
-        S = L.Server(fifo=fifo)
+    out = {"workload": "serve80", "cg_iters": 50, "points": []}
+    runs = [(False, 0, args.serve_lambdas), (True, 0, args.fifo_lambdas),
+            (False, 64, [1000]), (True, 64, [1000])]
+    for fifo, cap, lams in runs:
+        S = L.Server(fifo=fifo, pool_capacity=cap)
         for A in pool:
             S.add_matrix(A)
         # warm-up: touch every pool matrix once
         a, k, m = trace(2000.0, 200, 1)
         S.run_trace(a, np.zeros_like(k), np.arange(200) % n_pool, 50)
-        lams = args.serve_lambdas if not fifo else args.fifo_lambdas
         for lam in lams:
             n_req = int(min(max(lam * 1.0, 500), 6000))
             a, k, m = trace(float(lam), n_req, 100 + lam)
             st = S.run_trace(a, k, m, 50)
             pt = {"lambda": lam, "mode": "fifo" if fifo else "batched",
+                  "pool": cap if cap else "budget",
                   "requests": st["completed"], "p50_ms": round(st["p50_us"] / 1e3, 3),
                   "p99_ms": round(st["p99_us"] / 1e3, 3),
                   "req_per_s": round(st["req_per_s"], 1),

@@ -449,7 +449,8 @@ typedef struct lilac_server_s *lilac_server_t;
 typedef struct {
     int64_t hbm_budget;  /* device bytes for matrices + request state; <= 0: 200 GiB */
     int max_active;      /* requests admitted at once (slots); <= 0: 256 */
-    int pool_capacity;   /* resident matrices before eviction; <= 0: 64 */
+    int pool_capacity;   /* resident matrices before eviction; <= 0: no count
+                            limit (2^20), the budget alone decides */
     int fifo;            /* 1: no batching, one request at a time with the
                             single-matrix calls (the plain path, for comparison) */
 } lilac_server_config;

@@ -272,6 +272,22 @@ struct Account {
 Account *&thread_account();
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+
+// Temporaries of a handle build (freed before the build returns).  A thread
+// that installs a TmpCache takes them from one grow-only buffer of at most
+// `limit` bytes, charged to `acct`, so that its builds call no hipFree
+// (which waits for every stream of the device); without one, or for a
+// larger or second temporary, they are ordinary allocations.
+struct TmpCache {
+    void *p = nullptr;
+    size_t cap = 0, limit = 0;
+    bool busy = false;
+    Account *acct = nullptr;
+};
+TmpCache *&thread_tmp_cache();
+void *tmp_alloc(size_t bytes);
+void tmp_free(void *p);
+void tmp_cache_release(TmpCache &t);   // frees the buffer
 int device_cu_count();
 
 // ---- kernel launchers (kernels.hip) --------------------------------------
@@ -478,8 +494,10 @@ CsrHandle *create_handle(int rows, int cols, int64_t nnz, const int32_t *rp,
 // padded_nnz(nnz) entries.  They belong to the handle from the call on
 // (freed with it, also when the call fails).  Blocking.
 int64_t padded_nnz(int64_t nnz);
+// The checks and the analysis run on stream s (null: the library's stream).
 CsrHandle *create_handle_adopt(int rows, int cols, int64_t nnz, int32_t *rp,
-                               int32_t *col, void *vals, lilac_dtype dt);
+                               int32_t *col, void *vals, lilac_dtype dt,
+                               hipStream_t s = nullptr);
 void destroy_handle(CsrHandle *h);
 MatDesc make_desc(const CsrHandle &h, const void *x, void *y, const void *w,
                   double *chunk_part);

@@ -204,16 +204,71 @@ void dev_free(void *p)
 {
     if (!p || !g_ctx)
         return;
-    std::lock_guard<std::recursive_mutex> lk(g_mu);
-    Context &c = *g_ctx;
-    auto it = c.sizes.find(p);
-    if (it != c.sizes.end()) {
-        c.in_use -= (int64_t)it->second.bytes;
-        for (Account *a = it->second.acct; a; a = a->parent)
-            a->in_use -= (int64_t)it->second.bytes;
-        c.sizes.erase(it);
+    {
+        std::lock_guard<std::recursive_mutex> lk(g_mu);
+        Context &c = *g_ctx;
+        auto it = c.sizes.find(p);
+        if (it != c.sizes.end()) {
+            c.in_use -= (int64_t)it->second.bytes;
+            for (Account *a = it->second.acct; a; a = a->parent)
+                a->in_use -= (int64_t)it->second.bytes;
+            c.sizes.erase(it);
+        }
     }
-    (void)hipFree(p);  // waits for outstanding work on the device
+    // waits for outstanding work on the device, so not under the lock:
+    // other threads keep allocating meanwhile
+    (void)hipFree(p);
+}
+
+TmpCache *&thread_tmp_cache()
+{
+    static thread_local TmpCache *t = nullptr;
+    return t;
+}
+
+void *tmp_alloc(size_t bytes)
+{
+    TmpCache *t = thread_tmp_cache();
+    bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    if (!t || t->busy || bytes > t->limit)
+        return dev_alloc(bytes);
+    if (t->cap < bytes) {
+        // grow to the next MiB (at most the limit); the old buffer is idle
+        const size_t want = std::min(t->limit, (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1));
+        Account *saved = thread_account();
+        thread_account() = t->acct;
+        try {
+            dev_free(t->p);
+            t->p = nullptr;
+            t->cap = 0;
+            t->p = dev_alloc(want);
+            t->cap = want;
+        } catch (...) {
+            thread_account() = saved;
+            throw;
+        }
+        thread_account() = saved;
+    }
+    t->busy = true;
+    return t->p;
+}
+
+void tmp_free(void *p)
+{
+    TmpCache *t = thread_tmp_cache();
+    if (t && p && p == t->p && t->busy) {
+        t->busy = false;
+        return;
+    }
+    dev_free(p);
+}
+
+void tmp_cache_release(TmpCache &t)
+{
+    dev_free(t.p);
+    t.p = nullptr;
+    t.cap = 0;
+    t.busy = false;
 }
 
 template <typename T>
@@ -411,7 +466,7 @@ static double measure_line_ratio(const CsrHandle &h, hipStream_t s)
     if (h.rows == 0 || h.nnz == 0)
         return 0.0;
     const int32_t ngroups = (int32_t)std::min<int64_t>(256, ((int64_t)h.rows + 63) / 64);
-    int32_t *d = (int32_t *)dev_alloc((size_t)ngroups * 8);
+    int32_t *d = (int32_t *)tmp_alloc((size_t)ngroups * 8);
     std::vector<int32_t> out((size_t)ngroups * 2);
     try {
         launch_line_reuse(h.rows, h.d_row_ptr, h.d_col, ngroups,
@@ -419,10 +474,10 @@ static double measure_line_ratio(const CsrHandle &h, hipStream_t s)
         HIPC(hipMemcpyAsync(out.data(), d, out.size() * 4, hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
     } catch (...) {
-        dev_free(d);
+        tmp_free(d);
         throw;
     }
-    dev_free(d);
+    tmp_free(d);
     int64_t e = 0, l = 0;
     for (int32_t g = 0; g < ngroups; ++g) {
         e += out[2 * g];
@@ -448,7 +503,7 @@ static void build_panels(CsrHandle &h, hipStream_t s)
     pd.nblk = (int32_t)((h.rows + pd.rb - 1) / pd.rb);
     pd.rw = (pd.rb + kPanelWaves - 1) / kPanelWaves;
     const int64_t nptr = (int64_t)pd.nblk * pd.np * (pd.rb + 1);
-    int32_t *ptr = (int32_t *)dev_alloc((size_t)nptr * 4);
+    int32_t *ptr = (int32_t *)tmp_alloc((size_t)nptr * 4);
     try {
         launch_fill_i32(ptr, nptr, 0, s);
         launch_panel_count(pd, h.d_row_ptr, h.d_col, ptr, s);
@@ -467,10 +522,10 @@ static void build_panels(CsrHandle &h, hipStream_t s)
         launch_panel_wptr(pd, ptr, h.d_pw, s);
         HIPC(hipStreamSynchronize(s));
     } catch (...) {
-        dev_free(ptr);
+        tmp_free(ptr);
         throw;
     }
-    dev_free(ptr);
+    tmp_free(ptr);
     pd.vals = h.d_pv;
     pd.rc = h.d_prc;
     pd.wptr = h.d_pw;
@@ -563,7 +618,7 @@ static void build_hot(CsrHandle &h, hipStream_t s)
     hd.bsplit = bsplit;
     hd.gptr = h.d_hb + 3 * nb1 - 1;
     hd.gblk = hd.gptr + hd.grid + 1;
-    int32_t *hx = (int32_t *)dev_alloc((size_t)(h.rows + 1) * 4);
+    int32_t *hx = (int32_t *)tmp_alloc((size_t)(h.rows + 1) * 4);
     try {
         launch_fill_i32(hx + h.rows, 1, 0, s);
         launch_hot_count(hd, h.d_row_ptr, h.d_col, hx, s);
@@ -581,10 +636,10 @@ static void build_hot(CsrHandle &h, hipStream_t s)
                            h.d_hrc, h.d_hkey, s);
         HIPC(hipStreamSynchronize(s));
     } catch (...) {
-        dev_free(hx);
+        tmp_free(hx);
         throw;
     }
-    dev_free(hx);
+    tmp_free(hx);
     hd.vals = h.d_hv;
     hd.rc = h.d_hrc;
     hd.key = h.d_hkey;
@@ -604,7 +659,7 @@ static bool build_band(CsrHandle &h, hipStream_t s, bool automatic)
     if (h.rows == 0 || h.nnz == 0)
         return false;
     std::vector<int32_t> lo((size_t)h.rows), hi((size_t)h.rows), rp((size_t)h.rows + 1);
-    int32_t *d = (int32_t *)dev_alloc((size_t)h.rows * 8);
+    int32_t *d = (int32_t *)tmp_alloc((size_t)h.rows * 8);
     try {
         launch_row_span(h.rows, h.d_row_ptr, h.d_col, d, d + h.rows, s);
         HIPC(hipMemcpyAsync(lo.data(), d, (size_t)h.rows * 4, hipMemcpyDeviceToHost, s));
@@ -613,10 +668,10 @@ static bool build_band(CsrHandle &h, hipStream_t s, bool automatic)
         HIPC(hipMemcpyAsync(rp.data(), h.d_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
     } catch (...) {
-        dev_free(d);
+        tmp_free(d);
         throw;
     }
-    dev_free(d);
+    tmp_free(d);
     // about eight blocks per CU (they run eight at a time on one), between
     // 2048 entries (short chains for small matrices) and 32768
     const int64_t target = std::min<int64_t>(
@@ -709,7 +764,7 @@ static void analyse(CsrHandle &h, hipStream_t s)
             th.upper[k] = h.plan.upper[k];
         const int32_t nblk = (h.rows + kBlock - 1) / kBlock;
         const int64_t nh = (int64_t)NCLASS * nblk;
-        int32_t *hist = (int32_t *)dev_alloc(nh * sizeof(int32_t));
+        int32_t *hist = (int32_t *)tmp_alloc(nh * sizeof(int32_t));
         h.d_bin_rows = (int32_t *)dev_alloc((size_t)h.rows * sizeof(int32_t));
         try {
             launch_bin_count(h.rows, h.d_row_ptr, th, hist, nblk, s);
@@ -727,10 +782,10 @@ static void analyse(CsrHandle &h, hipStream_t s)
                 h.bin_off[k] = hh[(size_t)k * nblk];
             h.bin_off[NCLASS] = h.rows;
         } catch (...) {
-            dev_free(hist);
+            tmp_free(hist);
             throw;
         }
-        dev_free(hist);
+        tmp_free(hist);
 
         const int32_t split_begin = h.bin_off[C_SPLIT];
         h.nsplit = h.rows - split_begin;
@@ -919,7 +974,7 @@ CsrHandle *create_handle(int rows, int cols, int64_t nnz,
 }
 
 CsrHandle *create_handle_adopt(int rows, int cols, int64_t nnz, int32_t *rp,
-                               int32_t *col, void *vals, lilac_dtype dt)
+                               int32_t *col, void *vals, lilac_dtype dt, hipStream_t s)
 {
     auto *h = new CsrHandle();
     h->d_row_ptr = rp;
@@ -935,7 +990,7 @@ CsrHandle *create_handle_adopt(int rows, int cols, int64_t nnz, int32_t *rp,
             fail(LILAC_ERR_ARG, "bad adopted arrays");
         if (dt != LILAC_F64 && dt != LILAC_F32)
             fail(LILAC_ERR_ARG, "unknown dtype");
-        construct(*h, h->cols_given, rp, col, vals, ctx().stream);
+        construct(*h, h->cols_given, rp, col, vals, s ? s : ctx().stream);
     } catch (...) {
         destroy_handle(h);
         throw;

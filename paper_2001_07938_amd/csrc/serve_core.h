@@ -82,7 +82,9 @@ class Executor {
     virtual int64_t upload_reserve(int mid) = 0;
     // Starts the upload; its end is reported through Core::upload_done.
     virtual void start_upload(int mid) = 0;
-    // Frees the resident copy of `mid` (no request uses it).  Blocking.
+    // Gives up the resident copy of `mid` (no request uses it).  The memory
+    // may come back later, but before any upload or slot allocation after
+    // this call takes device memory.
     virtual void evict(int mid) = 0;
     // Total device bytes slot `slot` must hold to serve a request on `mid`.
     virtual int64_t slot_need(int slot, int mid) = 0;

@@ -48,6 +48,31 @@ int64_t now_ns()
 
 constexpr int kUploadThreads = 2;
 constexpr int64_t kHeavyNnz = 1 << 23;
+// Compute units kept for uploads: the upload streams run on these only and
+// the light lane's ticks on the others, so a matrix's checks and analysis
+// never queue behind a long tick (a tick's kernels can hold every CU for
+// hundreds of microseconds) and short requests never wait out an upload.
+// The heavy lane keeps every CU: its column-panel products launch one
+// workgroup per CU and would take a second round on fewer.
+constexpr int kUploadCus = 16;
+// Largest build temporary an upload thread keeps between uploads (its
+// builds then call no hipFree, which waits for every stream of the device).
+constexpr size_t kTmpCacheLimit = (size_t)16 << 20;
+
+// Streams on a subset of the compute units (mask bits [lo, hi)), or plain
+// streams when the device is too small to split.
+void create_masked_stream(hipStream_t *st, int lo, int hi)
+{
+    const int cus = device_cu_count();
+    if (cus < 4 * kUploadCus) {
+        HIPC(hipStreamCreateWithFlags(st, hipStreamNonBlocking));
+        return;
+    }
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+    for (int c = lo; c < hi && c < cus; ++c)
+        mask[(size_t)c / 32] |= 1u << (c % 32);
+    HIPC(hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()));
+}
 
 struct SMatrix {
     int rows = 0, cols = 0;
@@ -69,6 +94,13 @@ struct Slot {
     double *pq = nullptr, *rr = nullptr;  // kBlock and 2*kBlock partials
     int32_t *done = nullptr;
     double *chunk = nullptr;
+};
+
+// A resident copy given up by the scheduler, freed by an upload thread.
+struct Evicted {
+    int mid = -1;
+    CsrHandle *h = nullptr;
+    double *vin = nullptr;
 };
 
 // Tables of one tick, in pinned memory and on the device.  Sized once for
@@ -124,9 +156,15 @@ struct Server {
     std::thread sched;
     std::thread uploader[kUploadThreads];
     std::atomic<bool> stop{false};
+    // uploads and frees of evicted copies; an upload starts only when no
+    // free is queued or running, so that the memory a plan counted as
+    // released is back before anything new is allocated
     std::mutex up_mu;
     std::condition_variable up_cv;
     std::deque<int> up_q;
+    std::deque<Evicted> free_q;
+    int freeing = 0;
+    TmpCache tmp[kUploadThreads];
     std::atomic<bool> started{false};
     std::mutex start_mu;
 };
@@ -164,20 +202,67 @@ int64_t slot_bytes_for(const Server *S, int64_t chunks)
 
 // ------------------------------------------------------------- uploads
 
+// Frees an evicted copy (hipFree waits for the whole device, which is why
+// the scheduler does not do it itself).
+void free_evicted(Server *S, const Evicted &e)
+{
+    std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+    destroy_handle(e.h);
+    dev_free(e.vin);
+    if (S->mats[(size_t)e.mid].acct.in_use != 0)
+        fail(LILAC_ERR_DEVICE, "evicted matrix still holds device memory");
+}
+
+// Blocks until every queued eviction has given its memory back.
+void wait_frees(Server *S)
+{
+    std::unique_lock<std::mutex> lk(S->up_mu);
+    S->up_cv.wait(lk, [&] {
+        return (S->free_q.empty() && S->freeing == 0) || S->stop.load();
+    });
+}
+
 void upload_loop(Server *S, int t)
 {
     if (hipSetDevice(lib_device()) != hipSuccess)
         return;
     hipStream_t us = S->up_stream[t];
+    thread_tmp_cache() = &S->tmp[t];
     while (true) {
         int id = -1;
+        Evicted ev;
         {
             std::unique_lock<std::mutex> lk(S->up_mu);
-            S->up_cv.wait(lk, [&] { return !S->up_q.empty() || S->stop.load(); });
+            S->up_cv.wait(lk, [&] {
+                return !S->free_q.empty() || (!S->up_q.empty() && S->freeing == 0) ||
+                       S->stop.load();
+            });
             if (S->stop.load())
-                return;
-            id = S->up_q.front();
-            S->up_q.pop_front();
+                break;
+            if (!S->free_q.empty()) {
+                ev = S->free_q.front();
+                S->free_q.pop_front();
+                S->freeing += 1;
+            } else {
+                id = S->up_q.front();
+                S->up_q.pop_front();
+            }
+        }
+        if (id < 0) {
+            std::string why;
+            try {
+                free_evicted(S, ev);
+            } catch (const Error &e) {
+                why = e.msg;
+            }
+            {
+                std::lock_guard<std::mutex> lk(S->up_mu);
+                S->freeing -= 1;
+                S->up_cv.notify_all();
+            }
+            if (!why.empty())
+                S->core->die(why);
+            continue;
         }
         SMatrix &m = S->mats[(size_t)id];
         const int64_t npad = padded_nnz(m.nnz);
@@ -191,6 +276,7 @@ void upload_loop(Server *S, int t)
         try {
             {
                 std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+                m.acct.peak = m.acct.in_use;
                 d_rp = (int32_t *)dev_alloc((size_t)(m.rows + 1) * 4);
                 d_col = (int32_t *)dev_alloc((size_t)npad * 4);
                 d_vals = (double *)dev_alloc((size_t)npad * 8);
@@ -211,7 +297,7 @@ void upload_loop(Server *S, int t)
             double *v = d_vals;
             d_rp = d_col = nullptr;
             d_vals = nullptr;
-            h = create_handle_adopt(m.rows, m.cols, m.nnz, a, c, v, LILAC_F64);
+            h = create_handle_adopt(m.rows, m.cols, m.nnz, a, c, v, LILAC_F64, us);
             if (S->fifo && m.rows == m.cols && m.rows > 0)
                 handle_cg_prepare(*h);   // the plain path's CG state, counted here
             vin = (double *)dev_alloc((size_t)std::max(1, m.cols) * 8);
@@ -242,6 +328,8 @@ void upload_loop(Server *S, int t)
         }
         S->core->upload_done(id, ok, held, why);
     }
+    tmp_cache_release(S->tmp[t]);
+    thread_tmp_cache() = nullptr;
 }
 
 // ------------------------------------------------------------- executor
@@ -257,23 +345,27 @@ void HipExec::start_upload(int mid)
     {
         std::lock_guard<std::recursive_mutex> lk(lib_mutex());
         m.acct.limit = upload_bound(m, S->fifo);
-        m.acct.peak = m.acct.in_use;
     }
     std::lock_guard<std::mutex> lk(S->up_mu);
     S->up_q.push_back(mid);
     S->up_cv.notify_one();
 }
 
+// The copy goes to the upload threads to be freed; uploads and new slot
+// memory wait for that free (wait_frees), so the device never holds more
+// than the plan while the scheduler moves on at once.
 void HipExec::evict(int mid)
 {
     SMatrix &m = S->mats[(size_t)mid];
-    std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-    destroy_handle(m.h);
-    dev_free(m.vin);
+    Evicted e;
+    e.mid = mid;
+    e.h = m.h;
+    e.vin = m.vin;
     m.h = nullptr;
     m.vin = nullptr;
-    if (m.acct.in_use != 0)
-        fail(LILAC_ERR_DEVICE, "evicted matrix still holds device memory");
+    std::lock_guard<std::mutex> lk(S->up_mu);
+    S->free_q.push_back(e);
+    S->up_cv.notify_all();
 }
 
 int64_t HipExec::slot_need(int slot, int mid)
@@ -290,6 +382,10 @@ void HipExec::prepare_slot(int slot, int mid)
         S->slots.push_back(Slot());
     Slot &sl = S->slots[(size_t)slot];
     const int64_t n = std::max(1, S->max_rows);
+    const int64_t nc = S->mats[(size_t)mid].nchunks;
+    if (sl.r && sl.cap_chunks >= nc)
+        return;   // a slot that fits: nothing to allocate, no lock
+    wait_frees(S);
     std::lock_guard<std::recursive_mutex> lk(lib_mutex());
     if (!sl.r) {
         sl.r = (double *)dev_alloc((size_t)n * 8);
@@ -300,7 +396,6 @@ void HipExec::prepare_slot(int slot, int mid)
         sl.rr = (double *)dev_alloc(2 * kBlock * 8);
         sl.done = (int32_t *)dev_alloc(256);
     }
-    const int64_t nc = S->mats[(size_t)mid].nchunks;
     if (sl.cap_chunks < nc) {
         dev_free(sl.chunk);
         sl.chunk = nullptr;
@@ -314,6 +409,7 @@ void HipExec::release_slot(int slot)
 {
     if (slot >= (int)S->slots.size())
         return;
+    wait_frees(S);
     Slot &sl = S->slots[(size_t)slot];
     std::lock_guard<std::recursive_mutex> lk(lib_mutex());
     dev_free(sl.r);
@@ -515,21 +611,22 @@ void HipExec::run_one(serve::Request *r)
     Slot &sl = S->slots[(size_t)r->slot];
     const double *in = r->in ? (const double *)r->in : m.vin;
     double *out = r->out ? (double *)r->out : sl.x;
+    hipStream_t s = S->stream[lane_of(r->mid)];   // the CUs its lane would have
     if (r->kind == serve::kSpmv) {
-        spmv_enqueue(*m.h, in, out, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, S->stream[0]);
+        spmv_enqueue(*m.h, in, out, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, s);
     } else {
         // the CG state was made at upload, under the matrix's account
         thread_account() = &m.acct;
         try {
             std::lock_guard<std::recursive_mutex> lk(lib_mutex());
-            run_cg(*m.h, in, out, r->iters, LILAC_CG_GRAPH, S->stream[0], nullptr, nullptr);
+            run_cg(*m.h, in, out, r->iters, LILAC_CG_GRAPH, s, nullptr, nullptr);
         } catch (...) {
             thread_account() = &S->acct;
             throw;
         }
         thread_account() = &S->acct;
     }
-    HIPC(hipStreamSynchronize(S->stream[0]));
+    HIPC(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------------- threads
@@ -588,6 +685,13 @@ void fill_stats(Server *S, lilac_server_stats *o)
 void free_server(Server *S)
 {
     std::lock_guard<std::recursive_mutex> lk(lib_mutex());
+    for (const Evicted &e : S->free_q) {
+        destroy_handle(e.h);
+        dev_free(e.vin);
+    }
+    S->free_q.clear();
+    for (auto &t : S->tmp)
+        tmp_cache_release(t);
     for (auto &m : S->mats) {
         if (m.h)
             destroy_handle(m.h);
@@ -651,7 +755,12 @@ void start(Server *S)
             throw;
         }
         thread_account() = nullptr;
-        lim.overhead = S->acct.in_use;
+        // the upload threads' build caches, charged to the server as they grow
+        lim.overhead = S->acct.in_use + kUploadThreads * (int64_t)kTmpCacheLimit;
+        for (auto &t : S->tmp) {
+            t.limit = kTmpCacheLimit;
+            t.acct = &S->acct;
+        }
     }
     S->core = new serve::Core(S->exec, lim);
     for (auto &m : S->mats) {
@@ -702,15 +811,16 @@ int lilac_server_create(lilac_server_t *out, const lilac_server_config *cfg)
         S->cfg.hbm_budget = (cfg && cfg->hbm_budget > 0) ? cfg->hbm_budget
                                                          : (int64_t)200 << 30;
         S->cfg.max_active = (cfg && cfg->max_active > 0) ? cfg->max_active : 256;
-        S->cfg.pool_capacity = (cfg && cfg->pool_capacity > 0) ? cfg->pool_capacity : 64;
+        S->cfg.pool_capacity = (cfg && cfg->pool_capacity > 0) ? cfg->pool_capacity : 1 << 20;
         S->cfg.fifo = cfg ? cfg->fifo : 0;
         S->fifo = S->cfg.fifo != 0;
         S->acct.limit = S->cfg.hbm_budget;
         try {
-            for (auto &st : S->stream)
-                HIPC(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            const int cus = device_cu_count();
+            create_masked_stream(&S->stream[0], kUploadCus, cus);
+            HIPC(hipStreamCreateWithFlags(&S->stream[1], hipStreamNonBlocking));
             for (auto &us : S->up_stream)
-                HIPC(hipStreamCreateWithFlags(&us, hipStreamNonBlocking));
+                create_masked_stream(&us, 0, kUploadCus);
             for (auto &lane : S->ticks)
                 for (auto &t : lane)
                     HIPC(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));
