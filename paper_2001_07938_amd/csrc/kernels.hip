@@ -113,6 +113,13 @@ __device__ __forceinline__ void seg_step(double &val, int32_t key)
         val += t;
 }
 
+// acc += v on a double in LDS, no value returned (ds_add_f64: the wave
+// does not wait for it).
+__device__ __forceinline__ void lds_add_f64(double *acc, double v)
+{
+    (void)__hip_atomic_fetch_add(acc, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Segmented inclusive scan by key over the 64 lanes (keys ascending): row
 // shifts by 1, 2, 4, 8 inside each row of 16, then the last lane of row 0
 // (and of row 2) into rows 1 (and 3), then lane 31 into rows 2 and 3.
@@ -622,6 +629,16 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
             const bool full = base >= ks && base + 128 * kPanelChunks <= ke;
             int32_t k0[kPanelChunks], k1[kPanelChunks];
             double p0[kPanelChunks], incl[kPanelChunks];
+            // the x values of all entries first, every LDS read in flight at
+            // once.  Entries outside [ks, ke) are read too: each is some
+            // entry of the matrix, whose column in its panel is below pw, so
+            // the read stays inside the panel buffer; its product is dropped.
+            V xa[kPanelChunks], xb[kPanelChunks];
+#pragma unroll
+            for (int u = 0; u < kPanelChunks; ++u) {
+                xa[u] = xs[rc[u].x & 0xFFFFu];
+                xb[u] = xs[rc[u].y & 0xFFFFu];
+            }
 #pragma unroll
             for (int u = 0; u < kPanelChunks; ++u) {
                 const int32_t e = base + u * 128 + 2 * lane;
@@ -631,16 +648,16 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                 if (full) {
                     k0[u] = (int32_t)(rc[u].x >> 16);
                     k1[u] = (int32_t)(rc[u].y >> 16);
-                    p0[u] = (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu];
-                    p1 = (double)v[u].y * (double)xs[rc[u].y & 0xFFFFu];
+                    p0[u] = (double)v[u].x * (double)xa[u];
+                    p1 = (double)v[u].y * (double)xb[u];
                 } else {
                     k0[u] = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
                     k1[u] = (e + 1 < ks) ? -1
                             : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16)
                                            : kPanelMaxRb;
                     const bool ok0 = e >= ks && e < ke, ok1 = e + 1 >= ks && e + 1 < ke;
-                    p0[u] = ok0 ? (double)v[u].x * (double)xs[rc[u].x & 0xFFFFu] : 0.0;
-                    p1 = ok1 ? (double)v[u].y * (double)xs[rc[u].y & 0xFFFFu] : 0.0;
+                    p0[u] = ok0 ? (double)v[u].x * (double)xa[u] : 0.0;
+                    p1 = ok1 ? (double)v[u].y * (double)xb[u] : 0.0;
                 }
                 // this lane's part of the run of its last key (a run that
                 // starts inside a lane breaks the scan because keys ascend)
@@ -656,12 +673,16 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                 const double prev_incl = dpp_f64<0x138>(incl[u]);
                 const int32_t prev_k1 = dpp_i32z<0x138>(k1[u]);
                 const int32_t next_k0 = next_lane_key(k0[u]);
-                // a run of k0 that ends on this lane's first entry
+                // a run of k0 that ends on this lane's first entry.  A row's
+                // run ends on one lane of a chunk, and a row belongs to one
+                // wavefront, whose LDS operations complete in order: the
+                // additions (no-return LDS adds, nothing to wait for) reach
+                // each row in a fixed order.
                 if (k0[u] != k1[u] && k0[u] >= 0 && k0[u] < kPanelMaxRb)
-                    acc[k0[u]] += (prev_k1 == k0[u]) ? prev_incl + p0[u] : p0[u];
+                    lds_add_f64(&acc[k0[u]], (prev_k1 == k0[u]) ? prev_incl + p0[u] : p0[u]);
                 // the run of k1 ends on this lane
                 if (next_k0 != k1[u] && k1[u] >= 0 && k1[u] < kPanelMaxRb)
-                    acc[k1[u]] += incl[u];
+                    lds_add_f64(&acc[k1[u]], incl[u]);
             }
         }
         ks = nks;
@@ -1017,13 +1038,15 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
         const double prev_incl = dpp_f64<0x138>(incl);
         const int32_t prev_k1 = dpp_i32z<0x138>(k1);
         const int32_t next_k0 = next_lane_key(k0);
+        // no-return LDS adds: a row's runs end in this wavefront only (its
+        // first row goes to the carry slot), in program order
         if (k0 != k1 && k0 >= 0 && k0 < kKeyEnd) {
             double *t = (k0 == first) ? csum : acc + k0;
-            *t += (prev_k1 == k0) ? prev_incl + p0 : p0;
+            lds_add_f64(t, (prev_k1 == k0) ? prev_incl + p0 : p0);
         }
         if (next_k0 != k1 && k1 >= 0 && k1 < kKeyEnd) {
             double *t = (k1 == first) ? csum : acc + k1;
-            *t += incl;
+            lds_add_f64(t, incl);
         }
     }
 }
