@@ -332,6 +332,11 @@ int lilac_spmv_batched_tune(int count, const lilac_csr_t *hs, const void *const 
  * the longest row), as a NUL-terminated string into buf[cap].
  * LILAC_ERR_ARG if it does not fit. */
 int lilac_csr_tune_class(lilac_csr_t h, char *buf, int cap);
+/* Forgets every tuned plan held in memory (including those read from the
+ * LILAC_TUNE_CACHE file; the file itself is left as it is): handles created
+ * afterwards start from the default plan and the automatic layout choice;
+ * existing handles keep their plans.  Never fails. */
+int lilac_tune_clear(void);
 
 /* ---- measurement -------------------------------------------------------- */
 /*

@@ -89,6 +89,7 @@ _SIGS = {
     "lilac_csr64_destroy": ([_P], _I),
     "lilac_csr_tune": ([_P, _P], _I),
     "lilac_csr_tune_class": ([_P, ctypes.c_char_p, _I], _I),
+    "lilac_tune_clear": ([], _I),
     "lilac_hbm_stream": ([_P, _P, _I64, _I, _P], _I),
     "lilac_spmv_batched_tune": ([_I, _P, _P, _P, _P], _I),
     "lilac_bfs": ([_P, _I, _P, _P, _P], _I),
@@ -258,6 +259,12 @@ def lilac_spmv_batched(handles: Sequence["Csr"], xs, ys, stream=None):
     Y = (ctypes.c_void_p * n)(*[_ptr(y) for y in ys])
     _check(lib().lilac_spmv_batched(n, ctypes.cast(H, _P), ctypes.cast(X, _P),
                                     ctypes.cast(Y, _P), _stream(stream)))
+
+
+def lilac_tune_clear() -> None:
+    """Forgets the tuned plans held in memory; new handles start from the
+    default plan."""
+    _check(lib().lilac_tune_clear())
 
 
 def lilac_spmv_batched_tune(handles: Sequence["Csr"], xs, ys) -> float:

@@ -1051,6 +1051,191 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
     }
 }
 
+
+// The same for four entries per lane (float32 values: 16-byte loads).
+struct HotChunk4 {
+    typedef float quad_t __attribute__((ext_vector_type(4)));
+    typedef uint32_t uquad_t __attribute__((ext_vector_type(4)));
+    typedef uint16_t kquad_t __attribute__((ext_vector_type(4)));
+    quad_t v;
+    uquad_t rc;
+    kquad_t kk;
+};
+
+template <bool HOT, int NW = kPanelWaves>
+__device__ __forceinline__ void hot_first4(const float *__restrict__ pv,
+                                           const uint32_t *__restrict__ prc,
+                                           const uint16_t *__restrict__ pkey, int32_t s,
+                                           int32_t e, int wave, int lane, HotChunk4 &c)
+{
+    int32_t ks, ke;
+    hot_share<NW>(s, e, wave, ks, ke);
+    const int32_t kb = ks & ~3;
+    if (kb < ke) {
+        const int32_t en = kb + 4 * lane;
+        const int32_t ea = (en < ke) ? en : kb;
+        c.v = ld_stream((const HotChunk4::quad_t *)(pv + ea));
+        c.rc = ld_stream((const HotChunk4::uquad_t *)(prc + ea));
+        if (!HOT)
+            c.kk = ld_stream((const HotChunk4::kquad_t *)(pkey + ea));
+    }
+}
+
+// hot_part with four consecutive entries per lane and chunks of 256 from a
+// multiple of four: the runs that start and end inside a lane are added
+// directly, the lane's first run joins the previous lane's scan value, its
+// last run enters a segmented scan over the wavefront.  Each row still
+// gets one addition per chunk, from the lane where its run ends, so the
+// order of the additions is fixed by the matrix and the layout.
+template <bool HOT, int NW = kPanelWaves, bool XG = !HOT, bool PRE = false>
+__device__ __forceinline__ void hot_part4(const float *__restrict__ pv,
+                                          const uint32_t *__restrict__ prc,
+                                          const uint16_t *__restrict__ pkey,
+                                          int32_t s, int32_t e, const float *xsrc,
+                                          double *acc, int32_t *ckey, double *csum,
+                                          int wave, int lane,
+                                          const HotChunk4 *pre = nullptr)
+{
+    typedef HotChunk4::quad_t quad_t;
+    typedef HotChunk4::uquad_t uquad_t;
+    typedef HotChunk4::kquad_t kquad_t;
+    constexpr int32_t CH = 256;
+    int32_t ks, ke;
+    hot_share<NW>(s, e, wave, ks, ke);
+    const int32_t kb = ks & ~3;
+    quad_t v;
+    uquad_t rc;
+    kquad_t kk;
+    int32_t first = -1;
+    if (kb < ke) {
+        if (PRE) {
+            v = pre->v;
+            rc = pre->rc;
+            if (!HOT)
+                kk = pre->kk;
+        } else {
+            const int32_t en = kb + 4 * lane;
+            const int32_t ea = (en < ke) ? en : kb;
+            v = ld_stream((const quad_t *)(pv + ea));
+            rc = ld_stream((const uquad_t *)(prc + ea));
+            if (!HOT)
+                kk = ld_stream((const kquad_t *)(pkey + ea));
+        }
+        // the share's first entry is entry ks - kb of lane 0
+        const int32_t d = ks - kb;
+        const uint32_t w0 = d == 0 ? rc.x : d == 1 ? rc.y : d == 2 ? rc.z : rc.w;
+        const uint32_t q0 = d == 0 ? kk.x : d == 1 ? kk.y : d == 2 ? kk.z : kk.w;
+        first = __builtin_amdgcn_readfirstlane(HOT ? (int32_t)(w0 >> 16) : (int32_t)q0);
+    }
+    if (lane == 0) {
+        *ckey = first;
+        *csum = 0.0;
+    }
+    auto in_share = [&](int32_t base, int j) {
+        const int32_t en = base + 4 * lane + j;
+        return (base >= ks && base + CH <= ke) || (en >= ks && en < ke);
+    };
+    auto column = [&](uint32_t w, bool ok) {
+        return ok ? (HOT ? (w & 0xFFFFu) : w) : 0u;
+    };
+    auto request = [&](int32_t at, quad_t &rv, uquad_t &rr, kquad_t &rk) {
+        const int32_t nn = at + 4 * lane;
+        const int32_t ea = (nn < ke) ? nn : kb;
+        rv = ld_stream((const quad_t *)(pv + ea));
+        rr = ld_stream((const uquad_t *)(prc + ea));
+        if (!HOT)
+            rk = ld_stream((const kquad_t *)(pkey + ea));
+    };
+    auto add = [&](int32_t k, double t) {
+        lds_add_f64((k == first) ? csum : acc + k, t);
+    };
+    float g[4] = {0.f, 0.f, 0.f, 0.f};   // gathers of the current chunk
+    quad_t v2;                           // entries of the next chunk
+    uquad_t rc2;
+    kquad_t kk2;
+    if (XG && kb < ke) {
+        g[0] = gld(xsrc + column(rc.x, in_share(kb, 0)));
+        g[1] = gld(xsrc + column(rc.y, in_share(kb, 1)));
+        g[2] = gld(xsrc + column(rc.z, in_share(kb, 2)));
+        g[3] = gld(xsrc + column(rc.w, in_share(kb, 3)));
+        if (kb + CH < ke)
+            request(kb + CH, v2, rc2, kk2);
+    }
+    for (int32_t base = kb; base < ke; base += CH) {
+        const int32_t en = base + 4 * lane;
+        const bool full = base >= ks && base + CH <= ke;
+        const uint32_t wv[4] = {rc.x, rc.y, rc.z, rc.w};
+        const int32_t rw[4] = {HOT ? (int32_t)(rc.x >> 16) : (int32_t)kk.x,
+                               HOT ? (int32_t)(rc.y >> 16) : (int32_t)kk.y,
+                               HOT ? (int32_t)(rc.z >> 16) : (int32_t)kk.z,
+                               HOT ? (int32_t)(rc.w >> 16) : (int32_t)kk.w};
+        const float cv[4] = {v.x, v.y, v.z, v.w};
+        bool ok[4];
+        int32_t k[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            ok[t] = full || (en + t >= ks && en + t < ke);
+            k[t] = full ? rw[t] : (en + t < ks) ? -1 : ok[t] ? rw[t] : kKeyEnd;
+        }
+        float xv[4];
+        const int32_t nb = base + CH;
+        if (XG) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                xv[t] = g[t];
+            if (nb < ke) {
+                v = v2;
+                rc = rc2;
+                if (!HOT)
+                    kk = kk2;
+                g[0] = gld(xsrc + column(rc.x, in_share(nb, 0)));
+                g[1] = gld(xsrc + column(rc.y, in_share(nb, 1)));
+                g[2] = gld(xsrc + column(rc.z, in_share(nb, 2)));
+                g[3] = gld(xsrc + column(rc.w, in_share(nb, 3)));
+                if (nb + CH < ke)
+                    request(nb + CH, v2, rc2, kk2);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                xv[t] = xsrc[column(wv[t], ok[t])];
+            if (nb < ke)
+                request(nb, v, rc, kk);
+        }
+        double pr[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            pr[t] = ok[t] ? (double)cv[t] * (double)xv[t] : 0.0;
+        // runs inside the lane (keys ascend)
+        double run = pr[0], head = 0.0;
+        int32_t rk = k[0];
+        bool split = false;
+#pragma unroll
+        for (int t = 1; t < 4; ++t) {
+            if (k[t] == rk) {
+                run += pr[t];
+            } else {
+                if (!split) {
+                    head = run;
+                    split = true;
+                } else if (rk >= 0 && rk < kKeyEnd) {
+                    add(rk, run);   // a run wholly inside this lane
+                }
+                rk = k[t];
+                run = pr[t];
+            }
+        }
+        const double incl = seg_scan64(run, k[3]);
+        const double prev_incl = dpp_f64<0x138>(incl);
+        const int32_t prev_kl = dpp_i32z<0x138>(k[3]);
+        const int32_t next_kf = next_lane_key(k[0]);
+        if (split && k[0] >= 0 && k[0] < kKeyEnd)
+            add(k[0], (prev_kl == k[0]) ? prev_incl + head : head);
+        if (next_kf != k[3] && k[3] >= 0 && k[3] < kKeyEnd)
+            add(k[3], incl);
+    }
+}
+
 // Product over the hot-column layout.  Persistent: workgroup g copies the
 // hot columns of x into LDS once, then takes its own list of row blocks
 // (assigned on the host, balanced by work).
@@ -1059,7 +1244,8 @@ __device__ __forceinline__ void hot_part(const V *__restrict__ pv,
 // two parts add into separate row sums, so no wavefront waits for another
 // between them.  The carries are then summed in slot order by one lane per
 // row, and each row's result is its hot sum plus its cold sum: every sum is
-// formed in an order fixed by the matrix and the layout.
+// formed in an order fixed by the matrix and the layout.  float32 matrices
+// take four entries per lane (hot_part4), float64 two (hot_part).
 template <typename V, bool DOT>
 __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
     HotDesc hd, const V *__restrict__ x, V *__restrict__ y, Epi epi,
@@ -1089,14 +1275,23 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
     // the first chunk of the wavefront's first part of block bb is requested
     // before the barriers that end the previous block
     typedef const __attribute__((address_space(4))) int32_t *cptr;
+    constexpr bool Q = sizeof(V) == 4;   // float32: four entries per lane
     HotChunk<V> pre;
+    HotChunk4 pre4;
     auto prefetch = [&](int32_t bb) {
         const int32_t pe0 = ((cptr)hd.bent)[bb], pes = ((cptr)hd.bsplit)[bb];
         const int32_t pe1 = ((cptr)hd.bent)[bb + 1];
-        if (wave & 1)
-            hot_first<V, false>(pv, hd.rc, hd.key, pes, pe1, wave, lane, pre);
-        else
-            hot_first<V, true>(pv, hd.rc, hd.key, pe0, pes, wave, lane, pre);
+        if constexpr (Q) {
+            if (wave & 1)
+                hot_first4<false>((const float *)pv, hd.rc, hd.key, pes, pe1, wave, lane, pre4);
+            else
+                hot_first4<true>((const float *)pv, hd.rc, hd.key, pe0, pes, wave, lane, pre4);
+        } else {
+            if (wave & 1)
+                hot_first<V, false>(pv, hd.rc, hd.key, pes, pe1, wave, lane, pre);
+            else
+                hot_first<V, true>(pv, hd.rc, hd.key, pe0, pes, wave, lane, pre);
+        }
     };
     // this workgroup's blocks (a static assignment balanced by work)
     const int32_t i0 = ((cptr)hd.gptr)[blockIdx.x];
@@ -1110,19 +1305,39 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
         const int32_t e0 = ((cptr)hd.bent)[b], es = ((cptr)hd.bsplit)[b];
         const int32_t e1 = ((cptr)hd.bent)[b + 1];
         __syncthreads();  // hot columns staged, sums of the last block cleared
-        if (wave & 1) {
-            hot_part<V, false, kPanelWaves, true, true>(
-                pv, hd.rc, hd.key, es, e1, x, acc_c, ckey + kPanelWaves + wave,
-                csum + kPanelWaves + wave, wave, lane, &pre);
-            hot_part<V, true>(pv, hd.rc, hd.key, e0, es, xs, acc_h, ckey + wave,
-                              csum + wave, wave, lane);
+        if constexpr (Q) {
+            const float *fv = (const float *)pv;
+            const float *fx = (const float *)x;
+            const float *fs = (const float *)xs;
+            if (wave & 1) {
+                hot_part4<false, kPanelWaves, true, true>(
+                    fv, hd.rc, hd.key, es, e1, fx, acc_c, ckey + kPanelWaves + wave,
+                    csum + kPanelWaves + wave, wave, lane, &pre4);
+                hot_part4<true>(fv, hd.rc, hd.key, e0, es, fs, acc_h, ckey + wave,
+                                csum + wave, wave, lane);
+            } else {
+                hot_part4<true, kPanelWaves, false, true>(fv, hd.rc, hd.key, e0, es, fs,
+                                                          acc_h, ckey + wave, csum + wave,
+                                                          wave, lane, &pre4);
+                hot_part4<false>(fv, hd.rc, hd.key, es, e1, fx, acc_c,
+                                 ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
+                                 wave, lane);
+            }
         } else {
-            hot_part<V, true, kPanelWaves, false, true>(pv, hd.rc, hd.key, e0, es, xs,
-                                                        acc_h, ckey + wave, csum + wave,
-                                                        wave, lane, &pre);
-            hot_part<V, false>(pv, hd.rc, hd.key, es, e1, x, acc_c,
-                               ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
-                               wave, lane);
+            if (wave & 1) {
+                hot_part<V, false, kPanelWaves, true, true>(
+                    pv, hd.rc, hd.key, es, e1, x, acc_c, ckey + kPanelWaves + wave,
+                    csum + kPanelWaves + wave, wave, lane, &pre);
+                hot_part<V, true>(pv, hd.rc, hd.key, e0, es, xs, acc_h, ckey + wave,
+                                  csum + wave, wave, lane);
+            } else {
+                hot_part<V, true, kPanelWaves, false, true>(pv, hd.rc, hd.key, e0, es, xs,
+                                                            acc_h, ckey + wave, csum + wave,
+                                                            wave, lane, &pre);
+                hot_part<V, false>(pv, hd.rc, hd.key, es, e1, x, acc_c,
+                                   ckey + kPanelWaves + wave, csum + kPanelWaves + wave,
+                                   wave, lane);
+            }
         }
         if (i + 1 < i1)
             prefetch(((cptr)hd.gblk)[i + 1]);

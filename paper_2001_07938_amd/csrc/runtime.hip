@@ -2998,6 +2998,14 @@ int lilac_spmv_batched_tune(int count, const lilac_csr_t *hs, const void *const 
     });
 }
 
+int lilac_tune_clear(void)
+{
+    return guard([&] {
+        tune_cache_load();   // a later load must not bring the file's plans back
+        g_tune.clear();
+    });
+}
+
 int lilac_csr_tune_class(lilac_csr_t hh, char *buf, int cap)
 {
     return guard([&] {

@@ -76,13 +76,16 @@ def test_tuner_keeps_results_in_tolerance():
     A = gen.random_rows(50000, 5, 60, seed=3)
     x = gen.vector(A.cols, 4)
     h = L.Csr.from_gen(A)
-    us = h.tune()
-    assert us > 0
-    y = torch.empty(A.rows, dtype=torch.float64, device=DEV)
-    h.spmv(_dev(x), y)
-    torch.cuda.synchronize()
-    check_spmv(A, x, y.cpu().numpy(), TOL_F64)
-    h.destroy()
+    try:
+        us = h.tune()
+        assert us > 0
+        y = torch.empty(A.rows, dtype=torch.float64, device=DEV)
+        h.spmv(_dev(x), y)
+        torch.cuda.synchronize()
+        check_spmv(A, x, y.cpu().numpy(), TOL_F64)
+    finally:
+        h.destroy()
+        L.lilac_tune_clear()   # later tests expect the default plans
 
 
 def test_batched_with_panel_matrices_bitwise():
@@ -154,6 +157,18 @@ def test_batch_tuner_results_and_cache():
     """The batch autotuner changes layouts only; every matrix still equals
     its single call bitwise and the oracle within tolerance, and handles
     created afterwards start from the tuned plan of their class."""
+    try:
+        _batch_tuner_checks()
+    finally:
+        L.lilac_tune_clear()   # later tests expect the default plans
+    # after clearing, a fresh handle starts from the default plan again
+    A = gen.stencil(30, 27)
+    h = L.Csr.from_gen(A)
+    assert h.info().layout == L.LAYOUT_BAND
+    h.destroy()
+
+
+def _batch_tuner_checks():
     mats = _batch(60, 17, n_hi=60000)
     hs = [L.Csr.from_gen(A) for A in mats]
     xs_h = [gen.vector(max(A.cols, 1), 300 + i) for i, A in enumerate(mats)]

@@ -427,7 +427,22 @@ def test_hot_layout_parity(name):
     h.set_layout(L.LAYOUT_HOT)
     yd = torch.empty(B.rows, dtype=torch.float32, device=DEV)
     h.spmv(_dev(x32), yd)
-    check_spmv(B, x32, _host(yd), TOL_F32)
+    y32 = _host(yd)
+    check_spmv(B, x32, y32, TOL_F32)
+    h.spmv(_dev(x32), yd)
+    assert np.array_equal(_host(yd), y32)
+    h.destroy()
+    # float32 integer data: every partial sum is an integer below 2^24, so
+    # the product is exact whatever the order of the additions
+    B.vals = gen.int_vector(B.nnz, 74).astype(np.float32)
+    xi32 = gen.int_vector(B.cols, 75).astype(np.float32)
+    h = L.Csr.from_gen(B, cols=B.cols)
+    h.set_layout(L.LAYOUT_HOT)
+    h.spmv(_dev(xi32), yd)
+    want = oracle.spmv_csr(B.row_ptr, B.col_idx, B.vals.astype(np.float64),
+                           xi32.astype(np.float64))
+    assert np.max(np.abs(want)) < 2 ** 24
+    assert np.array_equal(_host(yd).astype(np.float64), want)
     h.destroy()
     A.vals = gen.int_vector(A.nnz, 72)
     xi = gen.int_vector(A.cols, 73)
