@@ -1871,7 +1871,8 @@ __global__ __launch_bounds__(kBlock) void k_cgb_init(const CgSeg *__restrict__ s
         const double bi = sg.b[i];
         sg.x[i] = 0.0;
         sg.r[i] = bi;
-        sg.p[i] = bi;
+        sg.p[i] = 0.0;
+        sg.s[i] = 0.0;
         acc = fma(bi, bi, acc);
     }
     const double t = block_sum<kWaves>(acc, lds);
@@ -1882,7 +1883,8 @@ __global__ __launch_bounds__(kBlock) void k_cgb_init(const CgSeg *__restrict__ s
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cgb_pq(const CgSeg *__restrict__ segs,
+// Partial sums of r.w after the product w = A r.
+__global__ __launch_bounds__(kBlock) void k_cgb_rw(const CgSeg *__restrict__ segs,
                                                    int32_t nseg)
 {
     __shared__ double lds[kWaves];
@@ -1891,45 +1893,17 @@ __global__ __launch_bounds__(kBlock) void k_cgb_pq(const CgSeg *__restrict__ seg
     double acc = 0.0;
     for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
          i += (int64_t)sg.nb * kBlock)
-        acc = fma(sg.p[i], sg.q[i], acc);
+        acc = fma(sg.r[i], sg.w[i], acc);
     const double t = block_sum<kWaves>(acc, lds);
     if (threadIdx.x == 0)
-        sg.pq_part[lb] = t;
+        sg.rw_part[lb] = t;
 }
 
-// alpha = rho/(p.q); x += alpha p; r -= alpha q; partial r.r for k+1.
-__global__ __launch_bounds__(kBlock) void k_cgb_update(const CgSeg *__restrict__ segs,
-                                                       int32_t nseg)
-{
-    __shared__ double lds[kWaves];
-    const CgSeg sg = segs[cg_seg_of(segs, nseg)];
-    if (*sg.done)
-        return;
-    const int32_t lb = blockIdx.x - sg.blk0;
-    const int par = sg.iter & 1;
-    const double rho = sum_small(sg.rr_part + par * sg.nb, sg.nb, lds);
-    const double pq = sum_small(sg.pq_part, sg.nb, lds);
-    if (rho == 0.0 || pq == 0.0) {
-        if (lb == 0 && threadIdx.x == 0)
-            *sg.done = 1;
-        return;
-    }
-    const double alpha = rho / pq;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
-         i += (int64_t)sg.nb * kBlock) {
-        sg.x[i] = fma(alpha, sg.p[i], sg.x[i]);
-        const double ri = fma(-alpha, sg.q[i], sg.r[i]);
-        sg.r[i] = ri;
-        acc = fma(ri, ri, acc);
-    }
-    const double t = block_sum<kWaves>(acc, lds);
-    if (threadIdx.x == 0)
-        sg.rr_part[(par ^ 1) * sg.nb + lb] = t;
-}
-
-// beta = rho'/rho; p = r + beta p.
-__global__ __launch_bounds__(kBlock) void k_cgb_xpay(const CgSeg *__restrict__ segs,
+// gamma = r.r, delta = r.w; beta = gamma / gamma_old (0 at k = 0),
+// p.Ap = delta - beta gamma / alpha_old, alpha = gamma / p.Ap; then
+// p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s and the
+// partial sums of the new r.r.
+__global__ __launch_bounds__(kBlock) void k_cgb_step(const CgSeg *__restrict__ segs,
                                                      int32_t nseg)
 {
     __shared__ double lds[kWaves];
@@ -1938,12 +1912,37 @@ __global__ __launch_bounds__(kBlock) void k_cgb_xpay(const CgSeg *__restrict__ s
         return;
     const int32_t lb = blockIdx.x - sg.blk0;
     const int par = sg.iter & 1;
-    const double rho = sum_small(sg.rr_part + par * sg.nb, sg.nb, lds);
-    const double rho_new = sum_small(sg.rr_part + (par ^ 1) * sg.nb, sg.nb, lds);
-    const double beta = rho_new / rho;
+    const double g = sum_small(sg.rr_part + par * sg.nb, sg.nb, lds);
+    const double d = sum_small(sg.rw_part, sg.nb, lds);
+    const double beta = (sg.iter > 0) ? g / sg.sc[par ^ 1] : 0.0;
+    const double pap = (sg.iter > 0) ? d - beta * g / sg.sc[2 + (par ^ 1)] : d;
+    if (g == 0.0 || pap == 0.0) {
+        if (lb == 0 && threadIdx.x == 0)
+            *sg.done = 1;
+        return;
+    }
+    const double alpha = g / pap;
+    double acc = 0.0;
     for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
-         i += (int64_t)sg.nb * kBlock)
-        sg.p[i] = fma(beta, sg.p[i], sg.r[i]);
+         i += (int64_t)sg.nb * kBlock) {
+        const double ri = sg.r[i];
+        const double pi = fma(beta, sg.p[i], ri);
+        const double si = fma(beta, sg.s[i], sg.w[i]);
+        sg.p[i] = pi;
+        sg.s[i] = si;
+        sg.x[i] = fma(alpha, pi, sg.x[i]);
+        const double rn = fma(-alpha, si, ri);
+        sg.r[i] = rn;
+        acc = fma(rn, rn, acc);
+    }
+    const double t = block_sum<kWaves>(acc, lds);
+    if (threadIdx.x == 0) {
+        sg.rr_part[(par ^ 1) * sg.nb + lb] = t;
+        if (lb == 0) {
+            sg.sc[par] = g;
+            sg.sc[2 + par] = alpha;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- analysis
@@ -2952,28 +2951,20 @@ void launch_cgb_init(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_
     check_launch("k_cgb_init");
 }
 
-void launch_cgb_pq(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
+void launch_cgb_rw(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
 {
     if (blocks <= 0)
         return;
-    hipLaunchKernelGGL(k_cgb_pq, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
-    check_launch("k_cgb_pq");
+    hipLaunchKernelGGL(k_cgb_rw, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
+    check_launch("k_cgb_rw");
 }
 
-void launch_cgb_update(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
+void launch_cgb_step(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
 {
     if (blocks <= 0)
         return;
-    hipLaunchKernelGGL(k_cgb_update, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
-    check_launch("k_cgb_update");
-}
-
-void launch_cgb_xpay(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s)
-{
-    if (blocks <= 0)
-        return;
-    hipLaunchKernelGGL(k_cgb_xpay, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
-    check_launch("k_cgb_xpay");
+    hipLaunchKernelGGL(k_cgb_step, dim3(blocks), dim3(kBlock), 0, s, segs, nseg);
+    check_launch("k_cgb_step");
 }
 
 void launch_dot_parts(int64_t n, const double *a, const double *b,

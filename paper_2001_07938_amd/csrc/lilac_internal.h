@@ -388,14 +388,18 @@ void launch_spmv_segments(lilac_dtype dt, const MatDesc *mats,
                           const int32_t *prefix, int32_t nseg, int32_t total,
                           int32_t grid, hipStream_t s);
 
-// Many CG solves advanced together, one iteration per call sequence
-// (init once, then pq -> update -> xpay after each product q = A p).
+// Many CG solves advanced together, one iteration per call sequence, in
+// the Chronopoulos-Gear arrangement of the single-matrix solve: init once
+// (x = 0, r = b, p = s = 0), then after each product w = A r the partial
+// sums of r.w (rw) and one step that forms beta, alpha and updates
+// p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s.
 struct CgSeg {
     const double *b;
-    double *x, *r, *p, *q;
-    double *pq_part;    // nb partial sums of p.q
+    double *x, *r, *p, *w, *s;
+    double *rw_part;    // nb partial sums of r.w
     double *rr_part;    // 2*nb partial sums of r.r (by iteration parity)
-    int32_t *done;      // set once the solve stopped (rho or p.q zero)
+    double *sc;         // gamma[2], alpha[2] (by iteration parity)
+    int32_t *done;      // set once the solve stopped (gamma or p.Ap zero)
     int64_t n;
     int32_t nb;         // workgroups of this solve (fixed by n)
     int32_t iter;       // iteration index k of this step
@@ -404,9 +408,8 @@ struct CgSeg {
 };
 int32_t cg_seg_blocks(int64_t n);
 void launch_cgb_init(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
-void launch_cgb_pq(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
-void launch_cgb_update(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
-void launch_cgb_xpay(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
+void launch_cgb_rw(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
+void launch_cgb_step(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);
 
 void launch_dot_parts(int64_t n, const double *a, const double *b,
                       double *part, int32_t nparts, hipStream_t s);

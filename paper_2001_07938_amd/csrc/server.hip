@@ -86,13 +86,14 @@ struct SMatrix {
     int64_t nchunks = 0;                    // of the resident handle
 };
 
-// Per-slot device workspace of an admitted request: CG vectors, its own
-// output vector for trace-mode requests, partials, chunk sums.
+// Per-slot device workspace of an admitted request: CG vectors (r, p,
+// w = A r, s), its own output vector for trace-mode requests, partials,
+// the solve's scalars, chunk sums.
 struct Slot {
     int64_t cap_chunks = 0;
-    double *r = nullptr, *p = nullptr, *q = nullptr, *x = nullptr;
-    double *pq = nullptr, *rr = nullptr;  // kBlock and 2*kBlock partials
-    int32_t *done = nullptr;
+    double *r = nullptr, *p = nullptr, *w = nullptr, *s = nullptr, *x = nullptr;
+    double *rw = nullptr, *rr = nullptr;  // kBlock (r.w) and 2*kBlock (r.r) partials
+    int32_t *done = nullptr;              // 256 bytes: done flag, then the scalars
     double *chunk = nullptr;
 };
 
@@ -195,7 +196,7 @@ int64_t upload_bound(const SMatrix &m, bool cg_state)
 int64_t slot_bytes_for(const Server *S, int64_t chunks)
 {
     const int64_t n = std::max(1, S->max_rows);
-    return 4 * (int64_t)round256((size_t)n * 8) + (int64_t)round256(kBlock * 8) +
+    return 5 * (int64_t)round256((size_t)n * 8) + (int64_t)round256(kBlock * 8) +
            (int64_t)round256(2 * kBlock * 8) + 256 +
            (chunks > 0 ? (int64_t)round256((size_t)chunks * 8) : 0);
 }
@@ -390,9 +391,10 @@ void HipExec::prepare_slot(int slot, int mid)
     if (!sl.r) {
         sl.r = (double *)dev_alloc((size_t)n * 8);
         sl.p = (double *)dev_alloc((size_t)n * 8);
-        sl.q = (double *)dev_alloc((size_t)n * 8);
+        sl.w = (double *)dev_alloc((size_t)n * 8);
+        sl.s = (double *)dev_alloc((size_t)n * 8);
         sl.x = (double *)dev_alloc((size_t)n * 8);
-        sl.pq = (double *)dev_alloc(kBlock * 8);
+        sl.rw = (double *)dev_alloc(kBlock * 8);
         sl.rr = (double *)dev_alloc(2 * kBlock * 8);
         sl.done = (int32_t *)dev_alloc(256);
     }
@@ -414,9 +416,10 @@ void HipExec::release_slot(int slot)
     std::lock_guard<std::recursive_mutex> lk(lib_mutex());
     dev_free(sl.r);
     dev_free(sl.p);
-    dev_free(sl.q);
+    dev_free(sl.w);
+    dev_free(sl.s);
     dev_free(sl.x);
-    dev_free(sl.pq);
+    dev_free(sl.rw);
     dev_free(sl.rr);
     dev_free(sl.done);
     dev_free(sl.chunk);
@@ -460,7 +463,7 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
             if (r->kind == serve::kSpmv)
                 descs.push_back(make_desc(*m.h, in, out, nullptr, sl.chunk));
             else
-                descs.push_back(make_desc(*m.h, sl.p, sl.q, nullptr, sl.chunk));
+                descs.push_back(make_desc(*m.h, sl.r, sl.w, nullptr, sl.chunk));
             prefix.push_back(prefix.back() + m.h->ntiles);
             if (m.h->nsplit > 0)
                 split.push_back(r);
@@ -471,9 +474,11 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
             sg.x = out;
             sg.r = sl.r;
             sg.p = sl.p;
-            sg.q = sl.q;
-            sg.pq_part = sl.pq;
+            sg.w = sl.w;
+            sg.s = sl.s;
+            sg.rw_part = sl.rw;
             sg.rr_part = sl.rr;
+            sg.sc = (double *)((char *)sl.done + 64);
             sg.done = sl.done;
             sg.n = m.rows;
             sg.nb = cg_seg_blocks(m.rows);
@@ -513,7 +518,7 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
         Slot &sl = S->slots[(size_t)r->slot];
         const PanelIO io = (r->kind == serve::kSpmv)
                                ? PanelIO{r->in ? r->in : m.vin, r->out ? r->out : sl.x}
-                               : PanelIO{sl.p, sl.q};
+                               : PanelIO{sl.r, sl.w};
         if (m.h->use_panels) {
             pdesc.push_back(m.h->pan);
             pio.push_back(io);
@@ -581,7 +586,7 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
             spmv_enqueue(*m.h, r->in ? r->in : m.vin, r->out ? r->out : sl.x,
                          Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, s);
         else
-            spmv_enqueue(*m.h, sl.p, sl.q, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, s);
+            spmv_enqueue(*m.h, sl.r, sl.w, Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, false, s);
     }
     // split rows: each request's chunk sums added up in chunk order, as the
     // single-matrix product does
@@ -591,15 +596,14 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
         const MatDesc d = (r->kind == serve::kSpmv)
                               ? make_desc(*m.h, r->in ? r->in : m.vin,
                                           r->out ? r->out : sl.x, nullptr, sl.chunk)
-                              : make_desc(*m.h, sl.p, sl.q, nullptr, sl.chunk);
+                              : make_desc(*m.h, sl.r, sl.w, nullptr, sl.chunk);
         launch_split_finalize(LILAC_F64, nullptr, m.h->nsplit, d, nullptr,
                               Epi{EPI_NONE, 0, 0.0, 0.0}, nullptr, s);
     }
     if (!step.empty()) {
         const CgSeg *d_step = (const CgSeg *)(tk.dev + o_step);
-        launch_cgb_pq(d_step, (int32_t)step.size(), step_blocks, s);
-        launch_cgb_update(d_step, (int32_t)step.size(), step_blocks, s);
-        launch_cgb_xpay(d_step, (int32_t)step.size(), step_blocks, s);
+        launch_cgb_rw(d_step, (int32_t)step.size(), step_blocks, s);
+        launch_cgb_step(d_step, (int32_t)step.size(), step_blocks, s);
     }
     HIPC(hipEventRecord(tk.ev, s));
 }
@@ -702,9 +706,10 @@ void free_server(Server *S)
     for (auto &sl : S->slots) {
         dev_free(sl.r);
         dev_free(sl.p);
-        dev_free(sl.q);
+        dev_free(sl.w);
+        dev_free(sl.s);
         dev_free(sl.x);
-        dev_free(sl.pq);
+        dev_free(sl.rw);
         dev_free(sl.rr);
         dev_free(sl.done);
         dev_free(sl.chunk);
