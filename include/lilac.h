@@ -246,7 +246,8 @@ int lilac_dot_dev(int64_t n, const void *a, const void *b, void *out, lilac_dtyp
  * `iters` iterations of
  *   q = A p; alpha = rho/(p.q); x += alpha p; r -= alpha q;
  *   rho' = r.r; beta = rho'/rho; p = r + beta p
- * stopping early (x kept) only if rho or p.q becomes exactly 0.  The
+ * stopping early (x kept) only if rho or p.q becomes exactly 0 (p.q as
+ * the recurrence below gives it).  The
  * iterations are computed in the arrangement of Chronopoulos and Gear
  * (1989), the same iterates in exact arithmetic: the product is w = A r and
  * s = A p is updated alongside p, so both inner products of an iteration
