@@ -60,7 +60,7 @@ constexpr int kUploadCus = 16;
 constexpr size_t kTmpCacheLimit = (size_t)16 << 20;
 
 // Streams on a subset of the compute units (mask bits [lo, hi)), or plain
-// streams when the device is too small to split.
+// streams when the device is too small to split or refuses the mask.
 void create_masked_stream(hipStream_t *st, int lo, int hi)
 {
     const int cus = device_cu_count();
@@ -71,7 +71,10 @@ void create_masked_stream(hipStream_t *st, int lo, int hi)
     std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
     for (int c = lo; c < hi && c < cus; ++c)
         mask[(size_t)c / 32] |= 1u << (c % 32);
-    HIPC(hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()));
+    if (hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();   // masks refused: a plain stream serves too
+        HIPC(hipStreamCreateWithFlags(st, hipStreamNonBlocking));
+    }
 }
 
 struct SMatrix {
