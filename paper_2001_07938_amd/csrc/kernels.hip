@@ -733,7 +733,15 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_panels_grouped(
     }
     const PanelDesc pd = descs[lo];
     const Epi epi{EPI_NONE, 0, 0.0, 0.0};
-    panel_block<V, false>(pd, g - prefix[lo], (const V *)io[lo].x, (V *)io[lo].y,
+    const PanelIO pio = io[lo];
+    if constexpr (sizeof(V) == 8) {
+        if (pio.dot) {
+            panel_block<V, true>(pd, g - prefix[lo], (const V *)pio.x, (V *)pio.y, epi,
+                                 (const V *)pio.x, pio.dot, smem);
+            return;
+        }
+    }
+    panel_block<V, false>(pd, g - prefix[lo], (const V *)pio.x, (V *)pio.y,
                           epi, nullptr, nullptr, smem);
 }
 
@@ -1471,7 +1479,15 @@ __global__ __launch_bounds__(kBandThreads) void k_spmv_band_grouped(
     }
     const BandDesc bd = descs[lo];
     const Epi epi{EPI_NONE, 0, 0.0, 0.0};
-    band_block<V, false>(bd, g - prefix[lo], (const V *)io[lo].x, (V *)io[lo].y, epi,
+    const PanelIO bio = io[lo];
+    if constexpr (sizeof(V) == 8) {
+        if (bio.dot) {
+            band_block<V, true>(bd, g - prefix[lo], (const V *)bio.x, (V *)bio.y, epi,
+                                (const V *)bio.x, bio.dot, smem);
+            return;
+        }
+    }
+    band_block<V, false>(bd, g - prefix[lo], (const V *)bio.x, (V *)bio.y, epi,
                          nullptr, nullptr, smem);
 }
 
@@ -1883,12 +1899,15 @@ __global__ __launch_bounds__(kBlock) void k_cgb_init(const CgSeg *__restrict__ s
     }
 }
 
-// Partial sums of r.w after the product w = A r.
+// Partial sums of r.w after the product w = A r (segments whose product
+// wrote them, nrw > 0, are skipped).
 __global__ __launch_bounds__(kBlock) void k_cgb_rw(const CgSeg *__restrict__ segs,
                                                    int32_t nseg)
 {
     __shared__ double lds[kWaves];
     const CgSeg sg = segs[cg_seg_of(segs, nseg)];
+    if (sg.nrw > 0)
+        return;   // the product wrote them
     const int32_t lb = blockIdx.x - sg.blk0;
     double acc = 0.0;
     for (int64_t i = (int64_t)lb * kBlock + threadIdx.x; i < sg.n;
@@ -1913,7 +1932,7 @@ __global__ __launch_bounds__(kBlock) void k_cgb_step(const CgSeg *__restrict__ s
     const int32_t lb = blockIdx.x - sg.blk0;
     const int par = sg.iter & 1;
     const double g = sum_small(sg.rr_part + par * sg.nb, sg.nb, lds);
-    const double d = sum_small(sg.rw_part, sg.nb, lds);
+    const double d = sum_small(sg.rw_part, sg.nrw > 0 ? sg.nrw : sg.nb, lds);
     const double beta = (sg.iter > 0) ? g / sg.sc[par ^ 1] : 0.0;
     const double pap = (sg.iter > 0) ? d - beta * g / sg.sc[2 + (par ^ 1)] : d;
     if (g == 0.0 || pap == 0.0) {

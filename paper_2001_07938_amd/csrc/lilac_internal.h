@@ -108,9 +108,13 @@ struct PanelDesc {
     int32_t pad;
 };
 // Vectors of one matrix in a grouped panel launch.
+// dot: when set (float64 only), the blocks also write the partial sums of
+// x_i * y_i over their rows (square matrices), one per row block, the
+// product's fused dot of the single-matrix launch.
 struct PanelIO {
     const void *x;
     void *y;
+    double *dot = nullptr;
 };
 constexpr int kPanelThreads = 1024;            // 16 wave64: one workgroup per CU
 constexpr int kPanelWaves = kPanelThreads / 64;
@@ -404,7 +408,7 @@ struct CgSeg {
     int32_t nb;         // workgroups of this solve (fixed by n)
     int32_t iter;       // iteration index k of this step
     int32_t blk0;       // first workgroup of this solve in the launch
-    int32_t pad;
+    int32_t nrw;        // r.w partials the product wrote (0: k_cgb_rw writes nb)
 };
 int32_t cg_seg_blocks(int64_t n);
 void launch_cgb_init(const CgSeg *segs, int32_t nseg, int32_t blocks, hipStream_t s);

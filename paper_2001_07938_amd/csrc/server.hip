@@ -445,6 +445,15 @@ void HipExec::wait_tick(int lane, int tick)
     HIPC(hipEventSynchronize(S->ticks[lane][tick].ev));
 }
 
+// Row blocks of a matrix whose grouped product can also write the r.w
+// partials of a CG iteration (column panels or band, at most kBlock blocks:
+// the step kernel sums them in one workgroup); 0 otherwise.
+int32_t fused_rw_parts(const CsrHandle &h)
+{
+    const int32_t nb = h.use_panels ? h.pan.nblk : h.use_band ? h.band.nblk : 0;
+    return (nb > 0 && nb <= kBlock) ? nb : 0;
+}
+
 // One batched tick over every active request of a lane.
 void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *> &reqs)
 {
@@ -486,7 +495,7 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
             sg.n = m.rows;
             sg.nb = cg_seg_blocks(m.rows);
             sg.iter = r->iter;
-            sg.pad = 0;
+            sg.nrw = own_layout(*m.h) ? fused_rw_parts(*m.h) : 0;
             if (r->iter == 0) {
                 sg.blk0 = init_blocks;
                 init_blocks += sg.nb;
@@ -521,7 +530,7 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
         Slot &sl = S->slots[(size_t)r->slot];
         const PanelIO io = (r->kind == serve::kSpmv)
                                ? PanelIO{r->in ? r->in : m.vin, r->out ? r->out : sl.x}
-                               : PanelIO{sl.r, sl.w};
+                               : PanelIO{sl.r, sl.w, fused_rw_parts(*m.h) ? sl.rw : nullptr};
         if (m.h->use_panels) {
             pdesc.push_back(m.h->pan);
             pio.push_back(io);
@@ -605,7 +614,11 @@ void HipExec::launch_tick(int lane, int tick, const std::vector<serve::Request *
     }
     if (!step.empty()) {
         const CgSeg *d_step = (const CgSeg *)(tk.dev + o_step);
-        launch_cgb_rw(d_step, (int32_t)step.size(), step_blocks, s);
+        bool rw = false;   // some product did not write its r.w partials
+        for (const CgSeg &sg : step)
+            rw = rw || sg.nrw == 0;
+        if (rw)
+            launch_cgb_rw(d_step, (int32_t)step.size(), step_blocks, s);
         launch_cgb_step(d_step, (int32_t)step.size(), step_blocks, s);
     }
     HIPC(hipEventRecord(tk.ev, s));

@@ -20,9 +20,11 @@ def _dev(a):
 
 def _workload():
     # layouts: column panels (spd 40000), band (spd 6000, stencils, random
-    # rows), row-class tiles (ragged with long rows)
+    # rows), row-class tiles (ragged with long rows, the small stencil).  CG
+    # requests run on every SPD one: the panel and band products write the
+    # r.w partials themselves, the tiles take the separate r.w pass
     spd = [gen.spd_random(6000, 30, seed=1), gen.stencil(16, 7), gen.stencil(10, 27),
-           gen.spd_random(40000, 60, seed=4)]
+           gen.spd_random(40000, 60, seed=4), gen.stencil(8, 7)]
     other = [gen.random_rows(9000, 5, 60, seed=2),
              gen.ragged(2500, 30000, seed=3, long_rows=2, long_len=20000)]
     return spd, other
@@ -63,6 +65,11 @@ def test_server_layouts_cover_all_grouped_paths():
     for h in hs:
         h.destroy()
     assert {L.LAYOUT_PANELS, L.LAYOUT_BAND, L.LAYOUT_ROWS} <= lays, lays
+    hs = [L.Csr.from_gen(A) for A in spd]
+    spd_lays = {h.info().layout for h in hs}
+    for h in hs:
+        h.destroy()
+    assert {L.LAYOUT_PANELS, L.LAYOUT_BAND, L.LAYOUT_ROWS} <= spd_lays, spd_lays
 
 
 def test_alone_equals_mix_and_oracle():
