@@ -442,10 +442,12 @@ int lilac_bfs(lilac_csr_t h, int source, int *level, int *nlevels, void *stream)
  * CG-solve requests as they arrive: a scheduler thread admits requests whose
  * matrix is resident while request slots and the HBM budget allow, and
  * advances all admitted requests together, one grouped product plus one CG
- * iteration per request per step, so requests that arrive while others run
- * join the next step.  Matrices not resident are uploaded by a second thread
- * (overlapping the steps); idle ones are evicted least recently used first
- * when the pool or the budget is full.  A request's result does not depend
+ * iteration per request per step (the Chronopoulos-Gear arrangement of
+ * lilac_cg), so requests that arrive while others run join the next step;
+ * matrices of 2^23 or more non-zeros step in a lane of their own.  Matrices
+ * not resident are uploaded by two upload threads (overlapping the steps);
+ * idle ones are evicted (LRU-2: the oldest second-to-last use first) when
+ * the pool or the budget is full.  A request's result does not depend
  * on what it was batched with.  This is the persistent-state, upload-once
  * marshaling of the paper (section "LiLAC-How", "Data Marshaling") applied
  * to a stream of independent calls.  Thread-safe.
