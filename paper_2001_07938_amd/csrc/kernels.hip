@@ -7,9 +7,11 @@
 // Every reduction here has a fixed shape (lane groups reduce with DPP moves
 // in a fixed pattern, segmented scans run over lanes in order, workgroups
 // combine their wavefronts in index order, split rows add their chunk sums
-// in chunk order, carries between wavefronts are added in slot order), so a
-// given matrix, layout and plan always give bitwise identical results,
-// whatever else runs on the GPU.
+// in chunk order, carries between wavefronts are added in slot order, and a
+// row sum held in LDS takes its additions from the one wavefront that owns
+// the row, whose LDS operations complete in program order), so a given
+// matrix, layout and plan always give bitwise identical results, whatever
+// else runs on the GPU.
 #include <algorithm>
 
 #include "lilac_internal.h"
