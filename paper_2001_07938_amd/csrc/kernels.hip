@@ -13,6 +13,7 @@
 // matrix, layout and plan always give bitwise identical results, whatever
 // else runs on the GPU.
 #include <algorithm>
+#include <type_traits>
 
 #include "lilac_internal.h"
 
@@ -584,6 +585,74 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
         }
     };
     int32_t ks = 0, ke = 0;
+    // One step: chunks of 128 entries at base, base + 128, ..., all in
+    // lockstep (independent scans interleave); the sums reach the rows chunk
+    // by chunk, in order.  FULL: every entry of the step lies in [ks, ke)
+    // (most steps), so the bound checks are compiled out; the two cases are
+    // separate code, with no merge of their values.
+    auto body = [&](auto fullc, const pair_t (&v)[kPanelChunks],
+                    const upair_t (&rc)[kPanelChunks], int32_t base) {
+        constexpr bool FULL = decltype(fullc)::value;
+        int32_t k0[kPanelChunks], k1[kPanelChunks];
+        double p0[kPanelChunks], incl[kPanelChunks];
+        // the x values of all entries first, every LDS read in flight at
+        // once.  Entries outside [ks, ke) are read too: each is some entry
+        // of the matrix, whose column in its panel is below pw, so the read
+        // stays inside the panel buffer; its product is dropped.
+        V xa[kPanelChunks], xb[kPanelChunks];
+#pragma unroll
+        for (int u = 0; u < kPanelChunks; ++u) {
+            xa[u] = xs[rc[u].x & 0xFFFFu];
+            xb[u] = xs[rc[u].y & 0xFFFFu];
+        }
+#pragma unroll
+        for (int u = 0; u < kPanelChunks; ++u) {
+            const int32_t e = base + u * 128 + 2 * lane;
+            // keys ascend along the wavefront: entries before ks belong to
+            // the previous wavefront (-1), entries past ke to nobody (max)
+            double p1;
+            if (FULL) {
+                k0[u] = (int32_t)(rc[u].x >> 16);
+                k1[u] = (int32_t)(rc[u].y >> 16);
+                p0[u] = (double)v[u].x * (double)xa[u];
+                p1 = (double)v[u].y * (double)xb[u];
+            } else {
+                k0[u] = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
+                k1[u] = (e + 1 < ks) ? -1
+                        : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16)
+                                       : kPanelMaxRb;
+                const bool ok0 = e >= ks && e < ke, ok1 = e + 1 >= ks && e + 1 < ke;
+                p0[u] = ok0 ? (double)v[u].x * (double)xa[u] : 0.0;
+                p1 = ok1 ? (double)v[u].y * (double)xb[u] : 0.0;
+            }
+            // this lane's part of the run of its last key (a run that
+            // starts inside a lane breaks the scan because keys ascend)
+            incl[u] = (k0[u] == k1[u]) ? p0[u] + p1 : p1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPanelChunks; ++u)
+            incl[u] = seg_scan64(incl[u], k1[u]);
+#pragma unroll
+        for (int u = 0; u < kPanelChunks; ++u) {
+            // the previous lane's scan value and key (wave_shr:1; lane 0
+            // reads 0 and key 0, which adds 0 if it matches)
+            const double prev_incl = dpp_f64<0x138>(incl[u]);
+            const int32_t prev_k1 = dpp_i32z<0x138>(k1[u]);
+            const int32_t next_k0 = next_lane_key(k0[u]);
+            // a run of k0 that ends on this lane's first entry.  A row's run
+            // ends on one lane of a chunk, and a row belongs to one
+            // wavefront, whose LDS operations complete in order: the
+            // additions (no-return LDS adds, nothing to wait for) reach each
+            // row in a fixed order.  Keys of a full step are all rows.
+            if (k0[u] != k1[u] && (FULL || (k0[u] >= 0 && k0[u] < kPanelMaxRb)))
+                lds_add_f64(&acc[k0[u]], (prev_k1 == k0[u]) ? prev_incl + p0[u] : p0[u]);
+            // the run of k1 ends on this lane
+            if (next_k0 != k1[u] && (FULL || (k1[u] >= 0 && k1[u] < kPanelMaxRb)))
+                lds_add_f64(&acc[k1[u]], incl[u]);
+        }
+    };
+    typedef std::integral_constant<bool, true> full_t;
+    typedef std::integral_constant<bool, false> edge_t;
     if (pd.np > 0)
         range(0, ks, ke);
     if ((ks & ~1) < ke)
@@ -625,67 +694,10 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                 request(base + 128 * kPanelChunks, kb, ke);
             else if (nkb < nke)
                 request(nkb, nkb, nke);
-            // all chunks in lockstep (independent scans interleave); the sums
-            // reach the rows chunk by chunk, in order.  Chunks wholly inside
-            // [ks, ke) (most of them) skip the bound checks.
-            const bool full = base >= ks && base + 128 * kPanelChunks <= ke;
-            int32_t k0[kPanelChunks], k1[kPanelChunks];
-            double p0[kPanelChunks], incl[kPanelChunks];
-            // the x values of all entries first, every LDS read in flight at
-            // once.  Entries outside [ks, ke) are read too: each is some
-            // entry of the matrix, whose column in its panel is below pw, so
-            // the read stays inside the panel buffer; its product is dropped.
-            V xa[kPanelChunks], xb[kPanelChunks];
-#pragma unroll
-            for (int u = 0; u < kPanelChunks; ++u) {
-                xa[u] = xs[rc[u].x & 0xFFFFu];
-                xb[u] = xs[rc[u].y & 0xFFFFu];
-            }
-#pragma unroll
-            for (int u = 0; u < kPanelChunks; ++u) {
-                const int32_t e = base + u * 128 + 2 * lane;
-                // keys ascend along the wavefront: entries before ks belong to
-                // the previous wavefront (-1), entries past ke to nobody (max)
-                double p1;
-                if (full) {
-                    k0[u] = (int32_t)(rc[u].x >> 16);
-                    k1[u] = (int32_t)(rc[u].y >> 16);
-                    p0[u] = (double)v[u].x * (double)xa[u];
-                    p1 = (double)v[u].y * (double)xb[u];
-                } else {
-                    k0[u] = (e < ks) ? -1 : (e < ke) ? (int32_t)(rc[u].x >> 16) : kPanelMaxRb;
-                    k1[u] = (e + 1 < ks) ? -1
-                            : (e + 1 < ke) ? (int32_t)(rc[u].y >> 16)
-                                           : kPanelMaxRb;
-                    const bool ok0 = e >= ks && e < ke, ok1 = e + 1 >= ks && e + 1 < ke;
-                    p0[u] = ok0 ? (double)v[u].x * (double)xa[u] : 0.0;
-                    p1 = ok1 ? (double)v[u].y * (double)xb[u] : 0.0;
-                }
-                // this lane's part of the run of its last key (a run that
-                // starts inside a lane breaks the scan because keys ascend)
-                incl[u] = (k0[u] == k1[u]) ? p0[u] + p1 : p1;
-            }
-#pragma unroll
-            for (int u = 0; u < kPanelChunks; ++u)
-                incl[u] = seg_scan64(incl[u], k1[u]);
-#pragma unroll
-            for (int u = 0; u < kPanelChunks; ++u) {
-                // the previous lane's scan value and key (wave_shr:1; lane 0 reads 0
-                // and key 0, which adds 0 if it matches)
-                const double prev_incl = dpp_f64<0x138>(incl[u]);
-                const int32_t prev_k1 = dpp_i32z<0x138>(k1[u]);
-                const int32_t next_k0 = next_lane_key(k0[u]);
-                // a run of k0 that ends on this lane's first entry.  A row's
-                // run ends on one lane of a chunk, and a row belongs to one
-                // wavefront, whose LDS operations complete in order: the
-                // additions (no-return LDS adds, nothing to wait for) reach
-                // each row in a fixed order.
-                if (k0[u] != k1[u] && k0[u] >= 0 && k0[u] < kPanelMaxRb)
-                    lds_add_f64(&acc[k0[u]], (prev_k1 == k0[u]) ? prev_incl + p0[u] : p0[u]);
-                // the run of k1 ends on this lane
-                if (next_k0 != k1[u] && k1[u] >= 0 && k1[u] < kPanelMaxRb)
-                    lds_add_f64(&acc[k1[u]], incl[u]);
-            }
+            if (base >= ks && base + 128 * kPanelChunks <= ke)
+                body(full_t(), v, rc, base);
+            else
+                body(edge_t(), v, rc, base);
         }
         ks = nks;
         ke = nke;
