@@ -100,7 +100,11 @@ __device__ __forceinline__ double dpp_f64m(double v, double old)
 // Shifts inside rows (all rows enabled) read 0 and key 0 where there is no
 // source lane: a false key match then adds 0.  Broadcasts into some rows
 // keep the lane's own key -1 / value 0 in the other rows.
-template <int CTRL, int ROWS>
+// MASKED: the addition runs under an execution mask (the empty asm keeps
+// the compiler from turning it into a select), one vector instruction
+// instead of an addition and two 32-bit selects; it pays in the
+// column-panel product, whose instruction stream bounds it.
+template <int CTRL, int ROWS, bool MASKED = false>
 __device__ __forceinline__ void seg_step(double &val, int32_t key)
 {
     double t;
@@ -112,8 +116,11 @@ __device__ __forceinline__ void seg_step(double &val, int32_t key)
         t = dpp_f64m<CTRL, ROWS>(val, 0.0);
         tk = dpp_i32<CTRL, ROWS>(key, -1);
     }
-    if (tk == key)
+    if (tk == key) {
         val += t;
+        if (MASKED)
+            __asm__ volatile("" : "+v"(val));
+    }
 }
 
 // acc += v on a double in LDS, no value returned (ds_add_f64: the wave
@@ -126,14 +133,15 @@ __device__ __forceinline__ void lds_add_f64(double *acc, double v)
 // Segmented inclusive scan by key over the 64 lanes (keys ascending): row
 // shifts by 1, 2, 4, 8 inside each row of 16, then the last lane of row 0
 // (and of row 2) into rows 1 (and 3), then lane 31 into rows 2 and 3.
+template <bool MASKED = false>
 __device__ __forceinline__ double seg_scan64(double val, int32_t key)
 {
-    seg_step<0x111, 0xF>(val, key);  // row_shr:1
-    seg_step<0x112, 0xF>(val, key);  // row_shr:2
-    seg_step<0x114, 0xF>(val, key);  // row_shr:4
-    seg_step<0x118, 0xF>(val, key);  // row_shr:8
-    seg_step<0x142, 0xA>(val, key);  // row_bcast:15 into rows 1 and 3
-    seg_step<0x143, 0xC>(val, key);  // row_bcast:31 into rows 2 and 3
+    seg_step<0x111, 0xF, MASKED>(val, key);  // row_shr:1
+    seg_step<0x112, 0xF, MASKED>(val, key);  // row_shr:2
+    seg_step<0x114, 0xF, MASKED>(val, key);  // row_shr:4
+    seg_step<0x118, 0xF, MASKED>(val, key);  // row_shr:8
+    seg_step<0x142, 0xA, MASKED>(val, key);  // row_bcast:15 into rows 1 and 3
+    seg_step<0x143, 0xC, MASKED>(val, key);  // row_bcast:31 into rows 2 and 3
     return val;
 }
 
@@ -631,7 +639,7 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
         }
 #pragma unroll
         for (int u = 0; u < kPanelChunks; ++u)
-            incl[u] = seg_scan64(incl[u], k1[u]);
+            incl[u] = seg_scan64<true>(incl[u], k1[u]);
 #pragma unroll
         for (int u = 0; u < kPanelChunks; ++u) {
             // the previous lane's scan value and key (wave_shr:1; lane 0
