@@ -537,8 +537,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_segments(
 // entries, a segmented scan over the lanes (rows ascend along the chunk) adds
 // up each row's run, and the last lane of a run adds it to the row's sum in
 // LDS.  Rows belong to one wavefront, chunks follow in order, panels follow
-// in order: the additions are in a fixed order given by the matrix and the
-// layout.
+// in an order fixed for the block: the additions are in a fixed order given
+// by the matrix and the layout.
 template <typename V, bool DOT>
 __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
                                             const V *__restrict__ x,
@@ -661,16 +661,25 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
     };
     typedef std::integral_constant<bool, true> full_t;
     typedef std::integral_constant<bool, false> edge_t;
+    // A matrix with many row blocks takes its panels in a rotated order:
+    // the workgroups that share an XCD (b, b + 8, ...) start at different
+    // panels, so their copies of x from that XCD's L2 spread over the run
+    // instead of all coming at once.  The order depends only on the matrix
+    // and the block, so a block sums its rows the same way in every launch.
+    const int32_t rot =
+        (pd.np > 1 && pd.nblk >= kPanelRotateBlocks) ? (int32_t)((b >> 3) % pd.np) : 0;
+    auto panel_at = [&](int32_t i) { return (i + rot < pd.np) ? i + rot : i + rot - pd.np; };
     if (pd.np > 0)
-        range(0, ks, ke);
+        range(panel_at(0), ks, ke);
     if ((ks & ~1) < ke)
         request(ks & ~1, ks & ~1, ke);
-    for (int32_t p = 0; p < pd.np; ++p) {
+    for (int32_t i = 0; i < pd.np; ++i) {
+        const int32_t p = panel_at(i);
         const int32_t c0 = p * pd.pw;
         const int32_t width = min(pd.pw, pd.cols - c0);
         int32_t nks = 0, nke = 0;  // the next panel's range
-        if (p + 1 < pd.np)
-            range(p + 1, nks, nke);
+        if (i + 1 < pd.np)
+            range(panel_at(i + 1), nks, nke);
         __syncthreads();  // the previous panel is no longer read
         // 16-byte pieces straight from memory into LDS (no registers): each
         // wavefront instruction fills 1 KiB at a uniform LDS address

@@ -122,6 +122,7 @@ constexpr int kPanelMaxRb = 4096;              // rows per block (sums in LDS)
 constexpr int kPanelLds = 160 * 1024;          // LDS of one workgroup
 constexpr int kPanelChunks = 2;                // 128-entry chunks in flight
 constexpr int kPanelMaxPanels = 64;            // one lane per panel in the build
+constexpr int kPanelRotateBlocks = 128;        // blocks from which panel order rotates
 // LDS bytes of the row sums of a block of rb rows (the x panel follows)
 constexpr int panel_sum_bytes(int rb)
 {
