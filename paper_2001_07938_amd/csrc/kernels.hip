@@ -1405,9 +1405,14 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
         }
         __syncthreads();  // carries are in
         for (int32_t i = threadIdx.x; i < nr; i += kPanelThreads) {
-            const V out = epilogue<V>(acc_h[i] + acc_c[i], epi);
-            acc_h[i] = 0.0;  // the thread that reads a sum clears it
-            acc_c[i] = 0.0;
+            const uint16_t k = gld(hd.rmap + r0 + i);
+            double sum = 0.0;
+            if (k != kHotEmpty) {
+                sum = acc_h[k] + acc_c[k];
+                acc_h[k] = 0.0;  // the thread that reads a sum clears it
+                acc_c[k] = 0.0;
+            }
+            const V out = epilogue<V>(sum, epi);
             gst(y + r0 + i, out);
             if (DOT)
                 dacc = fma((double)gld(w + r0 + i), (double)out, dacc);
@@ -1616,7 +1621,7 @@ __global__ __launch_bounds__(kBlock) void k_hot_scatter(
             hi = mid - 1;
     }
     const int32_t b = lo;
-    const uint32_t rl = (uint32_t)(i - hd.brow[b]);
+    const uint32_t rl = hd.rmap[i];   // used only if the row has entries
     const int32_t before = hx[i] - hx[hd.brow[b]];   // hot entries of earlier rows
     int32_t hp = hd.bent[b] + before;
     int32_t cp = hd.bsplit[b] + (rp[i] - hd.bent[b]) - before;

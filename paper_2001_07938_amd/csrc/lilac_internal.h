@@ -137,16 +137,19 @@ constexpr int panel_width(int vsize, int rb)
 // Hot-column layout, for matrices whose most referenced columns come first
 // (a graph relabelled by decreasing out-degree).  Columns [0, hot) are
 // copied into LDS once per workgroup; the others are read from x in global
-// memory.  Rows are cut into blocks of at most kHotRows rows and about the
-// same number of entries; block b holds rows [brow[b], brow[b+1]) and the
-// entries [bent[b], bent[b+1]), its hot entries first (up to bsplit[b]),
-// then its cold ones, each part row by row.  A hot entry's word packs the
-// row inside the block and the column, (row << 16) | col; a cold entry's
-// word is its column and key[] holds its row inside the block.
+// memory.  Rows are cut into blocks of at most kHotRows non-empty rows and
+// about the same number of entries; block b holds rows [brow[b], brow[b+1])
+// and the entries [bent[b], bent[b+1]), its hot entries first (up to
+// bsplit[b]), then its cold ones, each part row by row.  A row's key is its
+// number among the non-empty rows of its block (rmap[row]; kHotEmpty for an
+// empty row), so empty rows take no row sum.  A hot entry's word packs the
+// key and the column, (key << 16) | col; a cold entry's word is its column
+// and key[] holds its key.
 struct HotDesc {
     const void *vals;
     const uint32_t *rc;
     const uint16_t *key;
+    const uint16_t *rmap;    // [rows]: key of the row, kHotEmpty if it has no entries
     const int32_t *brow;     // [nblk + 1]
     const int32_t *bent;     // [nblk + 1]
     const int32_t *bsplit;   // [nblk]
@@ -154,7 +157,9 @@ struct HotDesc {
     const int32_t *gblk;     // [nblk]
     int32_t rows, cols, nblk, hot, grid, pad;
 };
-constexpr int kHotRows = 2048;                        // rows per block
+constexpr int kHotRows = 1536;                        // non-empty rows per block
+constexpr uint16_t kHotEmpty = 0xFFFF;                // rmap of an empty row
+constexpr int kHotSpan = 16 * kHotRows;               // rows per block, empty ones too
 constexpr int kHotLdsHead = 2 * kHotRows * 8 + 1024;  // hot and cold row sums + carries
 // hot columns (elements) for a value size
 constexpr int hot_width(int vsize)
@@ -219,6 +224,7 @@ struct CsrHandle {
     void *d_hv = nullptr;
     uint32_t *d_hrc = nullptr;
     uint16_t *d_hkey = nullptr;
+    uint16_t *d_hrmap = nullptr;    // rows: key of each row in its block
     int32_t *d_hb = nullptr;        // brow | bent | bsplit
     // band layout (when use_band)
     bool use_band = false;

@@ -372,6 +372,7 @@ static void free_analysis(CsrHandle &h)
     dev_free_reset(h.d_hv);
     dev_free_reset(h.d_hrc);
     dev_free_reset(h.d_hkey);
+    dev_free_reset(h.d_hrmap);
     dev_free_reset(h.d_hb);
     dev_free_reset(h.d_brc);
     dev_free_reset(h.d_bb);
@@ -397,7 +398,7 @@ static int64_t analysis_bytes(const CsrHandle &h)
         b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 4) +
              (int64_t)h.pan.nblk * h.pan.np * (kPanelWaves + 1) * 4;
     if (h.use_hot)
-        b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 6) +
+        b += (h.nnz + kPad) * ((int64_t)dtype_size(h.dt) + 6) + (int64_t)h.rows * 2 +
              (int64_t)(4 * h.hot.nblk + h.hot.grid + 3) * 4;
     if (h.use_band)
         b += (h.nnz + kPad) * 4 + (int64_t)(3 * h.band.nblk + 2) * 4;
@@ -539,11 +540,13 @@ static bool hot_possible(const CsrHandle &h)
     return h.rows > 0 && h.nnz > 0 && h.cols > 0;
 }
 
-// Builds the hot-column copy of the matrix (see HotDesc).  Block bounds are
-// chosen on the host from row_ptr: a new block starts when the current one
-// has kHotRows rows or at least one workgroup's share of the entries (few,
+// Builds the hot-column copy of the matrix (see HotDesc).  Block bounds and
+// row keys are chosen on the host from row_ptr: a new block starts before a
+// non-empty row when the current one has kHotRows non-empty rows, or when it
+// has at least one workgroup's share of the entries or kHotSpan rows (few,
 // large blocks cost the fewest barriers; the assignment below balances
-// them).
+// them).  Empty rows take no key, so a block of a graph's sparse tail
+// (where most rows are empty) spans more rows than kHotRows.
 static void build_hot(CsrHandle &h, hipStream_t s)
 {
     Context &c = ctx();
@@ -557,12 +560,18 @@ static void build_hot(CsrHandle &h, hipStream_t s)
     HIPC(hipStreamSynchronize(s));
     const int64_t target = std::max<int64_t>(16384, h.nnz / (int64_t)c.cu);
     std::vector<int32_t> brow{0};
-    int32_t start = 0;
-    for (int32_t r = 1; r < h.rows; ++r)
-        if (r - start >= kHotRows || (int64_t)rp[r] - rp[start] >= target) {
+    std::vector<uint16_t> rmap((size_t)h.rows);
+    int32_t start = 0, keys = 0;
+    for (int32_t r = 0; r < h.rows; ++r) {
+        const bool filled = rp[r + 1] > rp[r];
+        if (r > start && ((filled && keys >= kHotRows) || r - start >= kHotSpan ||
+                          (int64_t)rp[r] - rp[start] >= target)) {
             brow.push_back(r);
             start = r;
+            keys = 0;
         }
+        rmap[r] = filled ? (uint16_t)keys++ : kHotEmpty;
+    }
     brow.push_back(h.rows);
     hd.nblk = (int32_t)brow.size() - 1;
     hd.grid = std::min<int32_t>(hd.nblk, c.cu);
@@ -612,6 +621,9 @@ static void build_hot(CsrHandle &h, hipStream_t s)
     }
     h.d_hb = (int32_t *)dev_alloc(hb.size() * 4);
     HIPC(hipMemcpyAsync(h.d_hb, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, s));
+    h.d_hrmap = (uint16_t *)dev_alloc(rmap.size() * 2);
+    HIPC(hipMemcpyAsync(h.d_hrmap, rmap.data(), rmap.size() * 2, hipMemcpyHostToDevice, s));
+    hd.rmap = h.d_hrmap;
     hd.brow = h.d_hb;
     hd.bent = h.d_hb + nb1;
     int32_t *bsplit = h.d_hb + 2 * nb1;

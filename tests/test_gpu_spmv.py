@@ -395,11 +395,14 @@ HOT_MATS = {
     "stencil27": lambda: gen.stencil(12, 27),
     "cols_2p22": lambda: gen.random_rows(5000, 1, 20, seed=10, cols=1 << 22),
     "cols_one": lambda: gen.random_rows(3000, 1, 1, seed=11, cols=1),
-    # 2^20 rows cut into blocks of at most 2048 rows: at least 512 blocks, so
-    # every workgroup of the persistent grid (one per CU) takes two or more
-    # blocks and runs the code that moves from one block to the next
+    # 2^20 rows cut into blocks of at most 1536 non-empty rows: 522 blocks,
+    # so the workgroups of the persistent grid (one per CU) take two or more
+    # on average and run the code that moves from one block to the next
     "rmat20_by_degree": lambda: gen.relabel_by_degree(
         gen.rmat_pagerank(20, 1 << 24, seed=14)).astype(np.float64),
+    # 97% empty rows: blocks end at 24576 rows (16 x 1536) long before they
+    # hold 1536 non-empty ones, and most rows of a block take no row sum
+    "mostly_empty_span": lambda: gen.ragged(80000, 80000, seed=15, empty_frac=0.97),
 }
 
 
