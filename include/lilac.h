@@ -191,10 +191,10 @@ int lilac_csr_set_plan(lilac_csr_t h, const int *upper /* [8] */,
  * column-panel matrices of a batch in one launch, with the same results.  LILAC_LAYOUT_HOT: a second copy for
  * matrices whose most referenced columns have the lowest indices (a graph
  * relabelled by decreasing out-degree, as lilac_pagerank does by itself for
- * graphs of at least 65536 vertices): the first 32512 (float32) or 16256
+ * graphs of at least 65536 vertices): the first 34560 (float32) or 17280
  * (float64) columns of x stay in LDS, the others are read from x in device
- * memory; rows are cut into blocks of at most 2048 rows and about equal
- * non-zeros.  Built only on request and only for matrices with non-zeros;
+ * memory; rows are cut into blocks of at most 1536 non-empty rows (24576
+ * rows in all) and about equal non-zeros, and empty rows take no row sum.  Built only on request and only for matrices with non-zeros;
  * otherwise the rows layout is used (lilac_csr_info reports which).  Every
  * layout gives deterministic results.  LILAC_LAYOUT_BAND: the CSR order and
  * values with one extra 32-bit word per non-zero packing the row inside a
