@@ -1200,9 +1200,11 @@ __device__ __forceinline__ void hot_part4(const float *__restrict__ pv,
         if (kb + CH < ke)
             request(kb + CH, v2, rc2, kk2);
     }
-    for (int32_t base = kb; base < ke; base += CH) {
+    // one chunk; FULL: every entry lies in [ks, ke) (most chunks), so the
+    // bound checks are compiled out (full and edge chunks are separate code)
+    auto body = [&](int32_t base, auto fullc) {
         const int32_t en = base + 4 * lane;
-        const bool full = base >= ks && base + CH <= ke;
+        constexpr bool full = decltype(fullc)::value;
         const uint32_t wv[4] = {rc.x, rc.y, rc.z, rc.w};
         const int32_t rw[4] = {HOT ? (int32_t)(rc.x >> 16) : (int32_t)kk.x,
                                HOT ? (int32_t)(rc.y >> 16) : (int32_t)kk.y,
@@ -1257,7 +1259,7 @@ __device__ __forceinline__ void hot_part4(const float *__restrict__ pv,
                 if (!split) {
                     head = run;
                     split = true;
-                } else if (rk >= 0 && rk < kKeyEnd) {
+                } else if (full || (rk >= 0 && rk < kKeyEnd)) {
                     add(rk, run);   // a run wholly inside this lane
                 }
                 rk = k[t];
@@ -1268,10 +1270,16 @@ __device__ __forceinline__ void hot_part4(const float *__restrict__ pv,
         const double prev_incl = dpp_f64<0x138>(incl);
         const int32_t prev_kl = dpp_i32z<0x138>(k[3]);
         const int32_t next_kf = next_lane_key(k[0]);
-        if (split && k[0] >= 0 && k[0] < kKeyEnd)
+        if (split && (full || (k[0] >= 0 && k[0] < kKeyEnd)))
             add(k[0], (prev_kl == k[0]) ? prev_incl + head : head);
-        if (next_kf != k[3] && k[3] >= 0 && k[3] < kKeyEnd)
+        if (next_kf != k[3] && (full || (k[3] >= 0 && k[3] < kKeyEnd)))
             add(k[3], incl);
+    };
+    for (int32_t base = kb; base < ke; base += CH) {
+        if (base >= ks && base + CH <= ke)
+            body(base, std::true_type());
+        else
+            body(base, std::false_type());
     }
 }
 
