@@ -950,10 +950,12 @@ __device__ __forceinline__ void hot_first(const V *__restrict__ pv,
 // The part is split evenly by entries, so a row can span wavefronts: the
 // run of the wavefront's first row goes to its carry slot (added after the
 // block, in slot order), every other run is added to the row sum in LDS by
-// the one wavefront where it ends.  HOT: the entry's word packs (row << 16)
+// the one wavefront where it ends.  A row is named by its key (its number
+// among the block's non-empty rows in the hot-column layout, its offset in
+// the block in the band layout).  HOT: the entry's word packs (key << 16)
 // | column offset and the gather reads xsrc[offset] (the LDS copy of the
 // hot columns, or x from a block's first column in the band layout);
-// otherwise the word is the column of x and the row comes from key[].  The
+// otherwise the word is the column of x and the key comes from key[].  The
 // entries of the next chunk are requested before the gathers of the
 // current one are used; with gathers from device memory the next chunk's
 // gathers are requested too.  NW wavefronts share the part; XG: xsrc is in
