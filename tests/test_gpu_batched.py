@@ -89,10 +89,19 @@ def test_tuner_keeps_results_in_tolerance():
 
 
 def test_batched_with_panel_matrices_bitwise():
+    """The column-panel matrix has two panels and, on a 256-CU device, 181
+    row blocks of 221 rows (enough rows to be worth a copy of x), so its
+    blocks take the panels in a rotated order, in the grouped launch as in
+    its own."""
     mats = [gen.spd_random(40000, 60, seed=21), gen.stencil(12, 7),
             gen.uniform_rows(4096, 16), gen.random_rows(8000, 5, 60, seed=22)]
     hs = [L.Csr.from_gen(A) for A in mats]
     assert hs[0].info().layout == L.LAYOUT_PANELS
+    assert hs[0].info().npanels >= 2
+    A0 = mats[0]
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    rb = max(-(-A0.rows // cu), int(np.ceil(A0.cols * 8 / (A0.nnz / A0.rows * 12))))
+    assert cu != 256 or -(-A0.rows // rb) >= 128
     assert hs[1].info().layout == L.LAYOUT_ROWS
     xs = [_dev(gen.vector(A.cols, 30 + i)) for i, A in enumerate(mats)]
     ys = [torch.empty(A.rows, dtype=torch.float64, device=DEV) for A in mats]
