@@ -2328,17 +2328,6 @@ __global__ __launch_bounds__(kBlock) void k_copy(int64_t n,
         dst[i] = src[i];
 }
 
-// Sum of part[0..n) by one 256-thread workgroup in a fixed order (the same
-// value in every workgroup that computes it).
-__device__ __forceinline__ double sum_parts_256(const double *__restrict__ part,
-                                                int32_t n, double *lds)
-{
-    double acc = 0.0;
-    for (int32_t i = threadIdx.x; i < n; i += kBlock)
-        acc += part[i];
-    return block_sum<kWaves>(acc, lds);
-}
-
 // Conjugate gradient in the arrangement of Chronopoulos and Gear (1989):
 // the same iterates as the textbook loop in exact arithmetic, with both
 // inner products of an iteration (r.r and r.Ar) available together, so an
