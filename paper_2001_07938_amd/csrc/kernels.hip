@@ -673,13 +673,13 @@ __device__ __forceinline__ void panel_block(const PanelDesc &pd, int32_t b,
         range(panel_at(0), ks, ke);
     if ((ks & ~1) < ke)
         request(ks & ~1, ks & ~1, ke);
-    for (int32_t i = 0; i < pd.np; ++i) {
-        const int32_t p = panel_at(i);
+    for (int32_t pk = 0; pk < pd.np; ++pk) {   // the block's pk-th panel
+        const int32_t p = panel_at(pk);
         const int32_t c0 = p * pd.pw;
         const int32_t width = min(pd.pw, pd.cols - c0);
         int32_t nks = 0, nke = 0;  // the next panel's range
-        if (i + 1 < pd.np)
-            range(panel_at(i + 1), nks, nke);
+        if (pk + 1 < pd.np)
+            range(panel_at(pk + 1), nks, nke);
         __syncthreads();  // the previous panel is no longer read
         // 16-byte pieces straight from memory into LDS (no registers): each
         // wavefront instruction fills 1 KiB at a uniform LDS address
@@ -1414,8 +1414,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
                 (cold ? acc_c : acc_h)[k] += t;
         }
         __syncthreads();  // carries are in
-        for (int32_t i = threadIdx.x; i < nr; i += kPanelThreads) {
-            const uint16_t k = gld(hd.rmap + r0 + i);
+        for (int32_t r = threadIdx.x; r < nr; r += kPanelThreads) {
+            const uint16_t k = gld(hd.rmap + r0 + r);
             double sum = 0.0;
             if (k != kHotEmpty) {
                 sum = acc_h[k] + acc_c[k];
@@ -1423,9 +1423,9 @@ __global__ __launch_bounds__(kPanelThreads) void k_spmv_hot(
                 acc_c[k] = 0.0;
             }
             const V out = epilogue<V>(sum, epi);
-            gst(y + r0 + i, out);
+            gst(y + r0 + r, out);
             if (DOT)
-                dacc = fma((double)gld(w + r0 + i), (double)out, dacc);
+                dacc = fma((double)gld(w + r0 + r), (double)out, dacc);
         }
     }
     if (DOT) {
@@ -2118,7 +2118,7 @@ __global__ __launch_bounds__(1024) void k_scan_excl(int32_t *__restrict__ a,
         s[threadIdx.x] = v;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
-            const int32_t t = (threadIdx.x >= off) ? s[threadIdx.x - off] : 0;
+            const int32_t t = ((int)threadIdx.x >= off) ? s[threadIdx.x - off] : 0;
             __syncthreads();
             s[threadIdx.x] += t;
             __syncthreads();
