@@ -370,6 +370,36 @@ def test_panel_layout_tall_row_blocks():
     h.destroy()
 
 
+def test_panel_layout_rotated_order_many_panels():
+    """Over 128 row blocks and 16 panels: each block takes the panels in a
+    rotated order (blocks of one XCD start at different panels, most of
+    them past the eighth), alone and in a grouped launch, with the same
+    result."""
+    A = gen.random_rows(110000, 200, 280, seed=23, cols=300000)
+    h = L.Csr.from_gen(A)
+    h.set_layout(L.LAYOUT_PANELS)
+    inf = h.info()
+    assert inf.layout == L.LAYOUT_PANELS and inf.npanels >= 16, inf.npanels
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    rb = max(-(-A.rows // cu), int(np.ceil(A.cols * 8 / (A.nnz / A.rows * 12))))
+    assert cu != 256 or -(-A.rows // rb) >= 128
+    x = gen.vector(A.cols, 72)
+    xd = _dev(x)
+    yd = torch.full((A.rows,), np.nan, dtype=torch.float64, device=DEV)
+    h.spmv(xd, yd)
+    y = _host(yd)
+    check_spmv(A, x, y, TOL_F64)
+    B = gen.spd_random(20000, 40, seed=24)
+    hb = L.Csr.from_gen(B)
+    xb = _dev(gen.vector(B.cols, 73))
+    ys = [torch.empty(A.rows, dtype=torch.float64, device=DEV),
+          torch.empty(B.rows, dtype=torch.float64, device=DEV)]
+    L.lilac_spmv_batched([h, hb], [xd, xb], ys)
+    assert np.array_equal(_host(ys[0]), y)
+    h.destroy()
+    hb.destroy()
+
+
 def test_panel_layout_unaligned_x():
     """x starting 8 bytes past a 16-byte boundary takes the scalar staging
     path of the panel kernel."""
